@@ -1,0 +1,175 @@
+"""CPU ORACLE - test infrastructure only.
+
+Plain sequential decoders (``oracle.c``, built with gcc -O2) plus a tiny
+pure-Python transcription (``spec.py``) for brute force on tiny inputs.  Only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the library never does, and the oracle
+imports nothing from the library.
+
+Status numbering (a convention of the decode interface, restated here):
+0 OK, 1 EINVAL, 2 EBADCODE, 3 EESCAPE, 4 ECAPACITY, 5 EOVERFLOW, 6 EBADDICT,
+7 EOFFSETS.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS = range(8)
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.oracle_fsst8_decode.restype = ctypes.c_int
+        L.oracle_fsst8_decode.argtypes = [P, I64, P, I64, P, P, I32, ctypes.c_int, P, P, I64, P, P]
+        L.oracle_onpair16_decode.restype = ctypes.c_int
+        L.oracle_onpair16_decode.argtypes = [P, I64, P, I64, P, P, I32, ctypes.c_int, P, P, I64, P, P, P]
+        L.oracle_onpair16_decode_copy16.restype = ctypes.c_int
+        L.oracle_onpair16_decode_copy16.argtypes = [P, P, I64, P, P, I32, P, P, P]
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Result:
+    status: int
+    out_off: np.ndarray     # int64, n_strings + 1 (valid when status in (OK, ECAPACITY, EOVERFLOW))
+    out_bytes: np.ndarray   # uint8, min(total, capacity) bytes
+    total: int
+    err_pos: int
+
+
+def _p(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def _as_i64(code_off) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(code_off), dtype=np.int64)
+
+
+def decode(codec: str, codes, code_off, dict_bytes, dict_lens, index_bits: int | None = None,
+           out_capacity: int | None = None) -> Result:
+    """Decode a whole column.  ``out_capacity=None`` sizes the output exactly
+    (an upper bound is used for the call and the result trimmed)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8 if codec == "fsst8" else np.uint16)
+    code_off_arr = np.asarray(code_off)
+    if index_bits is None:
+        index_bits = 32 if code_off_arr.dtype == np.int32 else 64
+    co = _as_i64(code_off_arr)
+    db = np.ascontiguousarray(dict_bytes, dtype=np.uint8)
+    dl = np.ascontiguousarray(dict_lens, dtype=np.uint8)
+    n_strings = len(co) - 1
+    maxlen = 8 if codec == "fsst8" else 16
+    cap = out_capacity if out_capacity is not None else len(codes) * maxlen
+    out_off = np.zeros(max(n_strings + 1, 1), np.int64)
+    # guard band after the capacity: the oracle must never write past it
+    out = np.full(cap + 64, 0xA5, np.uint8)
+    total = ctypes.c_int64(0)
+    err = ctypes.c_int64(-1)
+    L = lib()
+    if codec == "fsst8":
+        st = L.oracle_fsst8_decode(_p(codes), len(codes), _p(co), n_strings, _p(db), _p(dl), len(dl), index_bits,
+                                   _p(out_off), _p(out), cap, ctypes.byref(total), ctypes.byref(err))
+    elif codec == "onpair16":
+        scratch = np.zeros(max(len(dl), 1), np.int64)
+        st = L.oracle_onpair16_decode(_p(codes), len(codes), _p(co), n_strings, _p(db), _p(dl), len(dl),
+                                      index_bits, _p(out_off), _p(out), cap, ctypes.byref(total),
+                                      ctypes.byref(err), _p(scratch))
+    else:
+        raise ValueError(codec)
+    t = int(total.value)
+    if not np.all(out[cap:] == 0xA5):
+        raise AssertionError("oracle wrote past out_capacity")
+    return Result(int(st), out_off, out[: min(t, cap)], t, int(err.value))
+
+
+def decode_onpair16_copy16(codes, code_off, dict_bytes, dict_lens):
+    """The copy-16-and-advance formulation (valid input only)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    co = _as_i64(code_off)
+    db = np.ascontiguousarray(dict_bytes, dtype=np.uint8)
+    dl = np.ascontiguousarray(dict_lens, dtype=np.uint8)
+    n_strings = len(co) - 1
+    out_off = np.zeros(n_strings + 1, np.int64)
+    out = np.zeros(len(codes) * 16 + 16, np.uint8)
+    table = np.zeros(max(len(dl), 1) * 16, np.uint8)
+    st = lib().oracle_onpair16_decode_copy16(_p(codes), _p(co), n_strings, _p(db), _p(dl), len(dl), _p(table),
+                                            _p(out_off), _p(out))
+    return int(st), out_off, out[: int(out_off[-1])]
+
+
+def time_decode(codec: str, codes, code_off, dict_bytes, dict_lens, threads: int = 1, repeats: int = 1,
+                max_strings: int | None = None):
+    """Time the oracle on contiguous string-range shards decoded by `threads`
+    threads at once (each shard is an independent oracle call; the calls
+    release the GIL).  Returns (best_seconds, decoded_bytes, strings_used).
+    Only the decode calls are timed; outputs are preallocated."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8 if codec == "fsst8" else np.uint16)
+    co = _as_i64(code_off)
+    if max_strings is not None:
+        co = co[: max_strings + 1]
+    s = len(co) - 1
+    db = np.ascontiguousarray(dict_bytes, dtype=np.uint8)
+    dl = np.ascontiguousarray(dict_lens, dtype=np.uint8)
+    maxlen = 8 if codec == "fsst8" else 16
+    bounds = [s * k // threads for k in range(threads + 1)]
+    shards = []
+    for k in range(threads):
+        a, b = bounds[k], bounds[k + 1]
+        sub = np.ascontiguousarray(co[a:b + 1])
+        n_c = int(sub[-1] - sub[0]) if b > a else 0
+        shards.append((sub, np.zeros(b - a + 1, np.int64), np.zeros(max(n_c * maxlen, 1), np.uint8)))
+    L = lib()
+    results = [None] * threads
+
+    def run(k):
+        sub, oo, ob = shards[k]
+        total = ctypes.c_int64(0)
+        err = ctypes.c_int64(-1)
+        if codec == "fsst8":
+            st = L.oracle_fsst8_decode(_p(codes), len(codes), _p(sub), len(sub) - 1, _p(db), _p(dl), len(dl), 64,
+                                       _p(oo), _p(ob), len(ob), ctypes.byref(total), ctypes.byref(err))
+        else:
+            scratch = np.zeros(max(len(dl), 1), np.int64)
+            st = L.oracle_onpair16_decode(_p(codes), len(codes), _p(sub), len(sub) - 1, _p(db), _p(dl), len(dl),
+                                          64, _p(oo), _p(ob), len(ob), ctypes.byref(total), ctypes.byref(err),
+                                          _p(scratch))
+        results[k] = (st, int(total.value))
+
+    best = None
+    for _ in range(repeats):
+        ths = [threading.Thread(target=run, args=(k,)) for k in range(threads)]
+        t0 = time.perf_counter()
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    if any(r[0] != OK for r in results):
+        raise RuntimeError("oracle failed on a shard: %r" % (results,))
+    return best, sum(r[1] for r in results), s
