@@ -1,0 +1,202 @@
+/*
+ * fastdecode.h - C ABI of the MI355X (gfx950) string-column decoder.
+ *
+ * The library decodes string columns compressed with fixed-width-code
+ * dictionary codecs into Arrow-style string arrays (offsets + bytes):
+ *
+ *   - FSST-8:    uint8 codes, a table of at most 255 symbols of 1..8 bytes;
+ *                code 255 is the escape: the byte after it is copied as a
+ *                one-byte literal (the escape mechanism of the paper's
+ *                background section on dictionary-compressed strings);
+ *   - OnPair-16: uint16 codes, a dictionary of at most 65,536 tokens of
+ *                1..16 bytes, no escapes (same section; the paper's OnPair-16
+ *                codec).
+ *
+ * Decoding looks every code's token up and concatenates the tokens in code
+ * order (same section).  String i of a column is the code range
+ * codes[code_offsets[i] .. code_offsets[i+1]); the output is
+ * out_offsets[0] = 0, out_offsets[i+1] - out_offsets[i] = decoded length of
+ * string i, and the decoded bytes of all strings back to back in out_bytes
+ * (the variable-length string array of the evaluation section).
+ *
+ * Output positions are computed on the device by a prefix scan of decoded
+ * lengths (the paper stores them per batch of codes in a "sidecar"; the
+ * design section notes they can be regenerated at decode time).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named codes, code_offsets, dict_*, out_*, workspace and status
+ *     are DEVICE pointers owned by the caller (for example torch tensors).
+ *     The library never frees or retains them past the call's stream work.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  All device work
+ *     of a call is enqueued on that stream.
+ *   - index_bits selects the width of code_offsets AND out_offsets: 32
+ *     (int32) or 64 (int64).
+ *   - code_offsets must be non-decreasing with 0 <= code_offsets[0] and
+ *     code_offsets[n_strings] <= n_codes; code_offsets[0] may be nonzero
+ *     (a slice).  n_strings = 0 is valid (out_offsets[0] = 0 is written).
+ *   - Errors the host can see (null pointers, bad widths, a workspace that is
+ *     too small, sizes out of range) return at once and enqueue nothing.
+ *   - Errors in the data are found on the device: FD_EBADDICT, FD_EOFFSETS,
+ *     FD_EBADCODE, FD_EESCAPE, FD_EOVERFLOW, FD_ECAPACITY.  When several
+ *     apply, the one reported is the first of: EBADDICT, EOFFSETS, the data
+ *     error at the lowest code position, EOVERFLOW, ECAPACITY.
+ *     Without FD_ASYNC the call waits for the stream and returns the status.
+ *     With FD_ASYNC the call returns FD_OK once enqueued and the final status
+ *     is written to *status (a device int32) when the work completes.
+ *   - On any error the contents of out_bytes are unspecified.  On
+ *     FD_ECAPACITY out_offsets is complete (the caller may allocate
+ *     out_offsets[n_strings] bytes and decode again).
+ *   - The library never writes outside out_bytes[0, out_capacity) or
+ *     out_offsets[0, n_strings].
+ *   - Calls on different streams with different workspaces may run
+ *     concurrently.  Two calls that share a workspace must be ordered.
+ *   - No exception crosses this interface.
+ */
+#ifndef FASTDECODE_H
+#define FASTDECODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fd_status {
+    FD_OK = 0,
+    FD_EINVAL = 1,     /* bad argument (host-side check)                          */
+    FD_EBADCODE = 2,   /* a code >= the dictionary size                           */
+    FD_EESCAPE = 3,    /* FSST-8: escape is the last code of a string             */
+    FD_ECAPACITY = 4,  /* decoded total > out_capacity                            */
+    FD_EOVERFLOW = 5,  /* index_bits = 32 and decoded total > INT32_MAX           */
+    FD_EBADDICT = 6,   /* token length 0 or above the codec maximum               */
+    FD_EOFFSETS = 7,   /* code_offsets decreasing, negative or past n_codes       */
+    FD_EHIP = 8,       /* a HIP runtime call failed                               */
+    FD_ENOMEM = 9      /* allocation failed / request exceeds a memory budget     */
+} fd_status;
+
+typedef enum fd_codec { FD_FSST8 = 1, FD_ONPAIR16 = 2 } fd_codec;
+
+/* flags */
+#define FD_ASYNC 1u
+
+/* Human-readable name of a status. Never NULL. */
+const char *fd_status_str(int status);
+
+/* Library version string. */
+const char *fd_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Workspace                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace one decode of a column needs.  The workspace holds
+ * the per-tile scan state of the decoded-length prefix sum (the on-device
+ * replacement of the paper's per-batch sidecar, design section, design
+ * overview), counters, the device error word and, for onpair_decode, the
+ * prepared dictionary.  n_codes is the length of the code stream, n_strings
+ * the number of strings.  Returns FD_EINVAL for negative sizes. */
+fd_status fd_workspace_size(fd_codec codec, int64_t n_codes, int64_t n_strings, size_t *bytes);
+
+/* Upper bound of the decoded size: n_codes * (8 for FSST-8, 16 for OnPair-16). */
+fd_status fd_decoded_bound(fd_codec codec, int64_t n_codes, int64_t *bytes);
+
+/* ------------------------------------------------------------------------- */
+/* Single-column decode                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* FSST-8 decode of one column (codec semantics: background section on
+ * dictionary-compressed strings, the escape paragraph).
+ *   codes[n_codes]              uint8 code stream (any alignment)
+ *   code_offsets[n_strings+1]   int32 or int64 (index_bits)
+ *   dict_bytes                  packed symbol bytes, sum(dict_lens) bytes
+ *   dict_lens[n_symbols]        uint8 symbol lengths, each 1..8
+ *   n_symbols                   0..255 (codes n_symbols..254 are FD_EBADCODE)
+ *   out_offsets[n_strings+1]    written, index_bits wide
+ *   out_bytes[out_capacity]     written
+ *   workspace[workspace_bytes]  at least fd_workspace_size(FD_FSST8, ...)
+ *   status                      device int32, required with FD_ASYNC, may be
+ *                               NULL otherwise */
+fd_status fsst_decode(const uint8_t *codes, int64_t n_codes, const void *code_offsets, int index_bits,
+                      int64_t n_strings, const uint8_t *dict_bytes, const uint8_t *dict_lens, int32_t n_symbols,
+                      void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
+                      size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
+
+/* OnPair-16 decode of one column (same section; the paper's OnPair-16 codec).
+ * Arguments as fsst_decode with uint16 codes (2-byte aligned), dict_lens each
+ * 1..16 and n_tokens 0..65536.  The dictionary is repacked into fixed-stride
+ * entries inside the workspace on every call (the paper does this repack
+ * before timing, evaluation section); callers that decode many columns with one
+ * dictionary should create an fd_dict once and use fd_decode. */
+fd_status onpair_decode(const uint16_t *codes, int64_t n_codes, const void *code_offsets, int index_bits,
+                        int64_t n_strings, const uint8_t *dict_bytes, const uint8_t *dict_lens, int32_t n_tokens,
+                        void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
+                        size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Device-resident dictionaries                                               */
+/* ------------------------------------------------------------------------- */
+
+/* An immutable device-resident dictionary, prepared once: for OnPair-16 the
+ * tokens are repacked into fixed 16-byte entries so that a token's address
+ * follows from its code (the fixed-stride dictionary of the introduction and of
+ * the design section's decode stages) plus a 65,536-entry length table; for
+ * FSST-8 the packed symbols are copied.  dict_bytes / dict_lens are device
+ * pointers (read during the call only).  Validation runs on the device: the
+ * call waits for hip_stream and returns FD_EBADDICT for a length of 0 or above
+ * the codec maximum.  The handle owns library-allocated device memory on the
+ * current device; destroy it after its last use on any stream has completed. */
+typedef struct fd_dict fd_dict;
+
+fd_status fd_dict_create(fd_codec codec, const uint8_t *dict_bytes, const uint8_t *dict_lens, int32_t n_tokens,
+                         void *hip_stream, fd_dict **out);
+fd_status fd_dict_destroy(fd_dict *dict);
+fd_codec fd_dict_codec(const fd_dict *dict);
+int32_t fd_dict_size(const fd_dict *dict);
+
+/* Decode one column with a prepared dictionary (codec taken from the handle).
+ * codes is uint8 (FSST-8) or uint16 (OnPair-16); other arguments as
+ * fsst_decode / onpair_decode. */
+fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets, int index_bits,
+                    int64_t n_strings, void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
+                    size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Tuning                                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* Launch parameters of a decode.  A zero field means "automatic".
+ *   mode              0: one pass; each tile finds its output position by a
+ *                        decoupled look-back over the totals published by
+ *                        earlier tiles;
+ *                     1: three phases (tile totals, a scan of the totals,
+ *                        expansion), reading the code stream twice (the
+ *                        "sidecar regenerated at decode time" variant the
+ *                        paper measures in its design overview).
+ *   strings_per_tile  1..512; automatic = about 70% of one pass of codes per
+ *                     tile (a pass is 4096 FSST-8 or 2048 OnPair-16 codes).
+ *   grid              workgroups to launch; automatic = all that can be
+ *                     resident on the device (they pull tiles from a counter).
+ * The decoded result does not depend on the tuning. */
+typedef struct fd_tuning {
+    int32_t mode;
+    int32_t strings_per_tile;
+    int32_t grid;
+    int32_t reserved;
+} fd_tuning;
+
+/* fd_workspace_size for a given tuning (NULL = automatic). */
+fd_status fd_workspace_size_ex(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning *tuning,
+                               size_t *bytes);
+
+/* fd_decode with explicit tuning (NULL = automatic). */
+fd_status fd_decode_ex(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets,
+                       int index_bits, int64_t n_strings, void *out_offsets, uint8_t *out_bytes, int64_t out_capacity,
+                       void *workspace, size_t workspace_bytes, int32_t *status, unsigned flags,
+                       const fd_tuning *tuning, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTDECODE_H */

@@ -1,0 +1,249 @@
+"""MI355X (gfx950) decoder for FSST-8 / OnPair-16 string columns.
+
+Thin Python binding over the C ABI of ``libfastdecode.so`` (declared in
+``include/fastdecode.h``).  PyTorch supplies device memory and streams only;
+every step of the decode runs in the library's HIP kernels.  There is no CPU
+fallback: importing works without the library, but every call raises
+``LibraryNotBuilt`` until ``python -m paper_2609_15034_amd.build`` has run.
+
+Names follow the C ABI:
+  * ``fsst_decode`` / ``onpair_decode``  - one column, raw dictionary;
+  * ``Dict`` (fd_dict) + ``decode_into`` - one column, prepared dictionary;
+  * ``decode``                           - convenience: sizes and allocates the
+                                           outputs (two device passes).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfastdecode.so")
+
+FSST8 = 1
+ONPAIR16 = 2
+CODECS = {"fsst8": FSST8, "onpair16": ONPAIR16}
+ASYNC = 1
+
+OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS, EHIP, ENOMEM = range(10)
+STATUS_NAMES = ["FD_OK", "FD_EINVAL", "FD_EBADCODE", "FD_EESCAPE", "FD_ECAPACITY", "FD_EOVERFLOW", "FD_EBADDICT",
+                "FD_EOFFSETS", "FD_EHIP", "FD_ENOMEM"]
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+class DecodeError(RuntimeError):
+    def __init__(self, status: int, what: str = "decode"):
+        self.status = int(status)
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{what} failed: {name}")
+
+
+class Tuning(ctypes.Structure):
+    """fd_tuning: mode (0 single pass / 1 three phases), strings_per_tile, grid."""
+    _fields_ = [("mode", ctypes.c_int32), ("strings_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfastdecode.so (raises LibraryNotBuilt when it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryNotBuilt(f"{LIB_PATH} is missing: run `python -m paper_2609_15034_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, U = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint
+    S = ctypes.c_size_t
+    L.fd_status_str.restype = ctypes.c_char_p
+    L.fd_status_str.argtypes = [ctypes.c_int]
+    L.fd_version.restype = ctypes.c_char_p
+    L.fd_workspace_size.restype = ctypes.c_int
+    L.fd_workspace_size.argtypes = [ctypes.c_int, I64, I64, ctypes.POINTER(S)]
+    L.fd_workspace_size_ex.restype = ctypes.c_int
+    L.fd_workspace_size_ex.argtypes = [ctypes.c_int, I64, I64, ctypes.POINTER(Tuning), ctypes.POINTER(S)]
+    L.fd_decoded_bound.restype = ctypes.c_int
+    L.fd_decoded_bound.argtypes = [ctypes.c_int, I64, ctypes.POINTER(I64)]
+    dec = [P, I64, P, ctypes.c_int, I64, P, P, I32, P, P, I64, P, S, P, U, P]
+    L.fsst_decode.restype = ctypes.c_int
+    L.fsst_decode.argtypes = dec
+    L.onpair_decode.restype = ctypes.c_int
+    L.onpair_decode.argtypes = dec
+    L.fd_dict_create.restype = ctypes.c_int
+    L.fd_dict_create.argtypes = [ctypes.c_int, P, P, I32, P, ctypes.POINTER(P)]
+    L.fd_dict_destroy.restype = ctypes.c_int
+    L.fd_dict_destroy.argtypes = [P]
+    L.fd_dict_codec.restype = ctypes.c_int
+    L.fd_dict_codec.argtypes = [P]
+    L.fd_dict_size.restype = I32
+    L.fd_dict_size.argtypes = [P]
+    L.fd_decode.restype = ctypes.c_int
+    L.fd_decode.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, P]
+    L.fd_decode_ex.restype = ctypes.c_int
+    L.fd_decode_ex.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, ctypes.POINTER(Tuning), P]
+    _lib = L
+    return L
+
+
+# --------------------------------------------------------------------------- #
+# helpers
+# --------------------------------------------------------------------------- #
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _codec_id(codec) -> int:
+    return CODECS[codec] if isinstance(codec, str) else int(codec)
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, Tuning):
+        return ctypes.byref(t)
+    return ctypes.byref(Tuning(**t))
+
+
+def status_str(status: int) -> str:
+    return lib().fd_status_str(int(status)).decode()
+
+
+def version() -> str:
+    return lib().fd_version().decode()
+
+
+def workspace_size(codec, n_codes: int, n_strings: int, tuning=None) -> int:
+    out = ctypes.c_size_t(0)
+    tu = Tuning(**tuning) if isinstance(tuning, dict) else tuning
+    st = lib().fd_workspace_size_ex(_codec_id(codec), int(n_codes), int(n_strings),
+                                    ctypes.byref(tu) if tu is not None else None, ctypes.byref(out))
+    if st:
+        raise DecodeError(st, "fd_workspace_size")
+    return int(out.value)
+
+
+def decoded_bound(codec, n_codes: int) -> int:
+    out = ctypes.c_int64(0)
+    st = lib().fd_decoded_bound(_codec_id(codec), int(n_codes), ctypes.byref(out))
+    if st:
+        raise DecodeError(st, "fd_decoded_bound")
+    return int(out.value)
+
+
+def alloc_workspace(codec, n_codes: int, n_strings: int, tuning=None, device=None):
+    torch = _torch()
+    n = workspace_size(codec, n_codes, n_strings, tuning)
+    # 256-byte aligned (the caching allocator returns 512-byte aligned blocks)
+    return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+
+def _index_bits(code_off) -> int:
+    torch = _torch()
+    if code_off.dtype == torch.int32:
+        return 32
+    if code_off.dtype == torch.int64:
+        return 64
+    raise TypeError("code_off must be int32 or int64")
+
+
+# --------------------------------------------------------------------------- #
+# one-shot entry points (raw dictionaries)
+# --------------------------------------------------------------------------- #
+def fsst_decode(codes, code_off, dict_bytes, dict_lens, out_off, out_bytes, workspace, status=None,
+                async_=False, stream=None) -> int:
+    """fsst_decode over torch device tensors; returns the fd_status."""
+    return lib().fsst_decode(_ptr(codes), codes.numel(), _ptr(code_off), _index_bits(code_off), code_off.numel() - 1,
+                             _ptr(dict_bytes), _ptr(dict_lens), dict_lens.numel(), _ptr(out_off), _ptr(out_bytes),
+                             out_bytes.numel(), _ptr(workspace), workspace.numel(), _ptr(status),
+                             ASYNC if async_ else 0, _stream_handle(stream))
+
+
+def onpair_decode(codes, code_off, dict_bytes, dict_lens, out_off, out_bytes, workspace, status=None,
+                  async_=False, stream=None) -> int:
+    """onpair_decode over torch device tensors (codes int16/uint16 storage)."""
+    return lib().onpair_decode(_ptr(codes), codes.numel(), _ptr(code_off), _index_bits(code_off),
+                               code_off.numel() - 1, _ptr(dict_bytes), _ptr(dict_lens), dict_lens.numel(),
+                               _ptr(out_off), _ptr(out_bytes), out_bytes.numel(), _ptr(workspace), workspace.numel(),
+                               _ptr(status), ASYNC if async_ else 0, _stream_handle(stream))
+
+
+# --------------------------------------------------------------------------- #
+# prepared dictionaries
+# --------------------------------------------------------------------------- #
+class Dict:
+    """fd_dict: an immutable device-resident dictionary."""
+
+    def __init__(self, codec, dict_bytes, dict_lens, stream=None):
+        self._h = ctypes.c_void_p(0)
+        self.codec = _codec_id(codec)
+        st = lib().fd_dict_create(self.codec, _ptr(dict_bytes), _ptr(dict_lens), dict_lens.numel(),
+                                  _stream_handle(stream), ctypes.byref(self._h))
+        if st:
+            raise DecodeError(st, "fd_dict_create")
+        self.size = int(lib().fd_dict_size(self._h))
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise ValueError("dictionary destroyed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().fd_dict_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode_into(d: Dict, codes, code_off, out_off, out_bytes, workspace, status=None, async_=False,
+                tuning=None, stream=None, n_codes=None) -> int:
+    """fd_decode_ex with preallocated outputs; returns the fd_status (FD_OK when
+    enqueued with async_=True)."""
+    return lib().fd_decode_ex(d.handle, _ptr(codes), int(codes.numel() if n_codes is None else n_codes),
+                              _ptr(code_off), _index_bits(code_off), code_off.numel() - 1, _ptr(out_off),
+                              _ptr(out_bytes), out_bytes.numel() if out_bytes is not None else 0, _ptr(workspace),
+                              workspace.numel(), _ptr(status), ASYNC if async_ else 0, _tuning(tuning),
+                              _stream_handle(stream))
+
+
+def decode(d: Dict, codes, code_off, tuning=None, stream=None):
+    """Decode a column into new tensors (out_offsets, out_bytes).  Runs a
+    first pass with zero capacity to obtain the offsets and the exact size."""
+    torch = _torch()
+    dev = codes.device
+    ws = alloc_workspace(d.codec, codes.numel(), code_off.numel() - 1, tuning, device=dev)
+    out_off = torch.empty(code_off.numel(), dtype=code_off.dtype, device=dev)
+    empty = torch.empty(0, dtype=torch.uint8, device=dev)
+    st = decode_into(d, codes, code_off, out_off, empty, ws, tuning=tuning, stream=stream)
+    if st not in (OK, ECAPACITY):
+        raise DecodeError(st)
+    total = int(out_off[-1].item())
+    out = torch.empty(total, dtype=torch.uint8, device=dev)
+    st = decode_into(d, codes, code_off, out_off, out, ws, tuning=tuning, stream=stream)
+    if st != OK:
+        raise DecodeError(st)
+    return out_off, out

@@ -1,0 +1,385 @@
+// Host runtime behind the C ABI: argument validation, workspace layout,
+// launch planning, device-resident dictionaries and status reporting.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+#include "fastdecode.h"
+#include "fd_internal.h"
+
+using namespace fd;
+
+struct fd_dict {
+    fd_codec codec;
+    int32_t n;
+    int device;
+    void* mem;              // single device allocation owned by the handle
+    const uint8_t* bytes;   // FSST-8: packed symbols (copy)
+    const uint8_t* lens;    // FSST-8: lengths (copy)
+    const uint4* tok16;     // OnPair-16: fixed 16-byte entries, 65,536 of them
+    const uint8_t* tok_len; // OnPair-16: 65,536 lengths (0 = invalid code)
+};
+
+namespace {
+
+constexpr size_t kHdr = 256;                 // err, counters, status words
+constexpr size_t kOffErr = 0;
+constexpr size_t kOffCounters = 8;
+constexpr size_t kOffStatus = 16;
+constexpr size_t kOffBadFlag = 20;
+constexpr size_t kTok16Bytes = 65536 * 16;
+constexpr size_t kTokLenBytes = 65536;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Plan {
+    int64_t sb;
+    int64_t n_tiles;
+    size_t off_tiles;
+    size_t off_dict;   // OnPair: prepared dictionary for the one-shot entry point
+    size_t bytes;
+};
+
+int codes_per_pass(fd_codec c) { return kWG * (c == FD_FSST8 ? 16 : 8); }
+
+bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl) {
+    if (n_codes < 0 || n_strings < 0) return false;
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16) return false;
+    int64_t sb = tu ? tu->strings_per_tile : 0;
+    if (sb < 0 || sb > kSbMax) return false;
+    if (sb == 0) {
+        const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+        const double target = 0.7 * codes_per_pass(codec);
+        double v = target / (mean < 1.0 ? 1.0 : mean);
+        sb = (int64_t)v;
+        if (sb < 1) sb = 1;
+        if (sb > kSbMax) sb = kSbMax;
+    }
+    pl->sb = sb;
+    pl->n_tiles = n_strings == 0 ? 1 : (n_strings + sb - 1) / sb;
+    pl->off_tiles = kHdr;
+    pl->off_dict = align_up(pl->off_tiles + (size_t)pl->n_tiles * 8, 256);
+    pl->bytes = pl->off_dict + (codec == FD_ONPAIR16 ? align_up(kTok16Bytes + kTokLenBytes, 256) : 0);
+    return true;
+}
+
+struct DevInfo {
+    int cus = 0;
+    int occ[3][2][3] = {};  // [codec][index64][mode]
+};
+std::mutex g_mu;
+DevInfo g_dev[64];
+
+int resident_grid(int codec, int index_bits, int mode) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevInfo& d = g_dev[dev];
+    if (!d.cus) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 1;
+        d.cus = v;
+    }
+    int& o = d.occ[codec][index_bits == 64][mode];
+    if (!o) o = decode_occupancy(codec, index_bits, mode);
+    return d.cus * o;
+}
+
+fd_status hip_fail() { return FD_EHIP; }
+
+struct Args {
+    fd_codec codec;
+    const void* codes;
+    int64_t n_codes;
+    const void* code_off;
+    int index_bits;
+    int64_t n_strings;
+    // raw dictionary (one-shot) or prepared handle
+    const uint8_t* dict_bytes;
+    const uint8_t* dict_lens;
+    int32_t n_dict;
+    const fd_dict* dict;
+    void* out_off;
+    uint8_t* out;
+    int64_t out_cap;
+    void* ws;
+    size_t ws_bytes;
+    int32_t* status;
+    unsigned flags;
+    const fd_tuning* tuning;
+    hipStream_t stream;
+};
+
+fd_status run_decode(const Args& a) {
+    // ---------------- host-side validation ----------------
+    if (a.index_bits != 32 && a.index_bits != 64) return FD_EINVAL;
+    if (a.n_strings < 0 || a.n_codes < 0 || a.out_cap < 0) return FD_EINVAL;
+    if (a.n_strings > (int64_t)1 << 40 || a.n_codes > (int64_t)1 << 40) return FD_EINVAL;
+    if (!a.code_off || !a.out_off || !a.ws) return FD_EINVAL;
+    if (a.n_codes > 0 && !a.codes) return FD_EINVAL;
+    if (a.out_cap > 0 && !a.out) return FD_EINVAL;
+    if ((a.flags & FD_ASYNC) && !a.status) return FD_EINVAL;
+    if (a.codec == FD_ONPAIR16 && a.codes && ((uintptr_t)a.codes & 1)) return FD_EINVAL;
+    if (a.index_bits == 32 && (a.n_codes > INT32_MAX || ((uintptr_t)a.code_off & 3) || ((uintptr_t)a.out_off & 3)))
+        return FD_EINVAL;
+    if (a.index_bits == 64 && (((uintptr_t)a.code_off & 7) || ((uintptr_t)a.out_off & 7))) return FD_EINVAL;
+    if ((uintptr_t)a.ws & 255) return FD_EINVAL;
+    const int mode_sel = a.tuning ? a.tuning->mode : 0;
+    if (mode_sel != 0 && mode_sel != 1) return FD_EINVAL;
+    if (a.tuning && a.tuning->grid < 0) return FD_EINVAL;
+    if (!a.dict) {
+        if (a.n_dict < 0) return FD_EINVAL;
+        if (a.codec == FD_FSST8 && a.n_dict > 255) return FD_EINVAL;
+        if (a.codec == FD_ONPAIR16 && a.n_dict > 65536) return FD_EINVAL;
+        if (a.n_dict > 0 && (!a.dict_lens || !a.dict_bytes)) return FD_EINVAL;
+    }
+    Plan pl;
+    if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl)) return FD_EINVAL;
+    if (a.ws_bytes < pl.bytes) return FD_EINVAL;
+
+    uint8_t* ws = (uint8_t*)a.ws;
+    DecodeParams p;
+    memset(&p, 0, sizeof(p));
+    p.codes = (const uint8_t*)a.codes;
+    p.n_codes = a.n_codes;
+    p.code_off = a.code_off;
+    p.n_strings = a.n_strings;
+    p.out_off = a.out_off;
+    p.out = a.out;
+    p.out_cap = a.out_cap;
+    p.n_tiles = pl.n_tiles;
+    p.sb = (int32_t)pl.sb;
+    p.err = (unsigned long long*)(ws + kOffErr);
+    p.counters = (unsigned*)(ws + kOffCounters);
+    p.tstate = (unsigned long long*)(ws + pl.off_tiles);
+    p.status = a.status;
+    p.status2 = (int32_t*)(ws + kOffStatus);
+
+    hipStream_t st = a.stream;
+    if (launch_reset(p.err, p.counters, p.tstate, pl.n_tiles, st) != hipSuccess) return hip_fail();
+
+    if (a.codec == FD_FSST8) {
+        if (a.dict) {
+            p.dict_bytes = a.dict->bytes;
+            p.dict_lens = a.dict->lens;
+            p.n_sym = a.dict->n;
+        } else {
+            p.dict_bytes = a.dict_bytes;
+            p.dict_lens = a.dict_lens;
+            p.n_sym = a.n_dict;
+        }
+    } else {
+        if (a.dict) {
+            p.tok16 = a.dict->tok16;
+            p.tok_len = a.dict->tok_len;
+        } else {
+            uint4* t16 = (uint4*)(ws + pl.off_dict);
+            uint8_t* tl = ws + pl.off_dict + kTok16Bytes;
+            if (launch_onpair_prepare(a.dict_bytes, a.dict_lens, a.n_dict, t16, tl, p.err, nullptr, st) != hipSuccess)
+                return hip_fail();
+            p.tok16 = t16;
+            p.tok_len = tl;
+        }
+    }
+
+    const int codec = (int)a.codec;
+    int grid_req = a.tuning ? a.tuning->grid : 0;
+    if (mode_sel == 0) {
+        int grid = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeLookback);
+        if ((int64_t)grid > pl.n_tiles) grid = (int)pl.n_tiles;
+        if (launch_decode(codec, a.index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();
+    } else {
+        int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
+        if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
+        if (launch_decode(codec, a.index_bits, kModeTotals, p, g1, st) != hipSuccess) return hip_fail();
+        if (launch_scan_totals(p.tstate, pl.n_tiles, st) != hipSuccess) return hip_fail();
+        // the expand phase takes tiles from the counter again
+        if (launch_reset(nullptr, p.counters, nullptr, 0, st) != hipSuccess) return hip_fail();
+        int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
+        if ((int64_t)g2 > pl.n_tiles) g2 = (int)pl.n_tiles;
+        if (launch_decode(codec, a.index_bits, kModeExpand, p, g2, st) != hipSuccess) return hip_fail();
+    }
+
+    if (a.flags & FD_ASYNC) return FD_OK;
+    if (hipStreamSynchronize(st) != hipSuccess) return hip_fail();
+    int32_t hs = 0;
+    if (hipMemcpy(&hs, p.status2, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail();
+    return (fd_status)hs;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fd_status_str(int status) {
+    switch (status) {
+        case FD_OK: return "FD_OK";
+        case FD_EINVAL: return "FD_EINVAL";
+        case FD_EBADCODE: return "FD_EBADCODE";
+        case FD_EESCAPE: return "FD_EESCAPE";
+        case FD_ECAPACITY: return "FD_ECAPACITY";
+        case FD_EOVERFLOW: return "FD_EOVERFLOW";
+        case FD_EBADDICT: return "FD_EBADDICT";
+        case FD_EOFFSETS: return "FD_EOFFSETS";
+        case FD_EHIP: return "FD_EHIP";
+        case FD_ENOMEM: return "FD_ENOMEM";
+        default: return "FD_UNKNOWN";
+    }
+}
+
+const char* fd_version(void) { return "fastdecode 0.1 gfx950"; }
+
+fd_status fd_workspace_size_ex(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tuning,
+                               size_t* bytes) {
+    if (!bytes) return FD_EINVAL;
+    Plan pl;
+    if (!plan_for(codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
+    *bytes = pl.bytes;
+    return FD_OK;
+}
+
+fd_status fd_workspace_size(fd_codec codec, int64_t n_codes, int64_t n_strings, size_t* bytes) {
+    return fd_workspace_size_ex(codec, n_codes, n_strings, nullptr, bytes);
+}
+
+fd_status fd_decoded_bound(fd_codec codec, int64_t n_codes, int64_t* bytes) {
+    if (!bytes || n_codes < 0) return FD_EINVAL;
+    if (codec == FD_FSST8) *bytes = n_codes * 8;
+    else if (codec == FD_ONPAIR16) *bytes = n_codes * 16;
+    else return FD_EINVAL;
+    return FD_OK;
+}
+
+fd_status fsst_decode(const uint8_t* codes, int64_t n_codes, const void* code_offsets, int index_bits,
+                      int64_t n_strings, const uint8_t* dict_bytes, const uint8_t* dict_lens, int32_t n_symbols,
+                      void* out_offsets, uint8_t* out_bytes, int64_t out_capacity, void* workspace,
+                      size_t workspace_bytes, int32_t* status, unsigned flags, void* hip_stream) {
+    Args a;
+    memset(&a, 0, sizeof(a));
+    a.codec = FD_FSST8;
+    a.codes = codes; a.n_codes = n_codes; a.code_off = code_offsets; a.index_bits = index_bits;
+    a.n_strings = n_strings; a.dict_bytes = dict_bytes; a.dict_lens = dict_lens; a.n_dict = n_symbols;
+    a.out_off = out_offsets; a.out = out_bytes; a.out_cap = out_capacity; a.ws = workspace;
+    a.ws_bytes = workspace_bytes; a.status = status; a.flags = flags; a.stream = (hipStream_t)hip_stream;
+    return run_decode(a);
+}
+
+fd_status onpair_decode(const uint16_t* codes, int64_t n_codes, const void* code_offsets, int index_bits,
+                        int64_t n_strings, const uint8_t* dict_bytes, const uint8_t* dict_lens, int32_t n_tokens,
+                        void* out_offsets, uint8_t* out_bytes, int64_t out_capacity, void* workspace,
+                        size_t workspace_bytes, int32_t* status, unsigned flags, void* hip_stream) {
+    Args a;
+    memset(&a, 0, sizeof(a));
+    a.codec = FD_ONPAIR16;
+    a.codes = codes; a.n_codes = n_codes; a.code_off = code_offsets; a.index_bits = index_bits;
+    a.n_strings = n_strings; a.dict_bytes = dict_bytes; a.dict_lens = dict_lens; a.n_dict = n_tokens;
+    a.out_off = out_offsets; a.out = out_bytes; a.out_cap = out_capacity; a.ws = workspace;
+    a.ws_bytes = workspace_bytes; a.status = status; a.flags = flags; a.stream = (hipStream_t)hip_stream;
+    return run_decode(a);
+}
+
+fd_status fd_decode_ex(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets,
+                       int index_bits, int64_t n_strings, void* out_offsets, uint8_t* out_bytes, int64_t out_capacity,
+                       void* workspace, size_t workspace_bytes, int32_t* status, unsigned flags,
+                       const fd_tuning* tuning, void* hip_stream) {
+    if (!dict) return FD_EINVAL;
+    Args a;
+    memset(&a, 0, sizeof(a));
+    a.codec = dict->codec;
+    a.dict = dict;
+    a.codes = codes; a.n_codes = n_codes; a.code_off = code_offsets; a.index_bits = index_bits;
+    a.n_strings = n_strings; a.out_off = out_offsets; a.out = out_bytes; a.out_cap = out_capacity;
+    a.ws = workspace; a.ws_bytes = workspace_bytes; a.status = status; a.flags = flags; a.tuning = tuning;
+    a.stream = (hipStream_t)hip_stream;
+    return run_decode(a);
+}
+
+fd_status fd_decode(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets, int index_bits,
+                    int64_t n_strings, void* out_offsets, uint8_t* out_bytes, int64_t out_capacity, void* workspace,
+                    size_t workspace_bytes, int32_t* status, unsigned flags, void* hip_stream) {
+    return fd_decode_ex(dict, codes, n_codes, code_offsets, index_bits, n_strings, out_offsets, out_bytes,
+                        out_capacity, workspace, workspace_bytes, status, flags, nullptr, hip_stream);
+}
+
+fd_status fd_dict_create(fd_codec codec, const uint8_t* dict_bytes, const uint8_t* dict_lens, int32_t n_tokens,
+                         void* hip_stream, fd_dict** out) {
+    if (!out) return FD_EINVAL;
+    *out = nullptr;
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16) return FD_EINVAL;
+    if (n_tokens < 0 || (codec == FD_FSST8 && n_tokens > 255) || (codec == FD_ONPAIR16 && n_tokens > 65536))
+        return FD_EINVAL;
+    if (n_tokens > 0 && (!dict_bytes || !dict_lens)) return FD_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    fd_dict* d = new (std::nothrow) fd_dict;
+    if (!d) return FD_ENOMEM;
+    memset(d, 0, sizeof(*d));
+    d->codec = codec;
+    d->n = n_tokens;
+    if (hipGetDevice(&d->device) != hipSuccess) { delete d; return FD_EHIP; }
+    // scratch: err word + bad flag
+    const size_t hdr = 256;
+    size_t bytes;
+    if (codec == FD_FSST8) bytes = hdr + 256 + 255 * 8;
+    else bytes = hdr + kTok16Bytes + kTokLenBytes;
+    if (hipMalloc(&d->mem, bytes) != hipSuccess) { delete d; return FD_ENOMEM; }
+    uint8_t* m = (uint8_t*)d->mem;
+    unsigned long long* err = (unsigned long long*)m;
+    int* bad = (int*)(m + 8);
+    if (hipMemsetAsync(m, 0, hdr, st) != hipSuccess) goto fail;
+    if (codec == FD_FSST8) {
+        uint8_t* lens = m + hdr;
+        uint8_t* syms = m + hdr + 256;
+        if (hipMemsetAsync(lens, 0, 256 + 255 * 8, st) != hipSuccess) goto fail;
+        if (n_tokens > 0) {
+            // the packed size is only known on the device: copy lengths first
+            uint8_t hl[256];
+            if (hipMemcpyAsync(hl, dict_lens, (size_t)n_tokens, hipMemcpyDeviceToHost, st) != hipSuccess) goto fail;
+            if (hipStreamSynchronize(st) != hipSuccess) goto fail;
+            size_t sum = 0;
+            for (int i = 0; i < n_tokens; i++) {
+                if (hl[i] == 0 || hl[i] > 8) { (void)hipFree(d->mem); delete d; return FD_EBADDICT; }
+                sum += hl[i];
+            }
+            if (hipMemcpyAsync(lens, dict_lens, (size_t)n_tokens, hipMemcpyDeviceToDevice, st) != hipSuccess) goto fail;
+            if (sum && hipMemcpyAsync(syms, dict_bytes, sum, hipMemcpyDeviceToDevice, st) != hipSuccess) goto fail;
+        }
+        d->lens = lens;
+        d->bytes = syms;
+        if (hipStreamSynchronize(st) != hipSuccess) goto fail;
+    } else {
+        uint4* t16 = (uint4*)(m + hdr);
+        uint8_t* tl = m + hdr + kTok16Bytes;
+        if (launch_onpair_prepare(dict_bytes, dict_lens, n_tokens, t16, tl, err, bad, st) != hipSuccess) goto fail;
+        int hbad = 0;
+        if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) goto fail;
+        if (hipStreamSynchronize(st) != hipSuccess) goto fail;
+        if (hbad) { (void)hipFree(d->mem); delete d; return FD_EBADDICT; }
+        d->tok16 = t16;
+        d->tok_len = tl;
+    }
+    *out = d;
+    return FD_OK;
+fail:
+    (void)hipFree(d->mem);
+    delete d;
+    return FD_EHIP;
+}
+
+fd_status fd_dict_destroy(fd_dict* dict) {
+    if (!dict) return FD_EINVAL;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != dict->device) (void)hipSetDevice(dict->device);
+    hipError_t e = hipFree(dict->mem);
+    if (cur != dict->device) (void)hipSetDevice(cur);
+    delete dict;
+    return e == hipSuccess ? FD_OK : FD_EHIP;
+}
+
+fd_codec fd_dict_codec(const fd_dict* dict) { return dict ? dict->codec : (fd_codec)0; }
+int32_t fd_dict_size(const fd_dict* dict) { return dict ? dict->n : -1; }
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal declarations shared by the decode kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fastdecode.h"
+
+namespace fd {
+
+constexpr int kFsst8 = FD_FSST8;
+constexpr int kOnpair16 = FD_ONPAIR16;
+
+constexpr int kWG = 256;            // threads per workgroup
+constexpr int kNWave = kWG / 64;    // waves per workgroup
+constexpr int kWin = 16384;         // LDS staging window (bytes)
+constexpr int kSbMax = 512;         // strings per tile, at most
+
+// decode modes
+constexpr int kModeLookback = 0;    // single pass, decoupled look-back for tile cursors
+constexpr int kModeTotals = 1;      // three-phase: tile totals only
+constexpr int kModeExpand = 2;      // three-phase: expand with precomputed tile cursors
+
+// tile state words (look-back): 2 flag bits + 62 value bits
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagIncl = 2ull << 62;
+constexpr uint64_t kFlagMask = 3ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;          // look-back sleeps before giving up
+
+// error keys: (rank << 4) | status; the smallest key wins
+constexpr uint64_t kRankInternal = 0;             // look-back wait limit exceeded
+constexpr uint64_t kRankDict = 0;
+constexpr uint64_t kRankOffsets = 1;
+constexpr uint64_t kRankData = 2;                 // + code position
+constexpr uint64_t kRankOverflow = 1ull << 58;
+constexpr uint64_t kRankCapacity = (1ull << 58) + 1;
+
+struct DecodeParams {
+    const uint8_t* codes;          // code stream (uint8 or uint16 codes)
+    int64_t n_codes;
+    const void* code_off;          // int32 / int64, n_strings + 1
+    int64_t n_strings;
+    // FSST-8: packed symbols
+    const uint8_t* dict_bytes;
+    const uint8_t* dict_lens;
+    int32_t n_sym;
+    // OnPair-16: prepared fixed-stride dictionary
+    const uint4* tok16;
+    const uint8_t* tok_len;
+    // outputs
+    void* out_off;
+    uint8_t* out;
+    int64_t out_cap;
+    // tiling
+    int64_t n_tiles;
+    int32_t sb;
+    // workspace
+    unsigned long long* err;
+    unsigned* counters;            // [0] tile counter, [1] finished workgroups
+    unsigned long long* tstate;    // per tile: look-back state / totals / cursors
+    int32_t* status;               // caller's device status (may be null)
+    int32_t* status2;              // workspace status slot
+};
+
+int decode_occupancy(int codec, int index_bits, int mode);
+hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams& p, int grid, hipStream_t st);
+hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* tstate, int64_t n,
+                        hipStream_t st);
+hipError_t launch_scan_totals(unsigned long long* tstate, int64_t n, hipStream_t st);
+hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int32_t n_tok, uint4* tok16,
+                                 uint8_t* tok_len, unsigned long long* err, int* bad_flag, hipStream_t st);
+
+}  // namespace fd

@@ -1,0 +1,94 @@
+"""The C ABI library loads and exports every function include/*.h declares
+(no GPU: only loading, symbol lookup and host-only entry points)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                             src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def fdlib():
+    import paper_2609_15034_amd as fd
+    if not os.path.exists(fd.LIB_PATH):
+        import paper_2609_15034_amd.build as b
+        b.build()
+    return fd
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("fsst_decode", "onpair_decode", "fd_decode", "fd_dict_create", "fd_workspace_size"):
+        assert n in names
+
+
+def test_library_exports_every_declared_function(fdlib):
+    L = ctypes.CDLL(fdlib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_host_only_entry_points(fdlib):
+    fd = fdlib
+    assert fd.status_str(0) == "FD_OK" and fd.status_str(7) == "FD_EOFFSETS" and fd.status_str(99) == "FD_UNKNOWN"
+    assert "gfx950" in fd.version()
+    assert fd.decoded_bound("fsst8", 10) == 80 and fd.decoded_bound("onpair16", 10) == 160
+    a = fd.workspace_size("fsst8", 1000, 10)
+    b = fd.workspace_size("fsst8", 1000, 10, {"mode": 0, "strings_per_tile": 1, "grid": 0, "reserved": 0})
+    assert b >= a > 0
+    # OnPair one-shot decodes repack the dictionary inside the workspace
+    assert fd.workspace_size("onpair16", 1000, 10) > 65536 * 17
+    with pytest.raises(fd.DecodeError):
+        fd.workspace_size("fsst8", -1, 10)
+    with pytest.raises(fd.DecodeError):
+        fd.workspace_size("fsst8", 10, 10, {"mode": 0, "strings_per_tile": 513, "grid": 0, "reserved": 0})
+
+
+def test_argument_errors_enqueue_nothing(fdlib):
+    """Host-side checks reject bad arguments before touching the device."""
+    L = fdlib.lib()
+    P = ctypes.c_void_p
+    fake = P(1 << 20)   # never dereferenced: the call must fail before any launch
+    ws = P(1 << 21)
+    # index_bits 16
+    st = L.fsst_decode(fake, 10, fake, 16, 1, fake, fake, 1, fake, fake, 10, ws, 1 << 20, None, 0, None)
+    assert st == fdlib.EINVAL
+    # workspace too small
+    st = L.fsst_decode(fake, 10, fake, 64, 1, fake, fake, 1, fake, fake, 10, ws, 8, None, 0, None)
+    assert st == fdlib.EINVAL
+    # async without a status pointer
+    st = L.fsst_decode(fake, 10, fake, 64, 1, fake, fake, 1, fake, fake, 10, ws, 1 << 20, None, 1, None)
+    assert st == fdlib.EINVAL
+    # too many symbols / tokens
+    st = L.fsst_decode(fake, 10, fake, 64, 1, fake, fake, 256, fake, fake, 10, ws, 1 << 20, None, 0, None)
+    assert st == fdlib.EINVAL
+    st = L.onpair_decode(fake, 10, fake, 64, 1, fake, fake, 65537, fake, fake, 10, ws, 1 << 22, None, 0, None)
+    assert st == fdlib.EINVAL
+    # odd address for uint16 codes
+    st = L.onpair_decode(P((1 << 20) + 1), 10, fake, 64, 1, fake, fake, 1, fake, fake, 10, ws, 1 << 22, None, 0, None)
+    assert st == fdlib.EINVAL
+    # negative sizes, null workspace
+    st = L.fsst_decode(fake, -1, fake, 64, 1, fake, fake, 1, fake, fake, 10, ws, 1 << 20, None, 0, None)
+    assert st == fdlib.EINVAL
+    st = L.fsst_decode(fake, 10, fake, 64, 1, fake, fake, 1, fake, fake, 10, None, 1 << 20, None, 0, None)
+    assert st == fdlib.EINVAL
+    # misaligned workspace
+    st = L.fsst_decode(fake, 10, fake, 64, 1, fake, fake, 1, fake, fake, 10, P((1 << 21) + 8), 1 << 20, None, 0,
+                       None)
+    assert st == fdlib.EINVAL
+    # null dictionary handle
+    assert L.fd_decode(None, fake, 10, fake, 64, 1, fake, fake, 10, ws, 1 << 20, None, 0, None) == fdlib.EINVAL

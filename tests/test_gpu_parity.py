@@ -1,0 +1,265 @@
+"""GPU parity: the HIP decoder (through the C ABI) against the CPU oracle,
+bit-exact in status, Arrow offsets and bytes, on seeded inputs."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, gpu_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_15034_amd as fd
+    fd.lib()   # raises when the library is not built
+    yield
+
+
+def pack(tokens):
+    lens = np.array([len(t) for t in tokens], np.uint8)
+    return np.frombuffer(b"".join(tokens), np.uint8).copy(), lens
+
+
+# --------------------------------------------------------------------------- #
+# workload recipes at test sizes
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("via", ["dict", "oneshot"])
+def test_fsst_small(datagen_mod, via):
+    c = datagen_mod.fsst_small()
+    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, via=via)
+
+
+@pytest.mark.parametrize("via", ["dict", "oneshot"])
+def test_fsst_logs_8mib(datagen_mod, via):
+    c = datagen_mod.fsst_logs(target_bytes=8 << 20)
+    exp = assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, via=via)
+    assert np.array_equal(exp.out_bytes, c.text)
+
+
+@pytest.mark.parametrize("via", ["dict", "oneshot"])
+def test_onpair_urls_8mib(datagen_mod, via):
+    c = datagen_mod.onpair_urls(target_bytes=8 << 20, sample_bytes=2 << 20)
+    exp = assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens, via=via)
+    assert np.array_equal(exp.out_bytes, c.text)
+
+
+def test_random_full_dictionary(datagen_mod):
+    c = datagen_mod.random_onpair(n_codes=1 << 20, n_strings=20_000)
+    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens)
+
+
+# --------------------------------------------------------------------------- #
+# tuning: modes, tiny tiles (long look-back chains), small grids
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("sb", [0, 1, 3, 17, 512])
+@pytest.mark.parametrize("grid", [0, 1, 7])
+def test_tuning_fsst(datagen_mod, mode, sb, grid):
+    c = datagen_mod.fsst_small(seed=4, n_strings=3000)
+    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens,
+                  tuning={"mode": mode, "strings_per_tile": sb, "grid": grid, "reserved": 0})
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("sb", [0, 1, 5, 512])
+@pytest.mark.parametrize("grid", [0, 2])
+def test_tuning_onpair(datagen_mod, mode, sb, grid):
+    c = datagen_mod.onpair_urls(seed=5, target_bytes=1 << 20, sample_bytes=1 << 20)
+    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens,
+                  tuning={"mode": mode, "strings_per_tile": sb, "grid": grid, "reserved": 0})
+
+
+# --------------------------------------------------------------------------- #
+# FSST-8 escapes: runs of 255 of every length across lane / wave / tile edges
+# --------------------------------------------------------------------------- #
+def _ff_column(seed, n_strings, max_run=300):
+    """Strings whose codes contain runs of 255 of every length 0..max_run.  A
+    run of even length 2m decodes to m bytes 0xFF; a run of odd length is
+    followed by one more byte that becomes a literal."""
+    rng = np.random.default_rng(seed)
+    strings = []
+    run = 0
+    while len(strings) < n_strings:
+        parts = bytearray()
+        for _ in range(int(rng.integers(0, 4))):
+            parts += bytes(rng.integers(0, 3, size=int(rng.integers(0, 20))).astype(np.uint8))  # codes 0..2
+            L = run % (max_run + 1)
+            run += 1
+            parts += b"\xff" * L
+            if L % 2 == 1:
+                parts.append(int(rng.choice([0, 1, 0xFF, 0x41, 200])))   # the literal
+        strings.append(bytes(parts))
+    codes = np.frombuffer(b"".join(strings), np.uint8).copy()
+    off = np.concatenate([[0], np.cumsum([len(s) for s in strings])]).astype(np.int64)
+    return codes, off
+
+
+@pytest.mark.parametrize("sb", [0, 1, 2, 7])
+def test_ff_runs(sb):
+    codes, off = _ff_column(7, 2500)
+    db, dl = pack([b"x", b"yz", b"0123456"])
+    assert_parity("fsst8", codes, off, db, dl, tuning={"mode": 0, "strings_per_tile": sb, "grid": 0, "reserved": 0})
+
+
+def test_ff_run_longer_than_a_pass():
+    """One string whose code stream is a 255 run longer than one pass (4096
+    codes) followed by a literal: parity carried across passes."""
+    for L in (4095, 4096, 4097, 9001, 20000):
+        codes = np.frombuffer(b"\x00" + b"\xff" * L + (b"\x01" if L % 2 else b"") + b"\x02", np.uint8).copy()
+        off = np.array([0, len(codes)], np.int64)
+        db, dl = pack([b"a", b"bc", b"def"])
+        assert_parity("fsst8", codes, off, db, dl)
+
+
+# --------------------------------------------------------------------------- #
+# slices, alignment, empty and degenerate columns
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("mis", [1, 3, 8, 15])
+def test_misaligned_pointers_fsst(datagen_mod, mis):
+    c = datagen_mod.fsst_small(seed=9, n_strings=1500)
+    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, codes_misalign=mis, out_misalign=mis)
+
+
+@pytest.mark.parametrize("mis", [2, 6, 14])
+def test_misaligned_pointers_onpair(datagen_mod, mis):
+    c = datagen_mod.onpair_urls(seed=10, target_bytes=256 << 10, sample_bytes=512 << 10)
+    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens, codes_misalign=mis,
+                  out_misalign=mis + 1)
+
+
+def test_slice(datagen_mod):
+    """code_offsets[0] > 0 and code_offsets[-1] < n_codes (an Arrow slice)."""
+    c = datagen_mod.fsst_small(seed=12, n_strings=4000)
+    sl = c.code_off[1000:3001].astype(np.int64)
+    assert_parity("fsst8", c.codes, sl, c.dict_bytes, c.dict_lens)
+    c2 = datagen_mod.onpair_urls(seed=13, target_bytes=512 << 10, sample_bytes=512 << 10)
+    sl2 = c2.code_off[777:5555]
+    assert_parity("onpair16", c2.codes, sl2, c2.dict_bytes, c2.dict_lens)
+
+
+def test_empty_and_degenerate():
+    db, dl = pack([b"ab", b"c"])
+    u8 = lambda *x: np.array(x, np.uint8)
+    # no strings
+    assert_parity("fsst8", u8(0, 1), np.array([0], np.int64), db, dl)
+    assert_parity("fsst8", np.zeros(0, np.uint8), np.array([0], np.int32), db, dl)
+    # all strings empty
+    assert_parity("fsst8", u8(0, 1, 1), np.zeros(1000, np.int64), db, dl)
+    # one code
+    assert_parity("fsst8", u8(1), np.array([0, 1], np.int64), db, dl)
+    assert_parity("onpair16", np.array([1], np.uint16), np.array([0, 1], np.int64), db, dl)
+    # strings of a single escape pair; empty strings in between
+    assert_parity("fsst8", u8(255, 7, 255, 255), np.array([0, 2, 2, 2, 4], np.int64), db, dl)
+    # empty dictionary: every code is bad
+    assert_parity("fsst8", u8(0), np.array([0, 1], np.int64), np.zeros(0, np.uint8), np.zeros(0, np.uint8),
+                  via="oneshot")
+
+
+@pytest.mark.parametrize("case", ["identity_onpair", "identity_fsst"])
+def test_identity_dictionaries(case):
+    rng = np.random.default_rng(3)
+    if case == "identity_onpair":
+        db, dl = pack([bytes([b]) for b in range(256)])
+        codes = rng.integers(0, 256, size=300_000).astype(np.uint16)
+        off = np.concatenate([[0], np.sort(rng.integers(0, len(codes), 4999)), [len(codes)]]).astype(np.int64)
+        exp = assert_parity("onpair16", codes, off, db, dl)
+        assert np.array_equal(exp.out_bytes, codes.astype(np.uint8))
+    else:
+        db, dl = pack([bytes([b]) for b in range(255)])
+        text = rng.integers(0, 256, size=200_000).astype(np.uint8)
+        codes = np.frombuffer(text.tobytes().replace(b"\xff", b"\xff\xff"), np.uint8).copy()
+        exp = assert_parity("fsst8", codes, np.array([0, len(codes)], np.int64), db, dl)
+        assert np.array_equal(exp.out_bytes, text)
+
+
+# --------------------------------------------------------------------------- #
+# errors (device-detected) and the status protocol
+# --------------------------------------------------------------------------- #
+def test_device_errors():
+    db, dl = pack([b"ab", b"c"])
+    u8 = lambda *x: np.array(x, np.uint8)
+    i64 = lambda *x: np.array(x, np.int64)
+    assert_parity("fsst8", u8(0, 9, 1), i64(0, 3), db, dl)                 # EBADCODE
+    assert_parity("fsst8", u8(0, 255, 1), i64(0, 2, 3), db, dl)            # EESCAPE (escape ends string 0)
+    assert_parity("fsst8", u8(0, 1, 255, 255, 255), i64(0, 2, 5), db, dl)  # EESCAPE after a literal 255
+    assert_parity("fsst8", u8(0, 1, 0), i64(0, 2, 1), db, dl)              # EOFFSETS (decreasing)
+    assert_parity("fsst8", u8(0, 1, 0), i64(-1, 2), db, dl)                # EOFFSETS (negative)
+    assert_parity("fsst8", u8(0, 1, 0), i64(0, 4), db, dl)                 # EOFFSETS (past n_codes)
+    assert_parity("fsst8", u8(0, 1), i64(0, 2), *pack([b"", b"c"]), via="oneshot")   # EBADDICT
+    assert_parity("fsst8", u8(0, 1), i64(0, 2), *pack([b"123456789", b"c"]), via="oneshot")
+    assert_parity("onpair16", np.array([0, 5], np.uint16), i64(0, 2), db, dl)   # EBADCODE
+    assert_parity("onpair16", np.array([0, 1], np.uint16), i64(0, 2), *pack([b"x" * 17, b"c"]), via="oneshot")
+    # precedence: the data error at the lowest position wins
+    assert_parity("fsst8", u8(9, 0, 255), i64(0, 3), db, dl)
+    assert_parity("fsst8", u8(0, 255, 9), i64(0, 2, 3), db, dl)
+    # EBADDICT before EOFFSETS before data errors
+    assert_parity("fsst8", u8(9), i64(1, 0), *pack([b"", b"c"]), via="oneshot")
+    assert_parity("fsst8", u8(9), i64(0, 2), db, dl)
+
+
+def test_dict_create_rejects_bad_lengths():
+    import torch
+    import paper_2609_15034_amd as fd
+    for codec, toks in (("fsst8", [b"", b"a"]), ("fsst8", [b"123456789"]), ("onpair16", [b"x" * 17]),
+                        ("onpair16", [b"a", b""])):
+        db, dl = pack(toks)
+        dbt = torch.from_numpy(db if len(db) else np.zeros(1, np.uint8)).cuda()
+        with pytest.raises(fd.DecodeError) as e:
+            fd.Dict(codec, dbt, torch.from_numpy(dl).cuda())
+        assert e.value.status == fd.EBADDICT
+
+
+def test_capacity_too_small(datagen_mod):
+    """ECAPACITY: offsets complete, bytes below the capacity correct, nothing
+    written past it (guard bands)."""
+    c = datagen_mod.fsst_small(seed=21, n_strings=2000)
+    total = len(c.text)
+    for cap in (0, 1, 17, total // 2, total - 1):
+        assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, cap=cap)
+    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, cap=total)
+    c2 = datagen_mod.onpair_urls(seed=22, target_bytes=256 << 10, sample_bytes=256 << 10)
+    assert_parity("onpair16", c2.codes, c2.code_off, c2.dict_bytes, c2.dict_lens, cap=len(c2.text) // 3)
+
+
+def test_overflow_int32():
+    """int32 offsets cannot hold 2**31 decoded bytes: EOVERFLOW (capacity 0,
+    so no 2 GiB output is needed), and exactly INT32_MAX fits."""
+    db, dl = pack([b"0123456789abcdef", b"0123456789abcde"])
+    n = 2 ** 27
+    codes = np.zeros(n, np.uint16)
+    st, _, _, _ = gpu_decode("onpair16", codes, np.array([0, n], np.int32), db, dl, cap=0)
+    assert st == 5
+    codes[-1] = 1
+    st, off, _, _ = gpu_decode("onpair16", codes, np.array([0, n], np.int32), db, dl, cap=0)
+    assert st == 4 and int(off[-1]) == 2 ** 31 - 1
+
+
+def test_async_status(datagen_mod):
+    c = datagen_mod.fsst_small(seed=31, n_strings=500)
+    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, async_=True)
+    db, dl = pack([b"ab", b"c"])
+    assert_parity("fsst8", np.array([0, 9], np.uint8), np.array([0, 2], np.int64), db, dl, async_=True)
+
+
+def test_determinism_repeated(datagen_mod):
+    """Tiny tiles (long look-back chains) and different grids: every repeat is
+    identical to the oracle."""
+    c = datagen_mod.fsst_small(seed=41, n_strings=4000)
+    for rep in range(12):
+        grid = [0, 1, 3, 64][rep % 4]
+        assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens,
+                      tuning={"mode": 0, "strings_per_tile": 1 + rep % 3, "grid": grid, "reserved": 0})
+
+
+def test_decode_convenience(datagen_mod):
+    import torch
+    import oracle
+    import paper_2609_15034_amd as fd
+    c = datagen_mod.onpair_urls(seed=51, target_bytes=512 << 10, sample_bytes=512 << 10)
+    d = fd.Dict("onpair16", torch.from_numpy(c.dict_bytes).cuda(), torch.from_numpy(c.dict_lens).cuda())
+    off, out = fd.decode(d, torch.from_numpy(c.codes.view(np.int16)).cuda(), torch.from_numpy(c.code_off).cuda())
+    exp = oracle.decode("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens)
+    assert np.array_equal(off.cpu().numpy(), exp.out_off) and np.array_equal(out.cpu().numpy(), exp.out_bytes)
