@@ -38,30 +38,48 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Plan {
     int64_t sb;
     int64_t n_tiles;
+    int64_t n_blocks;
     size_t off_tiles;
+    size_t off_blocks;
     size_t off_dict;   // OnPair: prepared dictionary for the one-shot entry point
     size_t bytes;
 };
 
-int codes_per_pass(fd_codec c) { return kWG * (c == FD_FSST8 ? 16 : 8); }
+// Codes one super-pass of a workgroup holds in registers.
+int64_t codes_per_pass(fd_codec c) {
+    const int codec = (int)c;
+    return (int64_t)kWG * chunks_per_lane(codec) * codes_per_chunk(codec);
+}
+
+// Strings per tile: the largest count whose expected code count plus four
+// standard deviations (per-string coefficient of variation taken as 0.6) fits
+// in one super-pass, so that almost every tile is decoded in one pass.
+int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings) {
+    const double cap = (double)codes_per_pass(codec) - 16.0;
+    const double m = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+    const double mean = m < 1.0 ? 1.0 : m;
+    int64_t sb = 1;
+    for (int64_t lo = 1, hi = codec == FD_FSST8 ? kSbMaxFsst : kSbMax; lo <= hi;) {
+        const int64_t mid = (lo + hi) / 2;
+        const double need = mid * mean + 4.0 * 0.6 * mean * __builtin_sqrt((double)mid);
+        if (need <= cap) { sb = mid; lo = mid + 1; } else { hi = mid - 1; }
+    }
+    return sb;
+}
 
 bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl) {
     if (n_codes < 0 || n_strings < 0) return false;
     if (codec != FD_FSST8 && codec != FD_ONPAIR16) return false;
+    const int64_t sb_max = codec == FD_FSST8 ? kSbMaxFsst : kSbMax;
     int64_t sb = tu ? tu->strings_per_tile : 0;
-    if (sb < 0 || sb > kSbMax) return false;
-    if (sb == 0) {
-        const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
-        const double target = 0.7 * codes_per_pass(codec);
-        double v = target / (mean < 1.0 ? 1.0 : mean);
-        sb = (int64_t)v;
-        if (sb < 1) sb = 1;
-        if (sb > kSbMax) sb = kSbMax;
-    }
+    if (sb < 0 || sb > sb_max) return false;
+    if (sb == 0) sb = auto_strings_per_tile(codec, n_codes, n_strings);
     pl->sb = sb;
     pl->n_tiles = n_strings == 0 ? 1 : (n_strings + sb - 1) / sb;
+    pl->n_blocks = (pl->n_tiles + kBlk - 1) / kBlk;
     pl->off_tiles = kHdr;
-    pl->off_dict = align_up(pl->off_tiles + (size_t)pl->n_tiles * 8, 256);
+    pl->off_blocks = pl->off_tiles + (size_t)pl->n_tiles * 8;
+    pl->off_dict = align_up(pl->off_blocks + (size_t)pl->n_blocks * 8, 256);
     pl->bytes = pl->off_dict + (codec == FD_ONPAIR16 ? align_up(kTok16Bytes + kTokLenBytes, 256) : 0);
     return true;
 }
@@ -154,12 +172,14 @@ fd_status run_decode(const Args& a) {
     p.sb = (int32_t)pl.sb;
     p.err = (unsigned long long*)(ws + kOffErr);
     p.counters = (unsigned*)(ws + kOffCounters);
-    p.tstate = (unsigned long long*)(ws + pl.off_tiles);
+    p.tagg = (unsigned long long*)(ws + pl.off_tiles);
+    p.bstate = (unsigned long long*)(ws + pl.off_blocks);
     p.status = a.status;
     p.status2 = (int32_t*)(ws + kOffStatus);
 
     hipStream_t st = a.stream;
-    if (launch_reset(p.err, p.counters, p.tstate, pl.n_tiles, st) != hipSuccess) return hip_fail();
+    // tile aggregates and block states are contiguous: one zeroing covers both
+    if (launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + pl.n_blocks, st) != hipSuccess) return hip_fail();
 
     if (a.codec == FD_FSST8) {
         if (a.dict) {
@@ -195,7 +215,7 @@ fd_status run_decode(const Args& a) {
         int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
         if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
         if (launch_decode(codec, a.index_bits, kModeTotals, p, g1, st) != hipSuccess) return hip_fail();
-        if (launch_scan_totals(p.tstate, pl.n_tiles, st) != hipSuccess) return hip_fail();
+        if (launch_scan_totals(p.tagg, pl.n_tiles, st) != hipSuccess) return hip_fail();
         // the expand phase takes tiles from the counter again
         if (launch_reset(nullptr, p.counters, nullptr, 0, st) != hipSuccess) return hip_fail();
         int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);

@@ -14,7 +14,10 @@ constexpr int kOnpair16 = FD_ONPAIR16;
 constexpr int kWG = 256;            // threads per workgroup
 constexpr int kNWave = kWG / 64;    // waves per workgroup
 constexpr int kWin = 16384;         // LDS staging window (bytes)
-constexpr int kSbMax = 512;         // strings per tile, at most
+constexpr int kSbMax = 1024;        // strings per tile, at most (OnPair-16)
+constexpr int kSbMaxFsst = 256;     // strings per tile, at most (FSST-8)
+constexpr int kBlkShift = 6;        // tiles per look-back block: 64
+constexpr int kBlk = 1 << kBlkShift;
 
 // decode modes
 constexpr int kModeLookback = 0;    // single pass, decoupled look-back for tile cursors
@@ -58,16 +61,19 @@ struct DecodeParams {
     // workspace
     unsigned long long* err;
     unsigned* counters;            // [0] tile counter, [1] finished workgroups
-    unsigned long long* tstate;    // per tile: look-back state / totals / cursors
+    unsigned long long* tagg;      // per tile: aggregate (look-back) / total / cursor (three phases)
+    unsigned long long* bstate;    // per block of kBlk tiles: look-back state
     int32_t* status;               // caller's device status (may be null)
     int32_t* status2;              // workspace status slot
 };
 
 int decode_occupancy(int codec, int index_bits, int mode);
 hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams& p, int grid, hipStream_t st);
-hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* tstate, int64_t n,
+hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n,
                         hipStream_t st);
-hipError_t launch_scan_totals(unsigned long long* tstate, int64_t n, hipStream_t st);
+hipError_t launch_scan_totals(unsigned long long* v, int64_t n, hipStream_t st);
+int chunks_per_lane(int codec);   // 16-byte code chunks each lane holds per super-pass
+int codes_per_chunk(int codec);
 hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int32_t n_tok, uint4* tok16,
                                  uint8_t* tok_len, unsigned long long* err, int* bad_flag, hipStream_t st);
 

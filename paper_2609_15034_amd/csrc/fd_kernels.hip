@@ -1,38 +1,40 @@
 // Decode kernels for FSST-8 and OnPair-16 string columns on gfx950 (CDNA4).
 //
-// One workgroup (4 waves of 64 lanes) decodes one tile at a time; tiles are
-// taken from a global counter in increasing order so that the decoupled
-// look-back over earlier tiles always makes progress.
+// Work decomposition.  A tile is a block of `sb` consecutive strings, so every
+// tile starts at a string boundary, where the FSST-8 escape state is "expect a
+// code" (an escape never crosses a string).  A workgroup (4 waves of 64 lanes)
+// decodes one tile at a time and takes tiles from a global counter in
+// increasing order (the next tile id is requested while the current one is
+// decoded).  Inside a tile the code range is cut into 16-byte-aligned chunks
+// (16 FSST codes or 8 OnPair codes); lane l owns P consecutive chunks, so its
+// codes are contiguous in the stream and stay in registers from the length
+// scan to the emit.  A tile with more chunks than one such "super-pass" holds
+// is decoded in several super-passes (lengths are recomputed for the emit).
 //
-// A tile is a block of `sb` consecutive strings, so a tile always starts at a
-// string boundary: the FSST-8 escape state is "expect a code" there (an escape
-// never crosses a string).  Inside a tile, lane l of a pass owns the 16 code
-// bytes of one 16-byte-aligned chunk of the code stream (16 FSST codes or 8
-// OnPair codes).  Per pass:
-//   1. load   - one 16-byte load per lane (the input stage of Algorithm 1,
-//               with lane-contiguous chunks instead of a stride-32 layout);
-//   2. parity - FSST-8 only: whether a lane starts on a literal follows from
-//               the parity of the run of 255 bytes before it (ballots over the
-//               wave, then over the waves of the workgroup);
-//   3. length - decoded length of each code (token length, 0 for an escape, 1
-//               for a literal) and the lane-serial prefix inside the chunk;
-//   4. scan   - workgroup exclusive scan of lane totals (the WarpPrefixSum of
-//               Algorithm 1 at workgroup scope);
-//   5. cursor - the tile's output position: decoupled look-back over earlier
-//               tiles' published totals (the on-device replacement of the
-//               paper's per-batch sidecar), or a precomputed cursor;
-//   6. emit   - every lane copies its tokens in order into an LDS staging
-//               window placed at the destination's alignment (Algorithm 1's
-//               emit stage); a lane writes whole 8/16-byte entries and lets its
-//               own next token overwrite the excess (the copy-and-advance loop
-//               of OnPair's CPU decoder), and writes exact lengths where the
-//               excess would leave its own range;
-//   7. drain  - aligned 16-byte stores of the staged window to the output,
-//               byte stores only for the unaligned head / tail (Algorithm 1's
-//               drain stage);
-//   8. offsets - Arrow offsets of the strings that start in the pass, from the
-//               per-code prefix kept in LDS.
-// No floating point anywhere.
+// Steps per super-pass (the stages of the paper's Algorithm 1, re-cut for
+// wave64 and LDS):
+//   load    - P 16-byte loads per lane (the input stage);
+//   parity  - FSST-8: a position is a literal iff the run of 255 bytes right
+//             before it has odd length; lanes classify their codes with a
+//             bit-parallel carry trick, and the run parity entering a lane
+//             comes from ballots over the wave and the waves of the workgroup;
+//   lengths - decoded length per code (token length, 0 for an escape, 1 for a
+//             literal), lane totals and per-code prefixes inside each chunk;
+//   scan    - workgroup exclusive scan of lane totals (WarpPrefixSum at
+//             workgroup scope);
+//   cursor  - the tile's output position by a two-level decoupled look-back
+//             (tiles inside a block of 64, then block totals), the on-device
+//             replacement of the paper's per-batch sidecar;
+//   emit    - each lane copies its tokens in order into an LDS staging window
+//             placed at the destination's 16-byte alignment; it writes whole
+//             8/16-byte entries and lets its own next token overwrite the
+//             excess (the copy-and-advance idea of OnPair's CPU loop), and
+//             writes exact lengths where the excess would leave its range;
+//   drain   - aligned 16-byte nontemporal stores, byte stores only for the
+//             head and tail of the range (the drain stage);
+//   offsets - Arrow offsets of the strings starting in the super-pass from the
+//             per-code prefixes kept in LDS.
+// All arithmetic is integer.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,9 +43,19 @@
 namespace fd {
 
 // --------------------------------------------------------------------------
-// small device helpers
+// device helpers
 // --------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// values the workgroup shares through LDS are uniform: keep them in SGPRs
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const unsigned lane = lane_id();
@@ -74,29 +86,28 @@ __device__ __forceinline__ void record_error(unsigned long long* err, uint64_t r
     atomicMin(err, (unsigned long long)((rank << 4) | (uint64_t)status));
 }
 
-// records the minimum of per-lane data-error keys of a wave (lanes without an
-// error pass UINT64_MAX)
+__device__ __forceinline__ uint64_t data_error_key(int64_t pos, int status) {
+    return ((uint64_t)(pos + (int64_t)kRankData) << 4) | (uint64_t)status;
+}
+
+// minimum over the wave of per-lane error keys (UINT64_MAX = none), one atomic
 __device__ __forceinline__ void wave_record_error(unsigned long long* err, uint64_t key) {
     if (__ballot(key != ~0ull)) {
-        uint64_t m = wave_min_u64(key);
+        const uint64_t m = wave_min_u64(key);
         if (lane_id() == 0) atomicMin(err, (unsigned long long)m);
     }
 }
 
-__device__ __forceinline__ uint64_t data_error_key(int64_t pos, int status) {
-    return ((uint64_t)(pos + kRankData) << 4) | (uint64_t)status;
-}
-
 // unaligned LDS stores (gfx950 supports unaligned DS access)
+__device__ __forceinline__ void lds_put16(uint8_t* p, u32x4 v) { __builtin_memcpy(p, &v, 16); }
 __device__ __forceinline__ void lds_put8(uint8_t* p, uint64_t v) { __builtin_memcpy(p, &v, 8); }
-__device__ __forceinline__ void lds_put16(uint8_t* p, uint4 v) { __builtin_memcpy(p, &v, 16); }
 __device__ __forceinline__ void lds_put4(uint8_t* p, uint32_t v) { __builtin_memcpy(p, &v, 4); }
 __device__ __forceinline__ void lds_put2(uint8_t* p, uint32_t v) {
-    uint16_t h = (uint16_t)v;
+    const uint16_t h = (uint16_t)v;
     __builtin_memcpy(p, &h, 2);
 }
 
-// Exact write of l (<= 8) bytes of v at p.
+// exact write of l (0..8) bytes of v
 __device__ __forceinline__ void lds_put_exact8(uint8_t* p, uint64_t v, uint32_t l) {
     if (l == 8) {
         lds_put8(p, v);
@@ -108,528 +119,816 @@ __device__ __forceinline__ void lds_put_exact8(uint8_t* p, uint64_t v, uint32_t 
     if (l & 1) { p[o] = (uint8_t)v; }
 }
 
-// Exact write of l (<= 16) bytes of v at p.
-__device__ __forceinline__ void lds_put_exact16(uint8_t* p, uint4 v, uint32_t l) {
+// exact write of l (0..16) bytes of v
+__device__ __forceinline__ void lds_put_exact16(uint8_t* p, u32x4 v, uint32_t l) {
     if (l == 16) {
         lds_put16(p, v);
         return;
     }
-    uint64_t lo = ((uint64_t)v.y << 32) | v.x, hi = ((uint64_t)v.w << 32) | v.z;
+    uint64_t lo = ((uint64_t)v.y << 32) | v.x;
+    const uint64_t hi = ((uint64_t)v.w << 32) | v.z;
     if (l & 8) { lds_put8(p, lo); p += 8; lo = hi; }
     lds_put_exact8(p, lo, l & 7);
 }
 
-// native 4 x u32 vector (the nontemporal builtins need a clang vector type)
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// byte j (0..15) of a 16-byte value held as 4 dwords
-__device__ __forceinline__ uint32_t byte_of(const uint32_t w[4], int j) { return (w[j >> 2] >> (8 * (j & 3))) & 0xffu; }
-
-// --------------------------------------------------------------------------
-// codec traits
-// --------------------------------------------------------------------------
-template <int CODEC> struct Codec;
-template <> struct Codec<kFsst8> {
-    static constexpr int CB = 1;       // bytes per code
-    static constexpr int CPL = 16;     // codes per lane (one 16-byte chunk)
-    static constexpr int MAXLEN = 8;
-};
-template <> struct Codec<kOnpair16> {
-    static constexpr int CB = 2;
-    static constexpr int CPL = 8;
-    static constexpr int MAXLEN = 16;
-};
-
-// --------------------------------------------------------------------------
-// shared memory
-// --------------------------------------------------------------------------
-struct Smem {
-    uint8_t stage[kWin];                // staging window
-    uint8_t pre8[kWG * 16];             // per code: lane-local exclusive prefix | escape bit
-    uint32_t lane_pre[kWG];             // per lane: exclusive prefix inside the pass
-    int64_t coff[kSbMax + 1];           // the tile's code offsets
-    uint64_t fsst_tab[256];             // FSST-8 symbols, zero padded
-    uint8_t fsst_len[256];              // FSST-8 symbol lengths (0 = not a symbol)
-    uint32_t wtmp[kNWave];
-    uint32_t wtmp2[kNWave];
-    int64_t bcast[4];
-    uint32_t flag;
-};
-
-// --------------------------------------------------------------------------
-// workgroup helpers
-// --------------------------------------------------------------------------
-// exclusive scan of one uint32 per thread over the workgroup; returns the
-// exclusive prefix and writes the workgroup total.  Contains two barriers.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* total, uint32_t* s_w) {
-    const unsigned tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t incl = wave_incl_scan(x);
-    if (lane == 63) s_w[w] = incl;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < kNWave; i++) {
-        uint32_t v = s_w[i];
-        base += (i < (int)w) ? v : 0u;
-        tot += v;
+// byte-wise write of the part of [q, q+l) inside [0, lim); v = bytes lo..hi
+__device__ __forceinline__ void lds_put_clipped(uint8_t* stage, int q, uint64_t lo, uint64_t hi, uint32_t l, int lim) {
+    for (uint32_t m = 0; m < l; m++) {
+        const int y = q + (int)m;
+        if (y >= 0 && y < lim) stage[y] = (uint8_t)lo;
+        lo = (lo >> 8) | (hi << 56);
+        hi >>= 8;
     }
-    __syncthreads();
-    *total = tot;
-    return base + incl - x;
 }
 
-// Load the FSST-8 table of packed symbols into LDS (once per workgroup).
-// Records EBADDICT and zeroes the table when a length is 0 or above 8, in
-// which case no symbol byte is read.
-__device__ void fsst_build_table(Smem& s, const DecodeParams& p) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// Escape classification of one lane's FSST-8 codes.
+//   F   - bit j set when code j is 255 (and inside the tile)
+//   cin - 1 when code 0 is a literal (the run of 255 before the lane is odd)
+// A 255 read where a code is expected is an escape, the code after an escape
+// is a literal.  Inside a run of 255 starting in the "code" state, escapes sit
+// at the run's even offsets.  Runs whose start is at an even bit position are
+// isolated with one addition (the carry clears exactly those runs).
+__device__ __forceinline__ void classify_escapes(uint32_t F, uint32_t cin, uint32_t& esc, uint32_t& lit) {
+    const uint32_t EVEN = 0x55555555u, ODD = 0xaaaaaaaau;
+    const uint32_t S = F & ~(F << 1);                     // run starts
+    uint32_t Se = S & EVEN;                               // runs starting at even positions
+    if (cin) Se &= ~1u;                                   // a run at 0 continues an odd run
+    const uint32_t Re = F & ~(F + Se);                    // bits of even-start runs
+    const uint32_t Ro = F & ~Re;
+    esc = (Re & EVEN) | (Ro & ODD);
+    lit = (esc << 1) | cin;
+}
+
+// expand 4 bits into bit 7 of each byte of a dword
+__device__ __forceinline__ uint32_t bits_to_byte_msb(uint32_t nib) { return (nib * 0x10204081u) & 0x80808080u; }
+
+// --------------------------------------------------------------------------
+// configuration
+// --------------------------------------------------------------------------
+constexpr int kMaxWin = 8;    // staging windows per super-pass, at most (64 KiB / (kWin - 256) + 1 = 5)
+template <int CODEC> struct Cfg;
+template <> struct Cfg<kFsst8> {
+    static constexpr int CB = 1;      // bytes per code
+    static constexpr int CPC = 16;    // codes per 16-byte chunk
+    static constexpr int P = 2;       // chunks per lane
+    static constexpr int CPL = 32;    // codes per lane
+    static constexpr int W = 8;       // bytes written per token (fixed-stride entry)
+    static constexpr int SB = kSbMaxFsst;
+};
+template <> struct Cfg<kOnpair16> {
+    static constexpr int CB = 2;
+    static constexpr int CPC = 8;
+    static constexpr int P = 2;
+    static constexpr int CPL = 16;
+    static constexpr int W = 16;
+    static constexpr int SB = kSbMax;
+};
+
+template <int CODEC> struct SmemT {
+    static constexpr int P = Cfg<CODEC>::P, CPC = Cfg<CODEC>::CPC, SB = Cfg<CODEC>::SB;
+    uint8_t stage[kWin + 16];             // staging window (+16: slack for the drain's 16-byte reads)
+    uint8_t pre8[kWG * P * CPC];          // per code: prefix inside its chunk | escape bit
+    uint32_t lane_pre[kWG];               // per lane: exclusive prefix inside the super-pass
+    uint16_t cbase[kWG * P];              // per chunk: prefix inside its lane
+    int64_t coff[SB + 1];                 // the current tile's code offsets
+    uint64_t fsst_tab[CODEC == kFsst8 ? 256 : 1];
+    uint8_t fsst_len[CODEC == kFsst8 ? 256 : 4];
+    uint32_t wsum[kNWave];
+    uint32_t wpar[kNWave];
+    int64_t nb[2];                        // first / last code offset of the next tile
+    int64_t cursor;
+    uint32_t wbase[kMaxWin + 1];          // staging windows: first output byte of each
+    uint32_t nwin;
+    int32_t next_id;
+};
+
+// Geometry of a tile: its strings, code range and 16-byte chunks.
+struct Geom {
+    int64_t i0;         // first string
+    int64_t a, b;       // code range [a, b) (clamped)
+    int64_t pos0;       // code position of byte 0 of chunk 0 (may be negative)
+    int64_t nchunk;
+    uintptr_t base;     // address of chunk 0
+    int ns;             // strings in the tile
+    int nsp;            // super-passes
+};
+
+template <int CODEC>
+__device__ __forceinline__ Geom make_geom(const DecodeParams& p, int64_t t, int64_t c_first, int64_t c_last) {
+    using C = Cfg<CODEC>;
+    Geom g;
+    g.i0 = t * (int64_t)p.sb;
+    const int64_t i1 = min(g.i0 + (int64_t)p.sb, p.n_strings);
+    g.ns = (int)(i1 - g.i0);
+    g.a = min(max(c_first, (int64_t)0), p.n_codes);
+    g.b = min(max(c_last, g.a), p.n_codes);
+    const uintptr_t lo = (uintptr_t)p.codes;
+    g.base = (lo + (uintptr_t)g.a * C::CB) & ~(uintptr_t)15;
+    g.nchunk = (g.b > g.a) ? (int64_t)((lo + (uintptr_t)g.b * C::CB - g.base + 15) >> 4) : 0;
+    g.nsp = (int)((g.nchunk + (int64_t)kWG * C::P - 1) / ((int64_t)kWG * C::P));
+    g.pos0 = ((int64_t)g.base - (int64_t)lo) / C::CB;
+    return g;
+}
+
+// A thread's share of a tile's code offsets: indices tid + kWG * r.
+template <int CODEC, typename IDX> struct CoffRegs {
+    static constexpr int R = (Cfg<CODEC>::SB + 1 + kWG - 1) / kWG;
+    IDX v[R];
+};
+
+template <int CODEC, typename IDX>
+__device__ __forceinline__ void coff_load(const DecodeParams& p, int64_t t, CoffRegs<CODEC, IDX>& cr) {
+    const int64_t i0 = t * (int64_t)p.sb;
+    const int ns = (int)(min(i0 + (int64_t)p.sb, p.n_strings) - i0);
+    const IDX* src = (const IDX*)p.code_off;
+#pragma unroll
+    for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
+        const int j = (int)threadIdx.x + kWG * r;
+        cr.v[r] = (j <= ns) ? src[i0 + j] : (IDX)0;
+    }
+}
+
+// Broadcast the first and last code offset of tile t from the registers that
+// hold them (one barrier) and return the tile's geometry.
+template <int CODEC, typename S, typename IDX>
+__device__ __forceinline__ Geom geom_from_regs(S& s, const DecodeParams& p, int64_t t,
+                                               const CoffRegs<CODEC, IDX>& cr) {
+    const int64_t i0 = t * (int64_t)p.sb;
+    const int ns = (int)(min(i0 + (int64_t)p.sb, p.n_strings) - i0);
+#pragma unroll
+    for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
+        const int j = (int)threadIdx.x + kWG * r;
+        if (j == 0) s.nb[0] = (int64_t)cr.v[r];
+        if (j == ns) s.nb[1] = (int64_t)cr.v[r];
+    }
+    __syncthreads();
+    const int64_t c0 = uniform64(s.nb[0]), c1 = uniform64(s.nb[1]);
+    return make_geom<CODEC>(p, t, c0, c1);
+}
+
+// Issue the loads of one super-pass's chunks (P per lane).  Chunks that only
+// partly overlap the code buffer (its first and last 16 bytes when they are not
+// 16-byte aligned) are read byte by byte, only inside the buffer.  Fully
+// unrolled, so that the compiler can count the loads in flight.
+template <int CODEC>
+__device__ __forceinline__ void codes_load(const DecodeParams& p, const Geom& g, int sp, uint32_t w[][4]) {
+    using C = Cfg<CODEC>;
+    const uintptr_t lo = (uintptr_t)p.codes, hi = lo + (uintptr_t)p.n_codes * C::CB;
+    const int64_t k0 = (int64_t)sp * kWG * C::P + (int64_t)threadIdx.x * C::P;
+#pragma unroll
+    for (int c = 0; c < C::P; c++) {
+        const int64_t k = k0 + c;
+        const uintptr_t ca = g.base + (uintptr_t)k * 16;
+        w[c][0] = w[c][1] = w[c][2] = w[c][3] = 0;
+        if (k < g.nchunk) {
+            if (ca >= lo && ca + 16 <= hi) {
+                const u32x4 v = __builtin_nontemporal_load((const u32x4*)ca);
+                w[c][0] = v.x; w[c][1] = v.y; w[c][2] = v.z; w[c][3] = v.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const uintptr_t x = ca + j;
+                    if (x >= lo && x < hi) w[c][j >> 2] |= (uint32_t)(*(const uint8_t*)x) << (8 * (j & 3));
+                }
+            }
+        }
+    }
+}
+
+// Per-lane state of one super-pass between its length scan and its emit.
+template <int CODEC> struct Lane {
+    static constexpr int P = Cfg<CODEC>::P;
+    uint32_t w[P][4];      // code bytes, chunk by chunk
+    uint32_t valid;        // bit j: code j inside the tile's code range
+    uint32_t lit;          // FSST-8: literal positions
+    uint32_t tot;          // decoded bytes of the lane
+    uint32_t lane_pre;     // exclusive prefix of the lane inside the super-pass
+    uint32_t lenp[P][Cfg<CODEC>::CPC / 4];   // per-code lengths, packed bytes
+    u32x4 tok[CODEC == kOnpair16 ? Cfg<CODEC>::CPL : 1];   // OnPair-16 token entries
+};
+
+// Load the FSST-8 table into LDS (once per workgroup).  Lengths 0 / above 8
+// record EBADDICT and leave every code invalid (no symbol byte is read).
+// fsst_len[c]: symbol length, 0x80 for codes that are not symbols, 0 for the
+// escape code 255.
+template <typename S>
+__device__ void fsst_build_table(S& s, const DecodeParams& p) {
     const unsigned tid = threadIdx.x;
+    const unsigned c = tid;            // kWG == 256: one code per thread
     uint32_t len = 0;
     bool bad = false;
-    for (unsigned c = tid; c < 256; c += kWG) {
-        if ((int)c < p.n_sym) {
-            len = p.dict_lens[c];
-            bad = (len == 0 || len > 8);
-        }
+    if ((int)c < p.n_sym) {
+        len = p.dict_lens[c];
+        bad = (len == 0 || len > 8);
     }
     bad = __syncthreads_or(bad);
     if (bad) {
         if (tid == 0) record_error(p.err, kRankDict, FD_EBADDICT);
-        for (unsigned c = tid; c < 256; c += kWG) { s.fsst_tab[c] = 0; s.fsst_len[c] = 0; }
+        s.fsst_tab[c] = 0;
+        s.fsst_len[c] = (c == 255) ? 0 : 0x80;
         __syncthreads();
         return;
     }
-    // kWG >= 256: one symbol per thread
-    uint32_t total;
-    uint32_t start = block_excl_scan(tid < 256 ? len : 0u, &total, s.wtmp);
-    if (tid < 256) {
-        uint64_t v = 0;
-        for (uint32_t j = 0; j < len; j++) v |= (uint64_t)p.dict_bytes[start + j] << (8 * j);
-        s.fsst_tab[tid] = v;
-        s.fsst_len[tid] = (uint8_t)len;
-    }
+    const unsigned lane = tid & 63, wv = tid >> 6;
+    const uint32_t incl = wave_incl_scan(len);
+    if (lane == 63) s.wsum[wv] = incl;
+    __syncthreads();
+    uint32_t start = incl - len;
+    for (unsigned i = 0; i < wv; i++) start += s.wsum[i];
+    uint64_t v = 0;
+    for (uint32_t j = 0; j < len; j++) v |= (uint64_t)p.dict_bytes[start + j] << (8 * j);
+    s.fsst_tab[c] = v;
+    s.fsst_len[c] = (c == 255) ? 0 : ((int)c < p.n_sym ? (uint8_t)len : (uint8_t)0x80);
     __syncthreads();
 }
 
-// Read code_offsets[i] (int32 or int64).
-template <typename IDX>
-__device__ __forceinline__ int64_t load_off(const void* off, int64_t i) {
-    return (int64_t)((const IDX*)off)[i];
+// --------------------------------------------------------------------------
+// per-chunk length scans
+// --------------------------------------------------------------------------
+// FSST-8: 16 codes; lit/valid/esc are the chunk's 16 bits.  Writes the
+// per-code prefix bytes (| escape bit) and lengths, returns the chunk total.
+template <typename S>
+__device__ __forceinline__ uint32_t fsst_chunk_lengths(S& s, const uint32_t (&w)[4], uint32_t lit, uint32_t valid,
+                                                       uint32_t esc, uint32_t (&pre)[4], uint32_t (&lenp)[4],
+                                                       uint32_t& bad) {
+    uint32_t ctot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        uint32_t pw = 0, lw = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int j = q * 4 + r;
+            const uint32_t bj = (w[q] >> (8 * r)) & 0xffu;
+            uint32_t v = ((lit >> j) & 1u) ? 1u : (uint32_t)s.fsst_len[bj];
+            v = ((valid >> j) & 1u) ? v : 0u;
+            bad |= (v >> 7) << j;
+            v &= 0x7fu;
+            pw |= ctot << (8 * r);
+            lw |= v << (8 * r);
+            ctot += v;
+        }
+        pre[q] = pw | bits_to_byte_msb((esc >> (q * 4)) & 0xfu);
+        lenp[q] = lw;
+    }
+    return ctot;
 }
 
-// Load a 16-byte chunk at chunk_addr; only bytes inside [lo, hi) (addresses)
-// are read, others are zero.
-__device__ __forceinline__ void load_chunk(uintptr_t chunk_addr, uintptr_t lo, uintptr_t hi, uint32_t w[4]) {
-    if (chunk_addr >= lo && chunk_addr + 16 <= hi) {
-        u32x4 v = __builtin_nontemporal_load((const u32x4*)chunk_addr);
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+// OnPair-16: 8 codes with gathered lengths lv.
+__device__ __forceinline__ uint32_t onpair_chunk_lengths(const uint32_t (&lv)[8], uint32_t valid, uint32_t (&pre)[2],
+                                                         uint32_t (&lenp)[2], uint32_t& bad) {
+    uint32_t ctot = 0;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        uint32_t pw = 0, lw = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int j = q * 4 + r;
+            const uint32_t v = ((valid >> j) & 1u) ? lv[j] : 0u;
+            bad |= (((valid >> j) & 1u) && v == 0u ? 1u : 0u) << j;
+            pw |= ctot << (8 * r);
+            lw |= v << (8 * r);
+            ctot += v;
+        }
+        pre[q] = pw;
+        lenp[q] = lw;
+    }
+    return ctot;
+}
+
+// --------------------------------------------------------------------------
+// length scan of one super-pass (codes already in L.w).  Writes pre8, cbase,
+// lane_pre and the staging windows to LDS and returns the super-pass total.
+// `carry` is the FSST-8 escape parity entering the super-pass (updated).
+// Windows are runs of whole lanes: lane l belongs to window lane_pre / K with
+// K = kWin - (largest lane output), so no lane straddles a window edge.
+// --------------------------------------------------------------------------
+template <int CODEC, typename S>
+__device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const Geom& g, int sp, Lane<CODEC>& L,
+                                            uint32_t& carry, bool gather_tokens,
+                                            const __amdgpu_buffer_rsrc_t& r_len,
+                                            const __amdgpu_buffer_rsrc_t& r_tok) {
+    using C = Cfg<CODEC>;
+    constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
+    const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t k0 = (int64_t)sp * kWG * P + (int64_t)tid * P;
+    const int64_t q0 = g.pos0 + k0 * CPC;
+    {
+        const int64_t lo = min(max(g.a - q0, (int64_t)0), (int64_t)CPL);
+        const int64_t hi = min(max(g.b - q0, (int64_t)0), (int64_t)CPL);
+        const uint32_t mhi = hi >= 32 ? 0xffffffffu : ((1u << (uint32_t)hi) - 1u);
+        const uint32_t mlo = lo >= 32 ? 0xffffffffu : ((1u << (uint32_t)lo) - 1u);
+        L.valid = mhi & ~mlo;
+    }
+    uint32_t tot = 0, bad = 0;
+    uint32_t pre8w[P][CPC / 4];
+    uint16_t cb[P];
+    if constexpr (CODEC == kFsst8) {
+        uint32_t F = 0;
+#pragma unroll
+        for (int c = 0; c < P; c++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                // bytes equal to 0xFF -> bit 7 of each byte, then packed to 4 bits
+                const uint32_t x = L.w[c][q];
+                const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
+                const uint32_t nib = ((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu;
+                F |= nib << (c * 16 + q * 4);
+            }
+        F &= L.valid;
+        const bool all_ff = (F == 0xffffffffu);
+        const uint32_t trail = __clz(~F);                       // 255s at the top of the lane
+        const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
+        const uint64_t m = M & ((1ull << lane) - 1ull);
+        if (lane == 0) s.wpar[wv] = M ? (1u | ((uint32_t)((T >> (63 - __clzll(M))) & 1ull) << 1)) : 0u;
+        __syncthreads();
+        uint32_t cw = carry, cout = carry;
+#pragma unroll
+        for (int i = 0; i < kNWave; i++) {
+            const uint32_t v = s.wpar[i];
+            if ((v & 1u) && i < (int)wv) cw = v >> 1;
+            if (v & 1u) cout = v >> 1;
+        }
+        carry = cout;
+        const uint32_t cin = m ? (uint32_t)((T >> (63 - __clzll(m))) & 1ull) : cw;
+        uint32_t esc;
+        classify_escapes(F, cin, esc, L.lit);
+        L.lit &= L.valid;
+#pragma unroll
+        for (int c = 0; c < P; c++) {
+            cb[c] = (uint16_t)tot;
+            tot += fsst_chunk_lengths(s, L.w[c], L.lit >> (16 * c), L.valid >> (16 * c), esc >> (16 * c), pre8w[c],
+                                      L.lenp[c], bad);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     } else {
-        w[0] = w[1] = w[2] = w[3] = 0;
-        for (int j = 0; j < 16; j++) {
-            uintptr_t a = chunk_addr + j;
-            if (a >= lo && a < hi) w[j >> 2] |= (uint32_t)(*(const uint8_t*)a) << (8 * (j & 3));
+#pragma unroll
+        for (int c = 0; c < P; c++) {
+            uint32_t lv[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t cj = (L.w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                lv[j] = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
+                if (gather_tokens) L.tok[c * 8 + j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, cj << 4, 0, 0);
+            }
+            uint32_t cbad = 0;
+            cb[c] = (uint16_t)tot;
+            tot += onpair_chunk_lengths(lv, L.valid >> (8 * c), pre8w[c], L.lenp[c], cbad);
+            bad |= cbad << (8 * c);
         }
     }
+    const uint64_t errkey = bad ? data_error_key(q0 + __builtin_ctz(bad), FD_EBADCODE) : ~0ull;
+    wave_record_error(p.err, errkey);
+    L.tot = tot;
+    const uint32_t incl = wave_incl_scan(tot);
+    if (lane == 63) s.wsum[wv] = incl;
+    __builtin_memcpy(&s.pre8[tid * P * CPC], pre8w, P * CPC);
+#pragma unroll
+    for (int c = 0; c < P; c++) s.cbase[tid * P + c] = cb[c];
+    __syncthreads();
+    uint32_t basew = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < kNWave; i++) {
+        const uint32_t v = s.wsum[i];
+        basew += (i < (int)wv) ? v : 0u;
+        total += v;
+    }
+    L.lane_pre = basew + incl - tot;
+    s.lane_pre[tid] = L.lane_pre;
+    __syncthreads();
+    // staging windows: window of a lane = lane_pre / K; first lanes record bases
+    {
+        constexpr uint32_t K = kWin - C::CPL * C::W;   // a lane writes at most CPL * W bytes
+        const uint32_t wl = L.lane_pre / K;
+        const uint32_t wprev = tid ? s.lane_pre[tid - 1] / K : 0xffffffffu;
+        if (wl != wprev) s.wbase[wl] = L.lane_pre;
+        if (tid == kWG - 1) {
+            s.nwin = wl + 1;
+            s.wbase[wl + 1] = total;
+        }
+    }
+    __syncthreads();
+    return uniform32(total);
+}
+
+// --------------------------------------------------------------------------
+// assembly of one window into s.stage.  Lanes of other windows return.  The
+// result does not depend on the output position, so it can overlap the
+// look-back.
+// --------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], uint32_t lit, const uint32_t (&lenp)[4],
+                                                int& q, int qend) {
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const uint32_t l = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        const uint32_t bj = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        uint64_t v = s.fsst_tab[bj];
+        if ((lit >> j) & 1u) v = bj;
+        if (q + 8 <= qend) {
+            // the whole entry; the excess lands inside the lane's own range and is
+            // overwritten by its next tokens
+            lds_put8(&s.stage[q], v);
+        } else {
+            // the lane's last bytes: exact length (l in 0..7)
+            const uint32_t o4 = l & 4u, o2 = l & 6u;
+            if (l & 4u) lds_put4(&s.stage[q], (uint32_t)v);
+            if (l & 2u) lds_put2(&s.stage[q + (int)o4], (uint32_t)(v >> (8 * o4)));
+            if (l & 1u) s.stage[q + (int)o2] = (uint8_t)(v >> (8 * o2));
+        }
+        q += (int)l;
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const uint32_t (&lenp)[2], int& q, int qend) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const uint32_t l = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        const u32x4 v = tok[j];
+        if (q + 16 <= qend) {
+            lds_put16(&s.stage[q], v);
+        } else {
+            const uint64_t lo = ((uint64_t)v.y << 32) | v.x, hi = ((uint64_t)v.w << 32) | v.z;
+            const uint32_t o8 = l & 8u, o4 = l & 12u, o2 = l & 14u;   // l in 0..15
+            const uint64_t r = o8 ? hi : lo;
+            if (l & 8u) lds_put8(&s.stage[q], lo);
+            if (l & 4u) lds_put4(&s.stage[q + (int)o8], (uint32_t)r);
+            const uint64_t r2 = (l & 4u) ? (r >> 32) : r;
+            if (l & 2u) lds_put2(&s.stage[q + (int)o4], (uint32_t)r2);
+            const uint64_t r3 = (l & 2u) ? (r2 >> 16) : r2;
+            if (l & 1u) s.stage[q + (int)o2] = (uint8_t)r3;
+        }
+        q += (int)l;
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int CODEC, typename S>
+__device__ __forceinline__ void assemble(S& s, const Lane<CODEC>& L, int win) {
+    using C = Cfg<CODEC>;
+    constexpr int P = C::P;
+    constexpr uint32_t K = kWin - C::CPL * C::W;
+    if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
+    int q = (int)(L.lane_pre - s.wbase[win]);
+    const int qend = q + (int)L.tot;
+    // opaque copies: keeps the compiler from hoisting every per-code predicate
+    // out of the window loop (they would all stay live)
+    uint32_t lit = L.lit, lenp[P][C::CPC / 4], w[P][4];
+    asm volatile("" : "+v"(lit));
+#pragma unroll
+    for (int c = 0; c < P; c++) {
+#pragma unroll
+        for (int i = 0; i < C::CPC / 4; i++) { lenp[c][i] = L.lenp[c][i]; asm volatile("" : "+v"(lenp[c][i])); }
+#pragma unroll
+        for (int i = 0; i < 4; i++) { w[c][i] = L.w[c][i]; asm volatile("" : "+v"(w[c][i])); }
+    }
+#pragma unroll
+    for (int c = 0; c < P; c++) {
+        if constexpr (CODEC == kFsst8) fsst_chunk_emit(s, w[c], lit >> (16 * c), lenp[c], q, qend);
+        else onpair_chunk_emit(s, &L.tok[c * 8], lenp[c], q, qend);
+    }
+}
+
+// Drain window `win` (super-pass output bytes [wbase[win], wbase[win+1]))
+// to the output, whose super-pass output starts at position O: aligned 16-byte
+// nontemporal stores read from the staging at the output's alignment, byte
+// stores for the partial head / tail chunks; nothing at or past out_cap.
+template <typename S>
+__device__ __forceinline__ void drain(S& s, const DecodeParams& p, int64_t O, int win) {
+    const int b0 = (int)s.wbase[win];
+    const int len = (int)s.wbase[win + 1] - b0;
+    const int64_t X = O + b0;                                     // output position of stage[0]
+    const int shift = (int)(((uintptr_t)p.out + (uintptr_t)X) & 15u);
+    const int64_t cap_rel = p.out_cap - X;
+    const int hi_all = (int)min((int64_t)len, max(cap_rel, (int64_t)0));
+    const int nch = (shift + len + 15) >> 4;
+    for (int c = threadIdx.x; c < nch; c += kWG) {
+        const int s0 = c * 16 - shift;
+        const int lo = max(s0, 0), hi = min(s0 + 16, hi_all);
+        if (lo == s0 && hi == s0 + 16) {
+            u32x4 v;
+            __builtin_memcpy(&v, &s.stage[s0], 16);
+            __builtin_nontemporal_store(v, (u32x4*)(p.out + X + s0));
+        } else {
+            for (int y = lo; y < hi; y++) p.out[X + y] = s.stage[y];
+        }
+    }
+}
+
+// Arrow offsets of the strings of the tile that start in super-pass sp (output
+// position O), and the FSST-8 dangling-escape check of the strings that end in
+// it.
+template <int CODEC, typename IDX, typename S>
+__device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom& g, int sp, int64_t O) {
+    using C = Cfg<CODEC>;
+    constexpr int P = C::P, CPC = C::CPC, CB = C::CB, SPC = kWG * C::P;
+    const uintptr_t codes_lo = (uintptr_t)p.codes;
+    const int64_t k_lo = (int64_t)sp * SPC, k_hi = k_lo + SPC;
+    for (int j = threadIdx.x; j < g.ns; j += kWG) {
+        const int64_t st = min(max(s.coff[j], g.a), g.b);
+        if (st < g.b) {
+            const int64_t k = (int64_t)((codes_lo + (uintptr_t)st * CB - g.base) >> 4);
+            if (k >= k_lo && k < k_hi) {
+                const int kk = (int)(k - k_lo);
+                const int jj = (int)(st - (g.pos0 + k * CPC));
+                uint32_t e = s.pre8[kk * CPC + jj];
+                if constexpr (CODEC == kFsst8) e &= 0x7fu;
+                const int64_t val = O + (int64_t)s.lane_pre[kk / P] + (int64_t)s.cbase[kk] + (int64_t)e;
+                ((IDX*)p.out_off)[g.i0 + j] = (IDX)val;
+            }
+        }
+        if constexpr (CODEC == kFsst8) {
+            const int64_t en = min(max(s.coff[j + 1], g.a), g.b);
+            if (en > st) {
+                const int64_t last = en - 1;
+                const int64_t k = (int64_t)((codes_lo + (uintptr_t)last * CB - g.base) >> 4);
+                if (k >= k_lo && k < k_hi) {
+                    const int kk = (int)(k - k_lo);
+                    const int jj = (int)(last - (g.pos0 + k * CPC));
+                    if (s.pre8[kk * CPC + jj] & 0x80u)
+                        atomicMin(p.err, (unsigned long long)data_error_key(last, FD_EESCAPE));
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// two-level decoupled look-back (wave 0 only).  Block kBlk tiles: a tile sums
+// the aggregates of the earlier tiles of its block, the last tile of a block
+// publishes the block aggregate, and block totals are combined by a decoupled
+// look-back over earlier blocks.  Split in two halves so that the loads of the
+// first round overlap the assembly.
+// --------------------------------------------------------------------------
+struct LookBack {
+    uint64_t in_v;      // this lane's in-block aggregate (first round)
+    uint64_t blk_v;     // this lane's block state (first round)
+};
+
+__device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
+    const unsigned lane = threadIdx.x & 63;
+    const int64_t blk = t >> kBlkShift;
+    const int jt = (int)(t & (kBlk - 1));
+    if (lane == 0)
+        __hip_atomic_store(&p.tagg[t], (unsigned long long)(kFlagAgg | A), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lb.in_v = kFlagAgg;
+    if ((int)lane < jt)
+        lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t idx = blk - 1 - (int64_t)lane;
+    lb.blk_v = kFlagIncl;
+    if (idx >= 0) lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Completes the look-back; returns the exclusive prefix of tile t.
+__device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64_t t, uint64_t A, LookBack lb) {
+    const unsigned lane = threadIdx.x & 63;
+    const int64_t blk = t >> kBlkShift;
+    const int jt = (int)(t & (kBlk - 1));
+    bool fail = false;
+    uint32_t spins = 0;
+    uint64_t inb = 0;
+    for (;;) {
+        if (__ballot((lb.in_v & kFlagMask) == 0) == 0) {
+            inb = wave_sum_u64(lb.in_v & kValueMask);
+            break;
+        }
+        if (++spins >= kSpinLimit) { fail = true; break; }
+        __builtin_amdgcn_s_sleep(1);
+        if ((int)lane < jt)
+            lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (jt == kBlk - 1 && lane == 0)
+        __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagAgg | (inb + A)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t bb = 0;
+    int64_t j = blk - 1;
+    uint64_t v = lb.blk_v;
+    while (j >= 0 && !fail) {
+        const uint64_t fl = v & kFlagMask;
+        const uint64_t incl = __ballot(fl == kFlagIncl);
+        const uint64_t empty = __ballot(fl == 0);
+        const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 63;
+        const uint64_t need = (first >= 63) ? ~0ull : ((2ull << first) - 1ull);
+        if (empty & need) {
+            if (++spins >= kSpinLimit) { fail = true; break; }
+            __builtin_amdgcn_s_sleep(1);
+        } else {
+            bb += wave_sum_u64(((int)lane <= first) ? (v & kValueMask) : 0ull);
+            if (incl) break;
+            j -= 64;
+        }
+        const int64_t idx = j - (int64_t)lane;
+        v = kFlagIncl;
+        if (idx >= 0) v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (fail && lane == 0) record_error(p.err, kRankInternal, FD_EHIP);
+    const uint64_t excl = bb + inb;
+    if (jt == kBlk - 1 && lane == 0)
+        __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagIncl | (excl + A)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
 }
 
 // --------------------------------------------------------------------------
 // the decode kernel
 // --------------------------------------------------------------------------
-// Per-pass register state of one lane.
-template <int CODEC> struct Lane {
-    uint32_t w[4];        // the 16 code bytes
-    uint32_t valid;       // bit j: code j inside the tile's code range
-    uint32_t lit_in;      // FSST-8: the lane starts on a literal
-    uint32_t tot;         // decoded bytes of the lane
-    uint32_t pre[Codec<CODEC>::CPL];
-    uint32_t esc;         // FSST-8: bit j set when code j is an escape
-    uint32_t lane_pre;    // exclusive prefix of the lane inside the pass
-    uint4 tok[Codec<CODEC>::CPL == 8 ? 8 : 1];  // OnPair-16 token entries
-    uint32_t tlen[Codec<CODEC>::CPL];
-};
-
 template <int CODEC, typename IDX, int MODE>
 __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
-    using C = Codec<CODEC>;
-    constexpr int CPL = C::CPL;
-    constexpr int CB = C::CB;
-    __shared__ Smem s;
-    const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    using C = Cfg<CODEC>;
+    constexpr int P = C::P;
+    __shared__ SmemT<CODEC> s;
+    const unsigned tid = threadIdx.x, wv = tid >> 6;
 
-    if (CODEC == kFsst8) fsst_build_table(s, p);
+    if constexpr (CODEC == kFsst8) fsst_build_table(s, p);
 
-    const uintptr_t codes_lo = (uintptr_t)p.codes;
-    const uintptr_t codes_hi = codes_lo + (uintptr_t)p.n_codes * CB;
-    const uintptr_t out_addr = (uintptr_t)p.out;
+    // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
+    const __amdgpu_buffer_rsrc_t r_len = make_rsrc(CODEC == kOnpair16 ? (const void*)p.tok_len : (const void*)p.codes,
+                                                   CODEC == kOnpair16 ? 65536u : 0u);
+    const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes,
+                                                   CODEC == kOnpair16 ? 65536u * 16u : 0u);
 
-    for (;;) {
-        // ---------------- acquire a tile ----------------
-        if (tid == 0) s.bcast[0] = (int64_t)atomicAdd(&p.counters[0], 1u);
+    // ---- prologue: the first two tiles of this workgroup ----
+    if (tid == 0) {
+        s.nb[0] = (int64_t)atomicAdd(&p.counters[0], 1u);
+        s.nb[1] = (int64_t)atomicAdd(&p.counters[0], 1u);
+    }
+    __syncthreads();
+    int64_t t = uniform64(s.nb[0]), tn = uniform64(s.nb[1]);
+    __syncthreads();
+    CoffRegs<CODEC, IDX> cr;
+    Geom g{};
+    uint32_t wc[P][4];
+    if (t < p.n_tiles) {
+        coff_load<CODEC, IDX>(p, t, cr);
+        g = geom_from_regs<CODEC>(s, p, t, cr);
+        codes_load<CODEC>(p, g, 0, wc);
+    }
+
+    while (t < p.n_tiles) {
+        // (A) the tile's code offsets into LDS, validation, id of the tile after tn
+        // (the atomic's result is only needed at the end of the iteration)
+        uint32_t nid = 0;
+        if (tid == 0) nid = atomicAdd(&p.counters[0], 1u);
+        int64_t cur_reg = 0;
+#pragma unroll
+        for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
+            const int j = (int)tid + kWG * r;
+            if (j <= g.ns) s.coff[j] = (int64_t)cr.v[r];
+        }
+        if constexpr (MODE == kModeExpand) {
+            if (tid == 0) cur_reg = (int64_t)p.tagg[t];
+        }
         __syncthreads();
-        const int64_t t = s.bcast[0];
-        __syncthreads();
-        if (t >= p.n_tiles) break;
-
-        const int64_t i0 = t * (int64_t)p.sb;
-        const int64_t i1 = min(i0 + (int64_t)p.sb, p.n_strings);
-        const int ns = (int)(i1 - i0);
-        for (int j = tid; j <= ns; j += kWG) s.coff[j] = load_off<IDX>(p.code_off, i0 + j);
-        __syncthreads();
-        // validate the offsets of this tile
         {
             bool bad = false;
-            for (int j = tid; j < ns; j += kWG) bad |= s.coff[j + 1] < s.coff[j];
+            for (int j = tid; j < g.ns; j += kWG) bad |= s.coff[j + 1] < s.coff[j];
             if (tid == 0) {
                 if (t == 0 && s.coff[0] < 0) bad = true;
-                if (i1 == p.n_strings && s.coff[ns] > p.n_codes) bad = true;
+                if (g.i0 + g.ns == p.n_strings && s.coff[g.ns] > p.n_codes) bad = true;
             }
             bad = __syncthreads_or(bad);
             if (bad && tid == 0) record_error(p.err, kRankOffsets, FD_EOFFSETS);
         }
-        const int64_t a = min(max(s.coff[0], (int64_t)0), p.n_codes);
-        const int64_t b = min(max(s.coff[ns], a), p.n_codes);
-        // 16-byte-aligned chunks covering code positions [a, b)
-        const uintptr_t base = (codes_lo + (uintptr_t)a * CB) & ~(uintptr_t)15;
-        const int64_t nchunk = (b > a) ? (int64_t)((codes_lo + (uintptr_t)b * CB - base + 15) >> 4) : 0;
-        const int npass = (int)((nchunk + kWG - 1) / kWG);
-        // code position of byte 0 of chunk 0 (may be negative before the buffer)
-        const int64_t pos0 = ((int64_t)base - (int64_t)codes_lo) / CB;
+        const bool has_next = tn < p.n_tiles;
+        if (has_next) coff_load<CODEC, IDX>(p, tn, cr);       // next tile's offsets (in flight)
 
-        // one pass: load + lengths + scan.  Returns the pass total.
-        auto pass_lengths = [&](int pass, uint32_t& carry, Lane<CODEC>& L) -> uint32_t {
-            const int64_t k = (int64_t)pass * kWG + tid;
-            const uintptr_t caddr = base + (uintptr_t)k * 16;
-            const int64_t cpos = pos0 + k * CPL;
-            L.valid = 0;
-            if (k < nchunk) {
-                load_chunk(caddr, codes_lo, codes_hi, L.w);
-#pragma unroll
-                for (int j = 0; j < CPL; j++) {
-                    const int64_t q = cpos + j;
-                    if (q >= a && q < b) L.valid |= 1u << j;
-                }
-            } else {
-                L.w[0] = L.w[1] = L.w[2] = L.w[3] = 0;
-            }
-            uint64_t errkey = ~0ull;
-            L.tot = 0;
-            L.esc = 0;
-            if constexpr (CODEC == kFsst8) {
-                // ---- escape parity: does this lane start on a literal? ----
-                uint32_t ffm = 0;
-#pragma unroll
-                for (int j = 0; j < 16; j++) ffm |= (byte_of(L.w, j) == 0xffu ? 1u : 0u) << j;
-                ffm &= L.valid;
-                const bool all_ff = (ffm == 0xffffu);
-                const uint32_t trail = __clz(~(ffm << 16));        // trailing run of 255 (from code 15 down)
-                const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
-                const uint64_t m = M & ((1ull << lane) - 1ull);
-                uint32_t wave_last = 0;                          // summary: bit0 has, bit1 parity
-                if (M) wave_last = 1u | ((uint32_t)((T >> (63 - __clzll(M))) & 1ull) << 1);
-                if (lane == 0) s.wtmp2[wv] = wave_last;
-                __syncthreads();
-                uint32_t c = carry;                              // parity carried into this wave
-                for (int i = 0; i < (int)wv; i++) {
-                    uint32_t v = s.wtmp2[i];
-                    if (v & 1u) c = v >> 1;
-                }
-                uint32_t cin = m ? (uint32_t)((T >> (63 - __clzll(m))) & 1ull) : c;
-                // carry out of the pass for the next pass
-                uint32_t cout = carry;
-                for (int i = 0; i < kNWave; i++) {
-                    uint32_t v = s.wtmp2[i];
-                    if (v & 1u) cout = v >> 1;
-                }
-                __syncthreads();
-                carry = cout;
-                L.lit_in = cin;
-                // ---- lengths ----
-                bool lit = cin != 0;
-#pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    L.pre[j] = L.tot;
-                    const uint32_t cj = byte_of(L.w, j);
-                    if (!((L.valid >> j) & 1u)) {
-                        lit = false;
-                    } else if (lit) {
-                        L.tot += 1;
-                        lit = false;
-                    } else if (cj == 255u) {
-                        L.esc |= 1u << j;
-                        lit = true;
-                    } else {
-                        const uint32_t l = s.fsst_len[cj];
-                        L.tot += l;
-                        if (l == 0 && errkey == ~0ull) errkey = data_error_key(cpos + j, FD_EBADCODE);
-                    }
-                }
-            } else {
-                // ---- OnPair-16: gather lengths and token entries ----
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const uint32_t cj = (L.w[j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                    if ((L.valid >> j) & 1u) {
-                        L.tlen[j] = p.tok_len[cj];
-                        L.tok[j] = p.tok16[cj];
-                    } else {
-                        L.tlen[j] = 0;
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    L.pre[j] = L.tot;
-                    L.tot += L.tlen[j];
-                    if (((L.valid >> j) & 1u) && L.tlen[j] == 0 && errkey == ~0ull)
-                        errkey = data_error_key(cpos + j, FD_EBADCODE);
-                }
-            }
-            wave_record_error(p.err, errkey);
-            uint32_t total;
-            L.lane_pre = block_excl_scan(L.tot, &total, s.wtmp);
-            return total;
-        };
-
-        int64_t cursor = 0;
-        uint64_t tile_total = 0;
+        // One super-pass (the common case): lengths, look-back issued, window 0
+        // assembled, next tile prefetched, look-back completed, drain, offsets.
+        // Several super-passes: the lengths of all of them first (tile total,
+        // blocking look-back), then each super-pass again with its emit.
         Lane<CODEC> L;
+        int64_t nc0 = 0, nc1 = 0;      // first / last code offset of the next tile
+        uint32_t wn[P][4];
         uint32_t carry = 0;
-        uint32_t first_total = 0;
-
-        auto publish_and_lookback = [&](uint64_t T) -> int64_t {
-            // returns the exclusive prefix of this tile
-            if constexpr (MODE == kModeLookback) {
-                if (wv == 0) {
-                    int64_t excl = 0;
-                    if (t == 0) {
-                        if (lane == 0)
-                            __hip_atomic_store(&p.tstate[0], (unsigned long long)(kFlagIncl | T), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        if (lane == 0)
-                            __hip_atomic_store(&p.tstate[t], (unsigned long long)(kFlagAgg | T), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                        int64_t j = t - 1;
-                        uint32_t spins = 0;
-                        for (;;) {
-                            const int64_t idx = j - (int64_t)lane;
-                            uint64_t v = kFlagIncl;
-                            if (idx >= 0)
-                                v = __hip_atomic_load(&p.tstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            const uint64_t flag = v & kFlagMask;
-                            const uint64_t incl = __ballot(flag == kFlagIncl);
-                            const uint64_t empty = __ballot(flag == 0);
-                            const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 63;
-                            const uint64_t need = (first >= 63) ? ~0ull : ((2ull << first) - 1ull);
-                            if (empty & need) {
-                                // bounded wait: a predecessor that never publishes is an
-                                // internal error, reported instead of hanging the device
-                                if (++spins < kSpinLimit) {
-                                    __builtin_amdgcn_s_sleep(1);
-                                    continue;
-                                }
-                                if (lane == 0) record_error(p.err, kRankInternal, FD_EHIP);
-                                break;
-                            }
-                            const uint64_t mine = ((int)lane <= first) ? (v & kValueMask) : 0ull;
-                            excl += (int64_t)wave_sum_u64(mine);
-                            if (incl) break;
-                            j -= 64;
-                        }
-                        if (lane == 0)
-                            __hip_atomic_store(&p.tstate[t], (unsigned long long)(kFlagIncl | (uint64_t)(excl + T)),
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    if (lane == 0) s.bcast[1] = excl;
-                }
-                __syncthreads();
-                int64_t r = s.bcast[1];
-                __syncthreads();
-                return r;
-            } else if constexpr (MODE == kModeTotals) {
-                if (tid == 0) p.tstate[t] = T;
-                return 0;
+        int64_t cursor = 0;
+        uint64_t tile_total = 0, sp_base = 0;
+        const int nsp = g.nsp;
+        const int iters = nsp <= 1 ? 1 : 2 * nsp;
+        bool prefetched = false;
+        for (int it = 0; it < iters; it++) {
+            const bool counting = nsp > 1 && it < nsp;
+            const int sp = nsp <= 1 ? 0 : (counting ? it : it - nsp);
+            if (nsp > 1 && it == nsp) carry = 0;
+            if (sp == 0) {
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) L.w[c][i] = wc[c][i];
             } else {
-                return (int64_t)p.tstate[t];   // exclusive cursors precomputed
+                codes_load<CODEC>(p, g, sp, L.w);
             }
-        };
-
-        if (npass <= 1) {
-            if (npass == 1) first_total = pass_lengths(0, carry, L);
-            tile_total = first_total;
-            cursor = publish_and_lookback(tile_total);
-        } else {
-            uint32_t c2 = 0;
-            for (int ps = 0; ps < npass; ps++) tile_total += pass_lengths(ps, c2, L);
-            cursor = publish_and_lookback(tile_total);
+            uint32_t tsp = 0;
+            if (nsp >= 1) tsp = lengths<CODEC>(s, p, g, sp, L, carry, !counting, r_len, r_tok);
+            if (counting) {
+                tile_total += tsp;
+                if (it == nsp - 1) {
+                    if constexpr (MODE == kModeTotals) {
+                        if (tid == 0) p.tagg[t] = tile_total;
+                    } else if constexpr (MODE == kModeLookback) {
+                        if (wv == 0) {
+                            LookBack lb;
+                            lookback_issue(p, t, tile_total, lb);
+                            const uint64_t ex = lookback_finish(p, t, tile_total, lb);
+                            if (tid == 0) s.cursor = (int64_t)ex;
+                        }
+                    } else {
+                        if (tid == 0) s.cursor = cur_reg;
+                    }
+                    __syncthreads();
+                    cursor = uniform64(s.cursor);
+                }
+                continue;
+            }
+            const bool single = nsp <= 1;
+            LookBack lb{};
+            if (single) {
+                tile_total = tsp;
+                if constexpr (MODE == kModeTotals) {
+                    if (tid == 0) p.tagg[t] = tsp;
+                } else if constexpr (MODE == kModeLookback) {
+                    if (wv == 0) lookback_issue(p, t, tsp, lb);
+                }
+            }
+            if constexpr (MODE != kModeTotals) {
+                if (nsp >= 1) assemble<CODEC>(s, L, 0);
+            }
+            if (!prefetched) {
+                prefetched = true;
+                if (has_next) {
+                    const Geom gn = geom_from_regs<CODEC>(s, p, tn, cr);     // one barrier
+                    nc0 = uniform64(s.nb[0]);
+                    nc1 = uniform64(s.nb[1]);
+                    codes_load<CODEC>(p, gn, 0, wn);
+                }
+            }
+            if (single) {
+                if constexpr (MODE == kModeLookback) {
+                    if (wv == 0) {
+                        const uint64_t ex = lookback_finish(p, t, tsp, lb);
+                        if (tid == 0) s.cursor = (int64_t)ex;
+                    }
+                } else if constexpr (MODE == kModeExpand) {
+                    if (tid == 0) s.cursor = cur_reg;
+                }
+            }
+            __syncthreads();
+            if constexpr (MODE != kModeTotals) {
+                if (single) cursor = uniform64(s.cursor);
+                if (nsp >= 1) {
+                    const int64_t O = cursor + (int64_t)sp_base;
+                    const int nwin = (int)uniform32(s.nwin);
+                    for (int win = 0; win < nwin; win++) {
+                        if (win > 0) {
+                            __syncthreads();
+                            assemble<CODEC>(s, L, win);
+                            __syncthreads();
+                        }
+                        drain(s, p, O, win);
+                    }
+                    offsets<CODEC, IDX>(s, p, g, sp, O);
+                    __syncthreads();
+                }
+            }
+            sp_base += tsp;
         }
 
         if constexpr (MODE != kModeTotals) {
-            uint64_t pass_base = 0;
-            carry = 0;
-            for (int ps = 0; ps < npass; ps++) {
-                uint32_t ptotal = first_total;
-                if (npass > 1) ptotal = pass_lengths(ps, carry, L);
-                // keep per-code prefixes for the offsets of strings starting here
-                {
-                    uint32_t packed[CPL / 4];
-#pragma unroll
-                    for (int q = 0; q < CPL / 4; q++) {
-                        uint32_t v = 0;
-#pragma unroll
-                        for (int r = 0; r < 4; r++) {
-                            const int j = 4 * q + r;
-                            uint32_t e = L.pre[j];
-                            if constexpr (CODEC == kFsst8) e |= ((L.esc >> j) & 1u) << 7;
-                            v |= e << (8 * r);
-                        }
-                        packed[q] = v;
-                    }
-                    __builtin_memcpy(&s.pre8[tid * CPL], packed, CPL);
-                    s.lane_pre[tid] = L.lane_pre;
-                }
-                // ---- emit into staging windows + drain ----
-                const int64_t O = cursor + (int64_t)pass_base;       // pass output position
-                const uint32_t shift = (uint32_t)((out_addr + (uintptr_t)O) & 15u);
-                const int nwin = (int)((ptotal + shift + kWin - 1) / kWin);
-                for (int win = 0; win < nwin; win++) {
-                    const int64_t wbase = (int64_t)win * kWin;
-                    int64_t q = (int64_t)shift + L.lane_pre - wbase;   // staging index of the lane's first byte
-                    const int64_t qend = q + L.tot;
-                    if (qend > 0 && q < kWin) {
-                        const int64_t lim = qend < kWin ? qend : (int64_t)kWin;
-                        if constexpr (CODEC == kFsst8) {
-                            bool lit = L.lit_in != 0;
-#pragma unroll
-                            for (int j = 0; j < 16; j++) {
-                                const uint32_t cj = byte_of(L.w, j);
-                                if (!((L.valid >> j) & 1u)) {
-                                    lit = false;
-                                } else if (lit) {
-                                    if (q >= 0 && q < kWin) s.stage[q] = (uint8_t)cj;
-                                    q += 1;
-                                    lit = false;
-                                } else if (cj == 255u) {
-                                    lit = true;
-                                } else {
-                                    const uint64_t v = s.fsst_tab[cj];
-                                    const uint32_t l = s.fsst_len[cj];
-                                    if (q >= 0 && q + 8 <= lim) {
-                                        lds_put8(&s.stage[q], v);
-                                    } else if (q >= 0 && q + l <= (int64_t)kWin) {
-                                        lds_put_exact8(&s.stage[q], v, l);
-                                    } else {
-                                        for (uint32_t m = 0; m < l; m++) {
-                                            const int64_t y = q + m;
-                                            if (y >= 0 && y < kWin) s.stage[y] = (uint8_t)(v >> (8 * m));
-                                        }
-                                    }
-                                    q += l;
-                                }
-                            }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 8; j++) {
-                                const uint32_t l = L.tlen[j];
-                                if (l) {
-                                    const uint4 v = L.tok[j];
-                                    if (q >= 0 && q + 16 <= lim) {
-                                        lds_put16(&s.stage[q], v);
-                                    } else if (q >= 0 && q + l <= (int64_t)kWin) {
-                                        lds_put_exact16(&s.stage[q], v, l);
-                                    } else {
-                                        const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
-                                        for (uint32_t m = 0; m < l; m++) {
-                                            const int64_t y = q + m;
-                                            if (y >= 0 && y < kWin) s.stage[y] = (uint8_t)byte_of(vv, (int)m);
-                                        }
-                                    }
-                                    q += l;
-                                }
-                            }
-                        }
-                    }
-                    __syncthreads();
-                    // drain staging [s_lo, s_hi) to out[(O - shift + wbase) + s]
-                    {
-                        const int64_t s_lo = (win == 0) ? (int64_t)shift : 0;
-                        const int64_t s_hi = min((int64_t)kWin, (int64_t)shift + (int64_t)ptotal - wbase);
-                        const int64_t obase = O - (int64_t)shift + wbase;  // output position of staging index 0
-                        const int64_t cap_hi = p.out_cap - obase;          // staging index limit by capacity
-                        const int64_t hi_all = min(s_hi, cap_hi);
-                        const int nch = (int)((s_hi + 15) >> 4);
-                        for (int c = tid; c < nch; c += kWG) {
-                            const int64_t lo = max((int64_t)c * 16, s_lo);
-                            const int64_t hi = min((int64_t)c * 16 + 16, hi_all);
-                            if (lo == (int64_t)c * 16 && hi == (int64_t)c * 16 + 16) {
-                                u32x4 v;
-                                __builtin_memcpy(&v, &s.stage[c * 16], 16);
-                                __builtin_nontemporal_store(v, (u32x4*)(p.out + obase + c * 16));
-                            } else {
-                                for (int64_t y = lo; y < hi; y++) p.out[obase + y] = s.stage[y];
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-                // ---- offsets of strings starting in this pass; dangling escapes ----
-                {
-                    const int64_t k_lo = (int64_t)ps * kWG, k_hi = k_lo + kWG;
-                    for (int j = tid; j < ns; j += kWG) {
-                        const int64_t st = min(max(s.coff[j], a), b);
-                        if (st < b) {
-                            const int64_t k = (int64_t)((codes_lo + (uintptr_t)st * CB - base) >> 4);
-                            if (k >= k_lo && k < k_hi) {
-                                const int li = (int)(k - k_lo);
-                                const int jj = (int)(st - (pos0 + k * CPL));
-                                uint32_t e = s.pre8[li * CPL + jj];
-                                if constexpr (CODEC == kFsst8) e &= 0x7fu;
-                                const int64_t val = O + (int64_t)s.lane_pre[li] + (int64_t)e;
-                                ((IDX*)p.out_off)[i0 + j] = (IDX)val;
-                            }
-                        }
-                        if constexpr (CODEC == kFsst8) {
-                            const int64_t en = min(max(s.coff[j + 1], a), b);
-                            if (en > st) {
-                                const int64_t last = en - 1;
-                                const int64_t k = (int64_t)((codes_lo + (uintptr_t)last * CB - base) >> 4);
-                                if (k >= k_lo && k < k_hi) {
-                                    const int li = (int)(k - k_lo);
-                                    const int jj = (int)(last - (pos0 + k * CPL));
-                                    if (s.pre8[li * CPL + jj] & 0x80u)
-                                        atomicMin(p.err, (unsigned long long)data_error_key(last, FD_EESCAPE));
-                                }
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-                pass_base += ptotal;
+            const int64_t endv = cursor + (int64_t)tile_total;
+            for (int j = tid; j < g.ns; j += kWG) {
+                if (min(max(s.coff[j], g.a), g.b) >= g.b) ((IDX*)p.out_off)[g.i0 + j] = (IDX)endv;
             }
-            // strings that start at the end of the tile's code range; the final offset
-            {
-                const int64_t endv = cursor + (int64_t)tile_total;
-                for (int j = tid; j < ns; j += kWG) {
-                    const int64_t st = min(max(s.coff[j], a), b);
-                    if (st >= b) ((IDX*)p.out_off)[i0 + j] = (IDX)endv;
-                }
-                if (tid == 0) {
-                    if (i1 == p.n_strings) ((IDX*)p.out_off)[p.n_strings] = (IDX)endv;
-                    if (sizeof(IDX) == 4 && endv > (int64_t)INT32_MAX) record_error(p.err, kRankOverflow, FD_EOVERFLOW);
-                    if (endv > p.out_cap) record_error(p.err, kRankCapacity, FD_ECAPACITY);
-                }
+            if (tid == 0) {
+                if (g.i0 + g.ns == p.n_strings) ((IDX*)p.out_off)[p.n_strings] = (IDX)endv;
+                if (sizeof(IDX) == 4 && endv > (int64_t)INT32_MAX) record_error(p.err, kRankOverflow, FD_EOVERFLOW);
+                if (endv > p.out_cap) record_error(p.err, kRankCapacity, FD_ECAPACITY);
             }
         }
+        if (tid == 0) s.next_id = (int32_t)nid;
         __syncthreads();
+        g = make_geom<CODEC>(p, tn, nc0, nc1);
+        t = tn;
+        tn = (int64_t)(int32_t)uniform32((uint32_t)s.next_id);
+#pragma unroll
+        for (int c = 0; c < P; c++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) wc[c][i] = wn[c][i];
     }
 
-    // ---------------- completion: the last workgroup publishes the status ----------------
+    // the last workgroup to finish publishes the status
     if (MODE != kModeTotals) {
         __threadfence();
         if (tid == 0) {
-            unsigned prev = atomicAdd(&p.counters[1], 1u);
+            const unsigned prev = atomicAdd(&p.counters[1], 1u);
             if (prev == gridDim.x - 1) {
                 __threadfence();
-                unsigned long long e = __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                int st = (e == ~0ull) ? FD_OK : (int)(e & 15ull);
+                const unsigned long long e = __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int st = (e == ~0ull) ? FD_OK : (int)(e & 15ull);
                 if (p.status) *p.status = st;
                 if (p.status2) *p.status2 = st;
             }
@@ -640,18 +939,18 @@ __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
 // --------------------------------------------------------------------------
 // workspace reset, cursor scan (three-phase mode), OnPair dictionary repack
 // --------------------------------------------------------------------------
-__global__ void k_reset(unsigned long long* err, unsigned* counters, unsigned long long* tstate, int64_t n) {
+__global__ void k_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         if (err) *err = ~0ull;
         counters[0] = 0;
         counters[1] = 0;
     }
-    for (int64_t k = i; k < n; k += (int64_t)gridDim.x * blockDim.x) tstate[k] = 0;
+    for (int64_t k = i; k < n; k += (int64_t)gridDim.x * blockDim.x) z[k] = 0;
 }
 
 // Single-workgroup exclusive scan of tile totals into tile cursors (in place).
-__global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* tstate, int64_t n) {
+__global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* v, int64_t n) {
     __shared__ uint64_t s_w[16];
     __shared__ uint64_t s_carry;
     const unsigned tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -659,10 +958,10 @@ __global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* tstate
     __syncthreads();
     for (int64_t base = 0; base < n; base += 1024) {
         const int64_t i = base + tid;
-        uint64_t x = i < n ? tstate[i] : 0;
+        const uint64_t x = i < n ? v[i] : 0;
         uint64_t incl = x;
         for (int d = 1; d < 64; d <<= 1) {
-            uint64_t y = __shfl_up(incl, d, 64);
+            const uint64_t y = __shfl_up(incl, d, 64);
             if (lane >= (unsigned)d) incl += y;
         }
         if (lane == 63) s_w[w] = incl;
@@ -672,7 +971,7 @@ __global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* tstate
             if (k < (int)w) pre += s_w[k];
             tot += s_w[k];
         }
-        if (i < n) tstate[i] = pre + incl - x;
+        if (i < n) v[i] = pre + incl - x;
         __syncthreads();
         if (tid == 0) s_carry += tot;
         __syncthreads();
@@ -681,9 +980,8 @@ __global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* tstate
 
 // Repack an OnPair dictionary (packed bytes + lengths) into fixed 16-byte
 // entries and a full 65,536-entry length table (0 for codes >= n_tok).
-// Launched with 256 workgroups of 256 threads; workgroup g handles codes
-// [256 g, 256 g + 256).  Records EBADDICT (and writes nothing else) when a
-// length is 0 or above 16.
+// 256 workgroups of 256 threads; workgroup g handles codes [256 g, 256 g + 256).
+// A length of 0 or above 16 records EBADDICT and leaves every code invalid.
 __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int32_t n_tok,
                                                          uint4* tok16, uint8_t* tok_len, unsigned long long* err,
                                                          int* bad_flag) {
@@ -691,17 +989,15 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
     __shared__ uint64_t s_red[4];
     const unsigned tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int32_t c0 = (int32_t)blockIdx.x * 256;
-    // validation of all lengths by every workgroup (64 KB read, cached)
     bool bad = false;
     uint64_t before = 0;
     for (int32_t c = tid; c < n_tok; c += 256) {
-        uint32_t l = lens[c];
+        const uint32_t l = lens[c];
         bad |= (l == 0 || l > 16);
         if (c < c0) before += l;
     }
     bad = __syncthreads_or(bad);
     if (bad) {
-        // every code becomes invalid (length 0); no token byte is read
         tok16[c0 + tid] = make_uint4(0, 0, 0, 0);
         tok_len[c0 + tid] = 0;
         if (blockIdx.x == 0 && tid == 0) {
@@ -712,12 +1008,14 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
     }
     before = wave_sum_u64(before);
     if (lane == 0) s_red[w] = before;
-    __syncthreads();
-    const uint64_t base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
     const int32_t c = c0 + (int32_t)tid;
     const uint32_t l = (c < n_tok) ? lens[c] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(l, &total, s_w);
+    const uint32_t incl = wave_incl_scan(l);
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    const uint64_t base = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    uint32_t ex = incl - l;
+    for (unsigned i = 0; i < w; i++) ex += s_w[i];
     uint32_t v[4] = {0, 0, 0, 0};
     const uint8_t* src = bytes + base + ex;
     for (uint32_t j = 0; j < l; j++) v[j >> 2] |= (uint32_t)src[j] << (8 * (j & 3));
@@ -741,41 +1039,42 @@ static int occupancy_of() {
     return nb < 1 ? 1 : nb;
 }
 
+#define FD_FOR_ALL(X)                                                                                  \
+    X(kFsst8, int32_t, kModeLookback) X(kFsst8, int64_t, kModeLookback) X(kOnpair16, int32_t, kModeLookback) \
+    X(kOnpair16, int64_t, kModeLookback) X(kFsst8, int32_t, kModeTotals) X(kFsst8, int64_t, kModeTotals)     \
+    X(kOnpair16, int32_t, kModeTotals) X(kOnpair16, int64_t, kModeTotals) X(kFsst8, int32_t, kModeExpand)    \
+    X(kFsst8, int64_t, kModeExpand) X(kOnpair16, int32_t, kModeExpand) X(kOnpair16, int64_t, kModeExpand)
+
 int decode_occupancy(int codec, int index_bits, int mode) {
-#define OCC(C, I, M) if (codec == C && index_bits == (sizeof(I) * 8) && mode == M) return occupancy_of<C, I, M>();
-    OCC(kFsst8, int32_t, kModeLookback) OCC(kFsst8, int64_t, kModeLookback)
-    OCC(kOnpair16, int32_t, kModeLookback) OCC(kOnpair16, int64_t, kModeLookback)
-    OCC(kFsst8, int32_t, kModeTotals) OCC(kFsst8, int64_t, kModeTotals)
-    OCC(kOnpair16, int32_t, kModeTotals) OCC(kOnpair16, int64_t, kModeTotals)
-    OCC(kFsst8, int32_t, kModeExpand) OCC(kFsst8, int64_t, kModeExpand)
-    OCC(kOnpair16, int32_t, kModeExpand) OCC(kOnpair16, int64_t, kModeExpand)
+#define OCC(C, I, M) \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8) && mode == M) return occupancy_of<C, I, M>();
+    FD_FOR_ALL(OCC)
 #undef OCC
     return 1;
 }
 
 hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams& p, int grid, hipStream_t st) {
-#define L1(C, I, M) if (codec == C && index_bits == (int)(sizeof(I) * 8) && mode == M) return launch_one<C, I, M>(p, grid, st);
-    L1(kFsst8, int32_t, kModeLookback) L1(kFsst8, int64_t, kModeLookback)
-    L1(kOnpair16, int32_t, kModeLookback) L1(kOnpair16, int64_t, kModeLookback)
-    L1(kFsst8, int32_t, kModeTotals) L1(kFsst8, int64_t, kModeTotals)
-    L1(kOnpair16, int32_t, kModeTotals) L1(kOnpair16, int64_t, kModeTotals)
-    L1(kFsst8, int32_t, kModeExpand) L1(kFsst8, int64_t, kModeExpand)
-    L1(kOnpair16, int32_t, kModeExpand) L1(kOnpair16, int64_t, kModeExpand)
+#define L1(C, I, M) \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8) && mode == M) return launch_one<C, I, M>(p, grid, st);
+    FD_FOR_ALL(L1)
 #undef L1
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* tstate, int64_t n,
+int chunks_per_lane(int codec) { return codec == kFsst8 ? Cfg<kFsst8>::P : Cfg<kOnpair16>::P; }
+int codes_per_chunk(int codec) { return codec == kFsst8 ? Cfg<kFsst8>::CPC : Cfg<kOnpair16>::CPC; }
+
+hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n,
                         hipStream_t st) {
     int64_t blocks = (n + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_reset, dim3((unsigned)blocks), dim3(256), 0, st, err, counters, tstate, n);
+    hipLaunchKernelGGL(k_reset, dim3((unsigned)blocks), dim3(256), 0, st, err, counters, z, n);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_totals(unsigned long long* tstate, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, tstate, n);
+hipError_t launch_scan_totals(unsigned long long* v, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, v, n);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def test_host_only_entry_points(fdlib):
     with pytest.raises(fd.DecodeError):
         fd.workspace_size("fsst8", -1, 10)
     with pytest.raises(fd.DecodeError):
-        fd.workspace_size("fsst8", 10, 10, {"mode": 0, "strings_per_tile": 513, "grid": 0, "reserved": 0})
+        fd.workspace_size("fsst8", 10, 10, {"mode": 0, "strings_per_tile": 257, "grid": 0, "reserved": 0})
 
 
 def test_argument_errors_enqueue_nothing(fdlib):

@@ -55,7 +55,7 @@ def test_random_full_dictionary(datagen_mod):
 # tuning: modes, tiny tiles (long look-back chains), small grids
 # --------------------------------------------------------------------------- #
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("sb", [0, 1, 3, 17, 512])
+@pytest.mark.parametrize("sb", [0, 1, 3, 17, 256])
 @pytest.mark.parametrize("grid", [0, 1, 7])
 def test_tuning_fsst(datagen_mod, mode, sb, grid):
     c = datagen_mod.fsst_small(seed=4, n_strings=3000)
