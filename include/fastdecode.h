@@ -195,6 +195,58 @@ fd_status fd_decode_ex(const fd_dict *dict, const void *codes, int64_t n_codes, 
                        void *workspace, size_t workspace_bytes, int32_t *status, unsigned flags,
                        const fd_tuning *tuning, void *hip_stream);
 
+/* ------------------------------------------------------------------------- */
+/* Batched decode                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* One column of a batch: the arguments of fd_decode.  dict is a prepared
+ * dictionary (its codec is the column's codec); columns may share one. */
+typedef struct fd_column {
+    const fd_dict *dict;
+    const void *codes;
+    int64_t n_codes;
+    const void *code_offsets;
+    int32_t index_bits;
+    int64_t n_strings;
+    void *out_offsets;
+    uint8_t *out_bytes;
+    int64_t out_capacity;
+} fd_column;
+
+#define FD_GRAPH 2u   /* batch_decode: replay a cached HIP graph of the batch */
+
+/* Workspace bytes for batch_decode of these columns with this tuning (NULL =
+ * the autotuner's largest candidate, enough for any tuning it picks). */
+fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const fd_tuning *tuning, size_t *bytes);
+
+/* Decode n_cols columns of any codecs and offset widths in one stream
+ * submission: columns of one codec and offset width form a group, each group
+ * runs as one persistent kernel in which every workgroup takes tiles of the
+ * group's columns, in column order, from one counter (each column keeps its
+ * own tile cursors and error word), and a last kernel collects the statuses.
+ * The byte semantics per column are those of fd_decode; out_bytes and
+ * out_offsets of different columns must not overlap.
+ *   cols, n_cols      host array of column descriptions (0 <= n_cols <= 65536);
+ *                     the description is read during the call only.
+ *   tuning            NULL: tiles are sized by a built-in autotuner that
+ *                     times candidate tile sizes on this batch the first time
+ *                     a batch of its shape is seen and caches the winner;
+ *                     else mode must be 0 and strings_per_tile / grid apply
+ *                     to every column / group (0 = automatic).
+ *   status            device int32[n_cols + 1] or NULL (required with
+ *                     FD_ASYNC): status[c] = the status of column c,
+ *                     status[n_cols] = the first non-OK status in column order.
+ *   flags             FD_ASYNC as for fd_decode; FD_GRAPH records the whole
+ *                     submission as a HIP graph the first time and replays
+ *                     the cached graph when the same columns, workspace,
+ *                     status pointer and tuning come back (the graph reads the
+ *                     column table from library-owned pinned memory).
+ * Returns the first non-OK status in column order (or FD_OK with FD_ASYNC).
+ * Host-visible errors of any column return FD_EINVAL before anything is
+ * enqueued.  Calls sharing a workspace must be ordered. */
+fd_status batch_decode(const fd_column *cols, int32_t n_cols, const fd_tuning *tuning, void *workspace,
+                       size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

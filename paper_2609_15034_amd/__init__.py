@@ -10,7 +10,9 @@ Names follow the C ABI:
   * ``fsst_decode`` / ``onpair_decode``  - one column, raw dictionary;
   * ``Dict`` (fd_dict) + ``decode_into`` - one column, prepared dictionary;
   * ``decode``                           - convenience: sizes and allocates the
-                                           outputs (two device passes).
+                                           outputs (two device passes);
+  * ``batch_decode``                     - many columns, one submission (or one
+                                           cached HIP graph), autotuned tiles.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ FSST8 = 1
 ONPAIR16 = 2
 CODECS = {"fsst8": FSST8, "onpair16": ONPAIR16}
 ASYNC = 1
+GRAPH = 2
 
 OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS, EHIP, ENOMEM = range(10)
 STATUS_NAMES = ["FD_OK", "FD_EINVAL", "FD_EBADCODE", "FD_EESCAPE", "FD_ECAPACITY", "FD_EOVERFLOW", "FD_EBADDICT",
@@ -45,6 +48,13 @@ class Tuning(ctypes.Structure):
     """fd_tuning: mode (0 single pass / 1 three phases), strings_per_tile, grid."""
     _fields_ = [("mode", ctypes.c_int32), ("strings_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class Column(ctypes.Structure):
+    """fd_column: one column of a batch (device pointers, prepared dictionary)."""
+    _fields_ = [("dict", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("n_codes", ctypes.c_int64),
+                ("code_offsets", ctypes.c_void_p), ("index_bits", ctypes.c_int32), ("n_strings", ctypes.c_int64),
+                ("out_offsets", ctypes.c_void_p), ("out_bytes", ctypes.c_void_p), ("out_capacity", ctypes.c_int64)]
 
 
 _lib = None
@@ -86,6 +96,10 @@ def lib():
     L.fd_decode.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, P]
     L.fd_decode_ex.restype = ctypes.c_int
     L.fd_decode_ex.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, ctypes.POINTER(Tuning), P]
+    L.fd_batch_workspace_size.restype = ctypes.c_int
+    L.fd_batch_workspace_size.argtypes = [ctypes.POINTER(Column), I32, ctypes.POINTER(Tuning), ctypes.POINTER(S)]
+    L.batch_decode.restype = ctypes.c_int
+    L.batch_decode.argtypes = [ctypes.POINTER(Column), I32, ctypes.POINTER(Tuning), P, S, P, U, P]
     _lib = L
     return L
 
@@ -247,3 +261,40 @@ def decode(d: Dict, codes, code_off, tuning=None, stream=None):
     if st != OK:
         raise DecodeError(st)
     return out_off, out
+
+
+# --------------------------------------------------------------------------- #
+# batches
+# --------------------------------------------------------------------------- #
+def make_columns(cols):
+    """fd_column array from a list of (Dict, codes, code_off, out_off, out_bytes)
+    tuples of device tensors (out_bytes may be None for capacity 0)."""
+    arr = (Column * max(len(cols), 1))()
+    for i, (d, codes, code_off, out_off, out_bytes) in enumerate(cols):
+        arr[i] = Column(d.handle.value, codes.data_ptr(), codes.numel(), code_off.data_ptr(), _index_bits(code_off),
+                        code_off.numel() - 1, out_off.data_ptr(), out_bytes.data_ptr() if out_bytes is not None else 0,
+                        out_bytes.numel() if out_bytes is not None else 0)
+    return arr
+
+
+def batch_workspace_size(cols, tuning=None) -> int:
+    """fd_batch_workspace_size for a list of column tuples (see make_columns)."""
+    arr = make_columns(cols)
+    out = ctypes.c_size_t(0)
+    tu = Tuning(**tuning) if isinstance(tuning, dict) else tuning
+    st = lib().fd_batch_workspace_size(arr, len(cols), ctypes.byref(tu) if tu is not None else None,
+                                       ctypes.byref(out))
+    if st:
+        raise DecodeError(st, "fd_batch_workspace_size")
+    return int(out.value)
+
+
+def batch_decode(cols, workspace, status=None, tuning=None, async_=False, graph=False, stream=None) -> int:
+    """batch_decode over a list of column tuples (Dict, codes, code_off, out_off,
+    out_bytes); `status` (device int32, len(cols) + 1) receives the per-column
+    statuses and the first error.  Returns the fd_status (FD_OK when enqueued
+    with async_=True)."""
+    arr = make_columns(cols)
+    flags = (ASYNC if async_ else 0) | (GRAPH if graph else 0)
+    return lib().batch_decode(arr, len(cols), _tuning(tuning), _ptr(workspace), workspace.numel(), _ptr(status),
+                              flags, _stream_handle(stream))

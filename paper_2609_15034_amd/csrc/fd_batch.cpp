@@ -1,0 +1,419 @@
+// Batched decode: many columns of mixed codecs and offset widths in one stream
+// submission (optionally one HIP graph), with an autotuner for tile sizes.
+//
+// A batch is split into groups of one codec and offset width.  Each group runs
+// as one persistent kernel over a device table of per-column parameters; its
+// tiles are numbered consecutively over its columns and taken from one
+// counter, so every workgroup works through the group's columns in order and
+// small columns cost no launch of their own.  Each column keeps its own tile
+// cursors (look-back state) and error word; a last one-workgroup kernel turns
+// the error words into per-column statuses.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <list>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "fastdecode.h"
+#include "fd_internal.h"
+
+using namespace fd;
+
+namespace {
+
+constexpr size_t kBHdr = 256;          // group tile counters (8 bytes each) and the status word
+constexpr size_t kBOffStatus = 128;
+constexpr int kMaxGroups = 4;          // (codec, offset width) pairs
+constexpr int32_t kMaxCols = 65536;
+
+// Candidate tile sizes of the autotuner: fractions (percent) of the automatic
+// strings-per-tile of each column (smaller tiles: more tiles and more
+// parallel look-back, larger: fewer tiles and less overhead per byte).
+constexpr int kScales[] = {100, 70, 45};
+constexpr int kNumScales = 3;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Group {
+    int codec = 0, index_bits = 0;
+    std::vector<int32_t> cols;   // column indices (caller order)
+    int64_t total = 0;           // tiles
+    int grid = 0;
+};
+
+struct BatchPlan {
+    std::vector<int64_t> sb, n_tiles;     // per column
+    std::vector<size_t> off_state;        // per column: tile aggregates, then block states
+    std::vector<Group> groups;
+    size_t states_end = 0;                // [0, states_end) is zeroed per call
+    size_t off_errs = 0, off_table = 0, table_bytes = 0, bytes = 0;
+};
+
+int group_of(int codec, int index_bits) { return (codec == FD_FSST8 ? 0 : 2) + (index_bits == 64 ? 1 : 0); }
+
+// Host-visible checks of one column (those of the single-column entry points).
+bool column_ok(const fd_column& c) {
+    if (!c.dict) return false;
+    const fd_codec codec = c.dict->codec;
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16) return false;
+    if (c.index_bits != 32 && c.index_bits != 64) return false;
+    if (c.n_strings < 0 || c.n_codes < 0 || c.out_capacity < 0) return false;
+    if (c.n_strings > (int64_t)1 << 40 || c.n_codes > (int64_t)1 << 40) return false;
+    if (!c.code_offsets || !c.out_offsets) return false;
+    if (c.n_codes > 0 && !c.codes) return false;
+    if (c.out_capacity > 0 && !c.out_bytes) return false;
+    if (codec == FD_ONPAIR16 && c.codes && ((uintptr_t)c.codes & 1)) return false;
+    if (c.index_bits == 32 &&
+        (c.n_codes > INT32_MAX || ((uintptr_t)c.code_offsets & 3) || ((uintptr_t)c.out_offsets & 3)))
+        return false;
+    if (c.index_bits == 64 && (((uintptr_t)c.code_offsets & 7) || ((uintptr_t)c.out_offsets & 7))) return false;
+    return true;
+}
+
+// Plan of a batch for one tile-size choice: `sb_fixed` > 0 sets every column's
+// strings per tile, else `scale` percent of the automatic value.
+bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, int grid_req, BatchPlan* pl) {
+    pl->sb.assign(n, 0);
+    pl->n_tiles.assign(n, 0);
+    pl->off_state.assign(n, 0);
+    pl->groups.assign(kMaxGroups, Group());
+    size_t off = kBHdr;
+    for (int32_t c = 0; c < n; c++) {
+        const fd_column& col = cols[c];
+        const fd_codec codec = col.dict->codec;
+        const int64_t sb_max = codec == FD_FSST8 ? kSbMaxFsst : kSbMax;
+        int64_t sb = sb_fixed;
+        if (sb > sb_max) return false;
+        if (sb == 0) {
+            sb = auto_strings_per_tile(codec, col.n_codes, col.n_strings) * scale / 100;
+            sb = std::max<int64_t>(1, std::min(sb, sb_max));
+        }
+        const int64_t tiles = col.n_strings == 0 ? 1 : (col.n_strings + sb - 1) / sb;
+        const int64_t tiles_pad = (tiles + kBlk - 1) / kBlk * kBlk;
+        pl->sb[c] = sb;
+        pl->n_tiles[c] = tiles;
+        pl->off_state[c] = off;
+        off += (size_t)tiles_pad * 8 + (size_t)(tiles_pad / kBlk) * 8;
+        Group& g = pl->groups[group_of((int)codec, col.index_bits)];
+        g.codec = (int)codec;
+        g.index_bits = col.index_bits;
+        g.cols.push_back(c);
+        g.total += tiles;
+    }
+    pl->states_end = off;
+    pl->off_errs = align_up(off, 256);
+    pl->off_table = align_up(pl->off_errs + (size_t)n * 8, 256);
+    // the table: every group's DecodeParams (group order), then every group's first-tile array
+    size_t tb = (size_t)n * sizeof(DecodeParams);
+    for (const Group& g : pl->groups) tb += (g.cols.size() + (g.cols.empty() ? 0 : 1)) * sizeof(int64_t);
+    pl->table_bytes = tb;
+    pl->bytes = align_up(pl->off_table + tb, 256);
+    for (Group& g : pl->groups) {
+        if (g.cols.empty()) continue;
+        int grid = grid_req ? grid_req : resident_grid_batch(g.codec, g.index_bits);
+        if ((int64_t)grid > g.total) grid = (int)g.total;
+        g.grid = grid < 1 ? 1 : grid;
+    }
+    return true;
+}
+
+// Fill the host image of the device table.
+void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* ws, uint8_t* host) {
+    DecodeParams* dp = (DecodeParams*)host;
+    int64_t* ft = (int64_t*)(host + (size_t)n * sizeof(DecodeParams));
+    int k = 0;
+    for (int gi = 0; gi < kMaxGroups; gi++) {
+        const Group& g = pl.groups[gi];
+        if (g.cols.empty()) continue;
+        int64_t first = 0;
+        for (int32_t c : g.cols) {
+            const fd_column& col = cols[c];
+            DecodeParams p;
+            memset(&p, 0, sizeof(p));
+            p.codes = (const uint8_t*)col.codes;
+            p.n_codes = col.n_codes;
+            p.code_off = col.code_offsets;
+            p.n_strings = col.n_strings;
+            p.dict_bytes = col.dict->bytes;
+            p.dict_lens = col.dict->lens;
+            p.n_sym = col.dict->n;
+            p.tok16 = col.dict->tok16;
+            p.tok_len = col.dict->tok_len;
+            p.out_off = col.out_offsets;
+            p.out = col.out_bytes;
+            p.out_cap = col.out_capacity;
+            p.n_tiles = pl.n_tiles[c];
+            p.sb = (int32_t)pl.sb[c];
+            p.err = (unsigned long long*)(ws + pl.off_errs) + c;
+            p.counters = nullptr;
+            p.tagg = (unsigned long long*)(ws + pl.off_state[c]);
+            const int64_t tiles_pad = (pl.n_tiles[c] + kBlk - 1) / kBlk * kBlk;
+            p.bstate = p.tagg + tiles_pad;
+            dp[k++] = p;
+            *ft++ = first;
+            first += pl.n_tiles[c];
+        }
+        *ft++ = first;
+    }
+}
+
+// Enqueue a planned batch whose table image is in pinned memory `host`.
+hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* ws, const uint8_t* host,
+                   int32_t* status, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(ws + pl.off_table, host, pl.table_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    unsigned long long* errs = (unsigned long long*)(ws + pl.off_errs);
+    e = launch_batch_reset((unsigned long long*)ws, (int64_t)(pl.states_end / 8), errs, n, st);
+    if (e != hipSuccess) return e;
+    const DecodeParams* dp = (const DecodeParams*)(ws + pl.off_table);
+    const int64_t* ft = (const int64_t*)(ws + pl.off_table + (size_t)n * sizeof(DecodeParams));
+    int k = 0;
+    for (int gi = 0; gi < kMaxGroups; gi++) {
+        const Group& g = pl.groups[gi];
+        if (g.cols.empty()) continue;
+        unsigned* ctr = (unsigned*)(ws + 8 * gi);
+        e = launch_decode_batch(g.codec, g.index_bits, dp + k, ft, (int32_t)g.cols.size(), g.total, ctr, g.grid, st);
+        if (e != hipSuccess) return e;
+        k += (int)g.cols.size();
+        ft += g.cols.size() + 1;
+    }
+    (void)cols;
+    return launch_batch_status(errs, n, status, (int32_t*)(ws + kBOffStatus), st);
+}
+
+// ---- pinned staging for the table image (reused once its last copy is done) ----
+struct Staging {
+    uint8_t* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+// ---- caches: autotuned choice per batch shape, graphs per exact batch ----
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint8_t* pinned = nullptr;
+};
+
+std::mutex g_bmu;
+Staging g_stage[64];
+std::unordered_map<uint64_t, int> g_tuned;                  // shape -> scale (percent)
+std::list<std::pair<uint64_t, GraphEntry>> g_graphs;        // most recent first
+constexpr size_t kMaxGraphs = 16;
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+int log2_bucket(int64_t x) { return x <= 0 ? 0 : 64 - __builtin_clzll((uint64_t)x); }
+
+uint64_t shape_key(const fd_column* cols, int32_t n, int dev) {
+    uint64_t h = mix(0x5eed, (uint64_t)n);
+    h = mix(h, (uint64_t)dev);
+    for (int32_t c = 0; c < n; c++) {
+        h = mix(h, (uint64_t)cols[c].dict->codec);
+        h = mix(h, (uint64_t)cols[c].index_bits);
+        h = mix(h, (uint64_t)log2_bucket(cols[c].n_strings));
+        h = mix(h, (uint64_t)log2_bucket(cols[c].n_codes));
+    }
+    return h;
+}
+
+uint64_t exact_key(const fd_column* cols, int32_t n, const void* ws, size_t ws_bytes, const int32_t* status,
+                   int64_t sb_fixed, int scale, int grid, int dev) {
+    uint64_t h = mix(0x9a9a, (uint64_t)n);
+    const uint64_t* w = (const uint64_t*)cols;
+    const size_t nw = (size_t)n * sizeof(fd_column) / 8;
+    for (size_t i = 0; i < nw; i++) h = mix(h, w[i]);
+    h = mix(h, (uint64_t)(uintptr_t)ws);
+    h = mix(h, (uint64_t)ws_bytes);
+    h = mix(h, (uint64_t)(uintptr_t)status);
+    h = mix(h, (uint64_t)sb_fixed);
+    h = mix(h, (uint64_t)scale);
+    h = mix(h, (uint64_t)grid);
+    return mix(h, (uint64_t)dev);
+}
+
+// Plan and enqueue one batch decode (no graph), staging the table in pinned memory.
+fd_status run_once(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* ws, int32_t* status,
+                   hipStream_t st, int dev) {
+    Staging& sg = g_stage[dev];
+    if (sg.pending) {
+        if (hipEventSynchronize(sg.done) != hipSuccess) return FD_EHIP;
+        sg.pending = false;
+    }
+    if (sg.cap < pl.table_bytes) {
+        if (sg.buf) (void)hipHostFree(sg.buf);
+        sg.buf = nullptr;
+        sg.cap = 0;
+        const size_t cap = std::max<size_t>(pl.table_bytes, 64 * 1024);
+        if (hipHostMalloc((void**)&sg.buf, cap, hipHostMallocDefault) != hipSuccess) return FD_ENOMEM;
+        sg.cap = cap;
+    }
+    if (!sg.done && hipEventCreateWithFlags(&sg.done, hipEventDisableTiming) != hipSuccess) return FD_EHIP;
+    fill_table(cols, n, pl, ws, sg.buf);
+    if (enqueue(cols, n, pl, ws, sg.buf, status, st) != hipSuccess) return FD_EHIP;
+    if (hipEventRecord(sg.done, st) != hipSuccess) return FD_EHIP;
+    sg.pending = true;
+    return FD_OK;
+}
+
+// Autotune: time every candidate scale on this batch, keep the fastest.
+fd_status autotune(const fd_column* cols, int32_t n, uint8_t* ws, size_t ws_bytes, hipStream_t st, int dev,
+                   int* best_scale) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return FD_EHIP;
+    float best = 1e30f;
+    *best_scale = kScales[0];
+    fd_status rc = FD_OK;
+    for (int i = 0; i < kNumScales && rc == FD_OK; i++) {
+        BatchPlan pl;
+        if (!make_plan(cols, n, 0, kScales[i], 0, &pl) || pl.bytes > ws_bytes) continue;
+        float ms_sum = 0.f;
+        for (int rep = 0; rep < 3 && rc == FD_OK; rep++) {      // one warm-up, two timed
+            if (hipEventRecord(a, st) != hipSuccess) { rc = FD_EHIP; break; }
+            rc = run_once(cols, n, pl, ws, nullptr, st, dev);
+            if (rc != FD_OK) break;
+            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) { rc = FD_EHIP; break; }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, a, b) != hipSuccess) { rc = FD_EHIP; break; }
+            if (rep > 0) ms_sum += ms;
+        }
+        if (rc == FD_OK && ms_sum < best) {
+            best = ms_sum;
+            *best_scale = kScales[i];
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+}
+
+fd_status read_status(uint8_t* ws, hipStream_t st) {
+    if (hipStreamSynchronize(st) != hipSuccess) return FD_EHIP;
+    int32_t hs = 0;
+    if (hipMemcpy(&hs, ws + kBOffStatus, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) return FD_EHIP;
+    return (fd_status)hs;
+}
+
+}  // namespace
+
+extern "C" {
+
+fd_status fd_batch_workspace_size(const fd_column* cols, int32_t n_cols, const fd_tuning* tuning, size_t* bytes) {
+    if (!bytes || n_cols < 0 || n_cols > kMaxCols || (n_cols > 0 && !cols)) return FD_EINVAL;
+    for (int32_t c = 0; c < n_cols; c++)
+        if (!column_ok(cols[c])) return FD_EINVAL;
+    if (tuning && (tuning->mode != 0 || tuning->strings_per_tile < 0 || tuning->grid < 0)) return FD_EINVAL;
+    size_t need = kBHdr;
+    for (int i = 0; i < (tuning ? 1 : kNumScales); i++) {
+        BatchPlan pl;
+        if (!make_plan(cols, n_cols, tuning ? tuning->strings_per_tile : 0, tuning ? 100 : kScales[i], 1, &pl))
+            return FD_EINVAL;
+        need = std::max(need, pl.bytes);
+    }
+    *bytes = need;
+    return FD_OK;
+}
+
+fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* tuning, void* workspace,
+                       size_t workspace_bytes, int32_t* status, unsigned flags, void* hip_stream) {
+    try {
+        if (n_cols < 0 || n_cols > kMaxCols || (n_cols > 0 && !cols)) return FD_EINVAL;
+        if (!workspace || ((uintptr_t)workspace & 255)) return FD_EINVAL;
+        if ((flags & FD_ASYNC) && !status) return FD_EINVAL;
+        if (flags & ~(FD_ASYNC | FD_GRAPH)) return FD_EINVAL;
+        if (tuning && (tuning->mode != 0 || tuning->strings_per_tile < 0 || tuning->grid < 0)) return FD_EINVAL;
+        for (int32_t c = 0; c < n_cols; c++)
+            if (!column_ok(cols[c])) return FD_EINVAL;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return FD_EHIP;
+        hipStream_t st = (hipStream_t)hip_stream;
+        uint8_t* ws = (uint8_t*)workspace;
+        if (n_cols == 0) {
+            if (status && hipMemsetAsync(status, 0, sizeof(int32_t), st) != hipSuccess) return FD_EHIP;
+            if (!(flags & FD_ASYNC) && hipStreamSynchronize(st) != hipSuccess) return FD_EHIP;
+            return FD_OK;
+        }
+
+        std::lock_guard<std::mutex> lk(g_bmu);
+        // the tile-size choice
+        int64_t sb_fixed = tuning ? tuning->strings_per_tile : 0;
+        int grid = tuning ? tuning->grid : 0;
+        int scale = 100;
+        if (!tuning) {
+            const uint64_t sk = shape_key(cols, n_cols, dev);
+            auto it = g_tuned.find(sk);
+            if (it != g_tuned.end()) {
+                scale = it->second;
+            } else {
+                const fd_status rc = autotune(cols, n_cols, ws, workspace_bytes, st, dev, &scale);
+                if (rc != FD_OK) return rc;
+                g_tuned[sk] = scale;
+            }
+        }
+        BatchPlan pl;
+        if (!make_plan(cols, n_cols, sb_fixed, scale, grid, &pl)) return FD_EINVAL;
+        if (workspace_bytes < pl.bytes) return FD_EINVAL;
+
+        if (flags & FD_GRAPH) {
+            const uint64_t key = exact_key(cols, n_cols, workspace, workspace_bytes, status, sb_fixed, scale, grid, dev);
+            GraphEntry* ge = nullptr;
+            for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
+                if (it->first == key) {
+                    g_graphs.splice(g_graphs.begin(), g_graphs, it);
+                    ge = &g_graphs.front().second;
+                    break;
+                }
+            }
+            if (!ge) {
+                GraphEntry ne;
+                if (hipHostMalloc((void**)&ne.pinned, pl.table_bytes, hipHostMallocDefault) != hipSuccess)
+                    return FD_ENOMEM;
+                fill_table(cols, n_cols, pl, ws, ne.pinned);
+                hipStream_t cs = nullptr;
+                hipGraph_t graph = nullptr;
+                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    const bool enq = enqueue(cols, n_cols, pl, ws, ne.pinned, status, cs) == hipSuccess;
+                    ok = hipStreamEndCapture(cs, &graph) == hipSuccess && enq;
+                }
+                ok = ok && hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+                if (cs) (void)hipStreamDestroy(cs);
+                if (!ok) {
+                    if (ne.exec) (void)hipGraphExecDestroy(ne.exec);
+                    (void)hipHostFree(ne.pinned);
+                    return FD_EHIP;
+                }
+                g_graphs.emplace_front(key, ne);
+                ge = &g_graphs.front().second;
+                while (g_graphs.size() > kMaxGraphs) {
+                    // a graph launched earlier may still run: wait before freeing what it reads
+                    (void)hipDeviceSynchronize();
+                    GraphEntry& old = g_graphs.back().second;
+                    (void)hipGraphExecDestroy(old.exec);
+                    (void)hipHostFree(old.pinned);
+                    g_graphs.pop_back();
+                }
+            }
+            if (hipGraphLaunch(ge->exec, st) != hipSuccess) return FD_EHIP;
+        } else {
+            const fd_status rc = run_once(cols, n_cols, pl, ws, status, st, dev);
+            if (rc != FD_OK) return rc;
+        }
+        if (flags & FD_ASYNC) return FD_OK;
+        return read_status(ws, st);
+    } catch (...) {
+        return FD_ENOMEM;
+    }
+}
+
+}  // extern "C"

@@ -12,16 +12,69 @@
 
 using namespace fd;
 
-struct fd_dict {
-    fd_codec codec;
-    int32_t n;
-    int device;
-    void* mem;              // single device allocation owned by the handle
-    const uint8_t* bytes;   // FSST-8: packed symbols (copy)
-    const uint8_t* lens;    // FSST-8: lengths (copy)
-    const uint4* tok16;     // OnPair-16: fixed 16-byte entries, 65,536 of them
-    const uint8_t* tok_len; // OnPair-16: 65,536 lengths (0 = invalid code)
+namespace fd {
+
+int64_t codes_per_pass(fd_codec c) {
+    const int codec = (int)c;
+    return (int64_t)kWG * chunks_per_lane(codec) * codes_per_chunk(codec);
+}
+
+// Strings per tile: the largest count whose expected code count plus four
+// standard deviations (per-string coefficient of variation taken as 0.6) fits
+// in one super-pass, so that almost every tile is decoded in one pass.
+int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings) {
+    const double cap = (double)codes_per_pass(codec) - 16.0;
+    const double m = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+    const double mean = m < 1.0 ? 1.0 : m;
+    int64_t sb = 1;
+    for (int64_t lo = 1, hi = codec == FD_FSST8 ? kSbMaxFsst : kSbMax; lo <= hi;) {
+        const int64_t mid = (lo + hi) / 2;
+        const double need = mid * mean + 4.0 * 0.6 * mean * __builtin_sqrt((double)mid);
+        if (need <= cap) { sb = mid; lo = mid + 1; } else { hi = mid - 1; }
+    }
+    return sb;
+}
+
+namespace {
+struct DevInfo {
+    int cus = 0;
+    int occ[3][2][3] = {};  // [codec][index64][mode]
+    int bocc[3][2] = {};    // batch kernels: [codec][index64]
 };
+std::mutex g_mu;
+DevInfo g_dev[64];
+
+DevInfo& dev_info(int* dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (dev_out) *dev_out = dev;
+    DevInfo& d = g_dev[dev];
+    if (!d.cus) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 1;
+        d.cus = v;
+    }
+    return d;
+}
+}  // namespace
+
+int resident_grid(int codec, int index_bits, int mode) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevInfo& d = dev_info(nullptr);
+    int& o = d.occ[codec][index_bits == 64][mode];
+    if (!o) o = decode_occupancy(codec, index_bits, mode);
+    return d.cus * o;
+}
+
+int resident_grid_batch(int codec, int index_bits) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevInfo& d = dev_info(nullptr);
+    int& o = d.bocc[codec][index_bits == 64];
+    if (!o) o = batch_occupancy(codec, index_bits);
+    return d.cus * o;
+}
+
+}  // namespace fd
 
 namespace {
 
@@ -45,28 +98,6 @@ struct Plan {
     size_t bytes;
 };
 
-// Codes one super-pass of a workgroup holds in registers.
-int64_t codes_per_pass(fd_codec c) {
-    const int codec = (int)c;
-    return (int64_t)kWG * chunks_per_lane(codec) * codes_per_chunk(codec);
-}
-
-// Strings per tile: the largest count whose expected code count plus four
-// standard deviations (per-string coefficient of variation taken as 0.6) fits
-// in one super-pass, so that almost every tile is decoded in one pass.
-int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings) {
-    const double cap = (double)codes_per_pass(codec) - 16.0;
-    const double m = n_strings ? (double)n_codes / (double)n_strings : 1.0;
-    const double mean = m < 1.0 ? 1.0 : m;
-    int64_t sb = 1;
-    for (int64_t lo = 1, hi = codec == FD_FSST8 ? kSbMaxFsst : kSbMax; lo <= hi;) {
-        const int64_t mid = (lo + hi) / 2;
-        const double need = mid * mean + 4.0 * 0.6 * mean * __builtin_sqrt((double)mid);
-        if (need <= cap) { sb = mid; lo = mid + 1; } else { hi = mid - 1; }
-    }
-    return sb;
-}
-
 bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl) {
     if (n_codes < 0 || n_strings < 0) return false;
     if (codec != FD_FSST8 && codec != FD_ONPAIR16) return false;
@@ -82,28 +113,6 @@ bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tunin
     pl->off_dict = align_up(pl->off_blocks + (size_t)pl->n_blocks * 8, 256);
     pl->bytes = pl->off_dict + (codec == FD_ONPAIR16 ? align_up(kTok16Bytes + kTokLenBytes, 256) : 0);
     return true;
-}
-
-struct DevInfo {
-    int cus = 0;
-    int occ[3][2][3] = {};  // [codec][index64][mode]
-};
-std::mutex g_mu;
-DevInfo g_dev[64];
-
-int resident_grid(int codec, int index_bits, int mode) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevInfo& d = g_dev[dev];
-    if (!d.cus) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 1;
-        d.cus = v;
-    }
-    int& o = d.occ[codec][index_bits == 64][mode];
-    if (!o) o = decode_occupancy(codec, index_bits, mode);
-    return d.cus * o;
 }
 
 fd_status hip_fail() { return FD_EHIP; }

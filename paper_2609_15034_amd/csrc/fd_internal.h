@@ -72,9 +72,34 @@ hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams
 hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n,
                         hipStream_t st);
 hipError_t launch_scan_totals(unsigned long long* v, int64_t n, hipStream_t st);
+int batch_occupancy(int codec, int index_bits);
+hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
+                               int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st);
+hipError_t launch_batch_reset(unsigned long long* z, int64_t n, unsigned long long* errs, int32_t n_cols,
+                              hipStream_t st);
+hipError_t launch_batch_status(const unsigned long long* errs, int32_t n_cols, int32_t* status, int32_t* status2,
+                               hipStream_t st);
 int chunks_per_lane(int codec);   // 16-byte code chunks each lane holds per super-pass
 int codes_per_chunk(int codec);
 hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int32_t n_tok, uint4* tok16,
                                  uint8_t* tok_len, unsigned long long* err, int* bad_flag, hipStream_t st);
 
+// host runtime helpers shared by the single-column and batch entry points
+int64_t codes_per_pass(fd_codec c);
+int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings);
+int resident_grid(int codec, int index_bits, int mode);
+int resident_grid_batch(int codec, int index_bits);
+
 }  // namespace fd
+
+// A prepared dictionary (device-resident, immutable after creation).
+struct fd_dict {
+    fd_codec codec;
+    int32_t n;
+    int device;
+    void* mem;              // single device allocation owned by the handle
+    const uint8_t* bytes;   // FSST-8: packed symbols (copy)
+    const uint8_t* lens;    // FSST-8: lengths (copy)
+    const uint4* tok16;     // OnPair-16: fixed 16-byte entries, 65,536 of them
+    const uint8_t* tok_len; // OnPair-16: 65,536 lengths (0 = invalid code)
+};

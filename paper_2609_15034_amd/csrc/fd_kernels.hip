@@ -736,45 +736,99 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
 }
 
 // --------------------------------------------------------------------------
-// the decode kernel
+// where a launch's tiles come from: one column, or a batch of columns whose
+// tiles are numbered consecutively (column c owns ids first_tile[c] ..
+// first_tile[c + 1] - 1; each column has its own look-back state)
 // --------------------------------------------------------------------------
-template <int CODEC, typename IDX, int MODE>
-__global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
+struct OneColumn {
+    static constexpr bool kBatch = false;
+    const DecodeParams& p;
+    __device__ int64_t n_tiles() const { return p.n_tiles; }
+    __device__ unsigned* counter() const { return p.counters; }
+    __device__ int column(int64_t, int) const { return 0; }
+    __device__ const DecodeParams& params(int) const { return p; }
+    __device__ int64_t first(int) const { return 0; }
+};
+
+struct ColumnBatch {
+    static constexpr bool kBatch = true;
+    const DecodeParams* __restrict__ cols;
+    const int64_t* __restrict__ first_tile;   // n_cols + 1
+    int32_t n_cols;
+    int64_t total;
+    unsigned* ctr;
+    __device__ int64_t n_tiles() const { return total; }
+    __device__ unsigned* counter() const { return ctr; }
+    // the column of global tile id v (v < total); `hint` is a likely answer
+    __device__ int column(int64_t v, int hint) const {
+        if (first_tile[hint] <= v && v < first_tile[hint + 1]) return hint;
+        int lo = 0, hi = n_cols - 1;            // the last c with first_tile[c] <= v
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first_tile[mid] <= v) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ const DecodeParams& params(int c) const { return cols[c]; }
+    __device__ int64_t first(int c) const { return first_tile[c]; }
+};
+
+// --------------------------------------------------------------------------
+// the decode loop of one workgroup: tiles from the counter until it runs out
+// --------------------------------------------------------------------------
+template <int CODEC, typename IDX, int MODE, typename SRC>
+__device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     using C = Cfg<CODEC>;
     constexpr int P = C::P;
-    __shared__ SmemT<CODEC> s;
     const unsigned tid = threadIdx.x, wv = tid >> 6;
-
-    if constexpr (CODEC == kFsst8) fsst_build_table(s, p);
-
-    // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
-    const __amdgpu_buffer_rsrc_t r_len = make_rsrc(CODEC == kOnpair16 ? (const void*)p.tok_len : (const void*)p.codes,
-                                                   CODEC == kOnpair16 ? 65536u : 0u);
-    const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes,
-                                                   CODEC == kOnpair16 ? 65536u * 16u : 0u);
+    const int64_t n_all = src.n_tiles();
+    unsigned* const ctr = src.counter();
 
     // ---- prologue: the first two tiles of this workgroup ----
     if (tid == 0) {
-        s.nb[0] = (int64_t)atomicAdd(&p.counters[0], 1u);
-        s.nb[1] = (int64_t)atomicAdd(&p.counters[0], 1u);
+        s.nb[0] = (int64_t)atomicAdd(ctr, 1u);
+        s.nb[1] = (int64_t)atomicAdd(ctr, 1u);
     }
     __syncthreads();
-    int64_t t = uniform64(s.nb[0]), tn = uniform64(s.nb[1]);
+    int64_t v = uniform64(s.nb[0]), vn = uniform64(s.nb[1]);   // global tile ids
     __syncthreads();
+    int col = 0, table_col = -1;
+    if (v < n_all) col = src.column(v, 0);
+    int64_t t = v - src.first(col);                           // tile inside its column
     CoffRegs<CODEC, IDX> cr;
     Geom g{};
     uint32_t wc[P][4];
-    if (t < p.n_tiles) {
+    if (v < n_all) {
+        const DecodeParams& p = src.params(col);
         coff_load<CODEC, IDX>(p, t, cr);
         g = geom_from_regs<CODEC>(s, p, t, cr);
         codes_load<CODEC>(p, g, 0, wc);
     }
 
-    while (t < p.n_tiles) {
-        // (A) the tile's code offsets into LDS, validation, id of the tile after tn
+    if constexpr (CODEC == kFsst8 && !SRC::kBatch) fsst_build_table(s, src.params(0));
+    while (v < n_all) {
+        const DecodeParams& p = src.params(col);
+        if constexpr (CODEC == kFsst8 && SRC::kBatch) {
+            if (col != table_col) {      // a column of the batch with another table
+                fsst_build_table(s, p);
+                table_col = col;
+            }
+        }
+        // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
+        const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
+            CODEC == kOnpair16 ? (const void*)p.tok_len : (const void*)p.codes, CODEC == kOnpair16 ? 65536u : 0u);
+        const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
+            CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes, CODEC == kOnpair16 ? 65536u * 16u : 0u);
+        // the tile after this one, and its column
+        const bool has_next = vn < n_all;
+        const int coln = has_next ? src.column(vn, col) : col;
+        const int64_t tn = vn - src.first(coln);
+        const DecodeParams& pn = src.params(coln);
+
+        // (A) the tile's code offsets into LDS, validation, id of the tile after the next
         // (the atomic's result is only needed at the end of the iteration)
         uint32_t nid = 0;
-        if (tid == 0) nid = atomicAdd(&p.counters[0], 1u);
+        if (tid == 0) nid = atomicAdd(ctr, 1u);
         int64_t cur_reg = 0;
 #pragma unroll
         for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
@@ -795,8 +849,7 @@ __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
             bad = __syncthreads_or(bad);
             if (bad && tid == 0) record_error(p.err, kRankOffsets, FD_EOFFSETS);
         }
-        const bool has_next = tn < p.n_tiles;
-        if (has_next) coff_load<CODEC, IDX>(p, tn, cr);       // next tile's offsets (in flight)
+        if (has_next) coff_load<CODEC, IDX>(pn, tn, cr);       // next tile's offsets (in flight)
 
         // One super-pass (the common case): lengths, look-back issued, window 0
         // assembled, next tile prefetched, look-back completed, drain, offsets.
@@ -861,10 +914,10 @@ __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
             if (!prefetched) {
                 prefetched = true;
                 if (has_next) {
-                    const Geom gn = geom_from_regs<CODEC>(s, p, tn, cr);     // one barrier
+                    const Geom gn = geom_from_regs<CODEC>(s, pn, tn, cr);     // one barrier
                     nc0 = uniform64(s.nb[0]);
                     nc1 = uniform64(s.nb[1]);
-                    codes_load<CODEC>(p, gn, 0, wn);
+                    codes_load<CODEC>(pn, gn, 0, wn);
                 }
             }
             if (single) {
@@ -911,19 +964,31 @@ __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
         }
         if (tid == 0) s.next_id = (int32_t)nid;
         __syncthreads();
-        g = make_geom<CODEC>(p, tn, nc0, nc1);
+        if (has_next) g = make_geom<CODEC>(pn, tn, nc0, nc1);
+        v = vn;
+        col = coln;
         t = tn;
-        tn = (int64_t)(int32_t)uniform32((uint32_t)s.next_id);
+        vn = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
 #pragma unroll
         for (int c = 0; c < P; c++)
 #pragma unroll
             for (int i = 0; i < 4; i++) wc[c][i] = wn[c][i];
     }
+}
+
+// --------------------------------------------------------------------------
+// the decode kernels: one column, or a batch of columns of one codec and
+// offset width (the statuses of a batch are collected by k_batch_status)
+// --------------------------------------------------------------------------
+template <int CODEC, typename IDX, int MODE>
+__global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
+    __shared__ SmemT<CODEC> s;
+    decode_tiles<CODEC, IDX, MODE>(s, OneColumn{p});
 
     // the last workgroup to finish publishes the status
     if (MODE != kModeTotals) {
         __threadfence();
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             const unsigned prev = atomicAdd(&p.counters[1], 1u);
             if (prev == gridDim.x - 1) {
                 __threadfence();
@@ -934,6 +999,46 @@ __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
             }
         }
     }
+}
+
+template <int CODEC, typename IDX>
+__global__ void __launch_bounds__(kWG) k_decode_batch(const DecodeParams* __restrict__ cols,
+                                                      const int64_t* __restrict__ first_tile, int32_t n_cols,
+                                                      int64_t total, unsigned* ctr) {
+    __shared__ SmemT<CODEC> s;
+    decode_tiles<CODEC, IDX, kModeLookback>(s, ColumnBatch{cols, first_tile, n_cols, total, ctr});
+}
+
+// Statuses of a batch: column c's error word -> status[c]; the first error in
+// column order -> status[n_cols] (one workgroup).
+__global__ void __launch_bounds__(256) k_batch_status(const unsigned long long* errs, int32_t n_cols,
+                                                      int32_t* status, int32_t* status2) {
+    __shared__ int s_first;
+    if (threadIdx.x == 0) s_first = n_cols;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_cols; c += blockDim.x) {
+        const unsigned long long e = errs[c];
+        const int st = (e == ~0ull) ? FD_OK : (int)(e & 15ull);
+        if (status) status[c] = st;
+        if (st != FD_OK) atomicMin(&s_first, c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int st = FD_OK;
+        if (s_first < n_cols) {
+            const unsigned long long e = errs[s_first];
+            st = (int)(e & 15ull);
+        }
+        if (status) status[n_cols] = st;
+        if (status2) *status2 = st;
+    }
+}
+
+// Workspace reset of a batch: n words zeroed, then the n_cols error words set to "none".
+__global__ void k_batch_reset(unsigned long long* z, int64_t n, unsigned long long* errs, int32_t n_cols) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t k = i0; k < n; k += (int64_t)gridDim.x * blockDim.x) z[k] = 0;
+    for (int64_t k = i0; k < n_cols; k += (int64_t)gridDim.x * blockDim.x) errs[k] = ~0ull;
 }
 
 // --------------------------------------------------------------------------
@@ -1059,6 +1164,46 @@ hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams
     FD_FOR_ALL(L1)
 #undef L1
     return hipErrorInvalidValue;
+}
+
+template <int CODEC, typename IDX>
+static int batch_occupancy_of() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_decode_batch<CODEC, IDX>, kWG, 0) != hipSuccess) nb = 1;
+    return nb < 1 ? 1 : nb;
+}
+
+int batch_occupancy(int codec, int index_bits) {
+    if (codec == kFsst8) return index_bits == 64 ? batch_occupancy_of<kFsst8, int64_t>() : batch_occupancy_of<kFsst8, int32_t>();
+    return index_bits == 64 ? batch_occupancy_of<kOnpair16, int64_t>() : batch_occupancy_of<kOnpair16, int32_t>();
+}
+
+hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
+                               int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st) {
+    if (codec == kFsst8 && index_bits == 32)
+        hipLaunchKernelGGL((k_decode_batch<kFsst8, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
+    else if (codec == kFsst8)
+        hipLaunchKernelGGL((k_decode_batch<kFsst8, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
+    else if (index_bits == 32)
+        hipLaunchKernelGGL((k_decode_batch<kOnpair16, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
+    else
+        hipLaunchKernelGGL((k_decode_batch<kOnpair16, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(unsigned long long* z, int64_t n, unsigned long long* errs, int32_t n_cols,
+                              hipStream_t st) {
+    int64_t blocks = (max(n, (int64_t)n_cols) + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)blocks), dim3(256), 0, st, z, n, errs, n_cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const unsigned long long* errs, int32_t n_cols, int32_t* status, int32_t* status2,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(256), 0, st, errs, n_cols, status, status2);
+    return hipGetLastError();
 }
 
 int chunks_per_lane(int codec) { return codec == kFsst8 ? Cfg<kFsst8>::P : Cfg<kOnpair16>::P; }

@@ -92,3 +92,25 @@ def test_argument_errors_enqueue_nothing(fdlib):
     assert st == fdlib.EINVAL
     # null dictionary handle
     assert L.fd_decode(None, fake, 10, fake, 64, 1, fake, fake, 10, ws, 1 << 20, None, 0, None) == fdlib.EINVAL
+
+
+def test_batch_argument_errors_enqueue_nothing(fdlib):
+    """batch_decode rejects bad batches on the host, before touching the device."""
+    L = fdlib.lib()
+    P = ctypes.c_void_p
+    ws = P(1 << 21)
+    arr = (fdlib.Column * 1)()
+    assert L.batch_decode(arr, -1, None, ws, 1 << 20, None, 0, None) == fdlib.EINVAL          # n_cols < 0
+    assert L.batch_decode(None, 1, None, ws, 1 << 20, None, 0, None) == fdlib.EINVAL          # no column array
+    assert L.batch_decode(arr, 0, None, None, 1 << 20, None, 0, None) == fdlib.EINVAL        # no workspace
+    assert L.batch_decode(arr, 0, None, P((1 << 21) + 8), 1 << 20, None, 0, None) == fdlib.EINVAL   # misaligned
+    assert L.batch_decode(arr, 0, None, ws, 1 << 20, None, 1, None) == fdlib.EINVAL          # async, no status
+    assert L.batch_decode(arr, 0, None, ws, 1 << 20, None, 8, None) == fdlib.EINVAL          # unknown flag
+    tu = fdlib.Tuning(1, 0, 0, 0)                                                             # three-phase mode
+    assert L.batch_decode(arr, 0, ctypes.byref(tu), ws, 1 << 20, None, 0, None) == fdlib.EINVAL
+    arr[0] = fdlib.Column(0, 1 << 20, 10, 1 << 20, 64, 1, 1 << 20, 1 << 20, 10)               # no dictionary
+    assert L.batch_decode(arr, 1, None, ws, 1 << 20, None, 0, None) == fdlib.EINVAL
+    sz = ctypes.c_size_t(0)
+    assert L.fd_batch_workspace_size(arr, 1, None, ctypes.byref(sz)) == fdlib.EINVAL
+    assert L.fd_batch_workspace_size(arr, 0, None, ctypes.byref(sz)) == 0 and sz.value >= 256
+    assert L.fd_batch_workspace_size(arr, -1, None, ctypes.byref(sz)) == fdlib.EINVAL
