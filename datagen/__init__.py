@@ -298,6 +298,67 @@ def random_onpair(seed: int = 33, n_codes: int = 1 << 16, n_strings: int = 1000,
                   _stats("onpair16", codes, coff, dl, 0, decoded))
 
 
+def batch_columns(seed: int = 4, n_cols: int = 256, min_bytes: int = 4 << 10, max_bytes: int = 64 << 20,
+                  threads: int | None = None, keep_text: bool = True) -> list[Column]:
+    """The batched workload: n_cols columns, decoded sizes log-uniform in
+    [min_bytes, max_bytes], codecs half FSST-8 log lines and half OnPair-16
+    URLs (shuffled), every column with its own dictionary trained on its own
+    sample (1 MiB for FSST-8, 4 MiB for OnPair-16)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(min_bytes), np.log(max_bytes), n_cols)).astype(np.int64)
+    codecs = rng.permutation(np.array([0] * (n_cols // 2) + [1] * (n_cols - n_cols // 2)))
+    cols = []
+    for j in range(n_cols):
+        cseed = seed * 100_003 + j
+        if codecs[j] == 0:
+            cols.append(fsst_logs(cseed, int(sizes[j]), 1 << 20, threads, keep_text))
+        else:
+            cols.append(onpair_urls(cseed, int(sizes[j]), 4 << 20, threads, keep_text))
+    return cols
+
+
+@dataclass
+class ServePool:
+    """Dictionaries and request chunks of the served workload."""
+    dicts: list          # (codec, dict_bytes, dict_lens)
+    chunks: list[Column]  # each encoded with dicts[chunk_dict[i]]
+    chunk_dict: list[int]
+
+
+def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 48, min_bytes: int = 64 << 10,
+               max_bytes: int = 32 << 20, threads: int | None = None, keep_text: bool = True) -> ServePool:
+    """The served workload: n_dicts dictionaries (half FSST-8 trained on log
+    samples, half OnPair-16 trained on URL samples, each from its own seed) and
+    a pool of request chunks with decoded sizes log-uniform in [min_bytes,
+    max_bytes], each of fresh text encoded with a dictionary drawn at random."""
+    rng = np.random.default_rng(seed)
+    dicts = []
+    for k in range(n_dicts):
+        dseed = seed * 100_003 + 50_000 + k
+        if k % 2 == 0:
+            st, so = log_lines(dseed, 1 << 20, nchunk=4, threads=threads, stream_base=SAMPLE_STREAM)
+            dicts.append(("fsst8",) + tuple(fsst_train(st, so, 255)))
+        else:
+            st, so = url_strings(dseed, 4 << 20, nchunk=16, threads=threads, stream_base=SAMPLE_STREAM)
+            dicts.append(("onpair16",) + tuple(onpair_train(st, so, max_tokens=65536, tau=2, max_len=16)))
+    sizes = np.exp(rng.uniform(np.log(min_bytes), np.log(max_bytes), n_chunks)).astype(np.int64)
+    chunks, which = [], []
+    for i in range(n_chunks):
+        k = int(rng.integers(0, n_dicts))
+        codec, db, dl = dicts[k]
+        cseed = seed * 100_003 + i
+        if codec == "fsst8":
+            text, off = log_lines(cseed, int(sizes[i]), threads=threads)
+            codes, coff, esc = encode_fsst(db, dl, text, off, threads)
+        else:
+            text, off = url_strings(cseed, int(sizes[i]), threads=threads)
+            codes, coff, esc = encode_onpair(db, dl, text, off, threads)
+        chunks.append(Column("serve_chunk", codec, codes, coff, db, dl, text if keep_text else None,
+                             off if keep_text else None, esc, _stats(codec, codes, coff, dl, esc, len(text))))
+        which.append(k)
+    return ServePool(dicts, chunks, which)
+
+
 def column_for(name: str, **kw) -> Column:
     return {"fsst_small": fsst_small, "fsst_logs": fsst_logs, "onpair_urls": onpair_urls,
             "random_onpair": random_onpair}[name](**kw)

@@ -247,6 +247,47 @@ fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const f
 fd_status batch_decode(const fd_column *cols, int32_t n_cols, const fd_tuning *tuning, void *workspace,
                        size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
 
+/* ------------------------------------------------------------------------- */
+/* Served decode (continuous batching)                                         */
+/* ------------------------------------------------------------------------- */
+
+/* A decode server on the current device.  Requests are single columns
+ * (fd_column: prepared dictionaries, caller-owned device buffers that must stay
+ * valid until the request completes).  A scheduler thread owns n_slots streams;
+ * whenever a slot is free it admits waiting requests in arrival order while the
+ * device bytes they hold (codes, code and Arrow offsets, output capacity,
+ * workspace) stay within max_inflight_bytes, up to max_batch per batch, and runs
+ * them as one asynchronous batch_decode on the slot's stream.  Requests that
+ * arrive while batches run are admitted as slots and budget free up, so their
+ * work overlaps on the device.  Each request's bytes and offsets are those of
+ * fd_decode on the same column. */
+typedef struct fd_server fd_server;
+
+typedef struct fd_server_config {
+    int64_t max_inflight_bytes;   /* HBM budget of admitted requests; 0 = 16 GiB */
+    int32_t n_slots;              /* batches on the device at once (1..64); 0 = 4 */
+    int32_t max_batch;            /* requests per batch (1..65536); 0 = 64 */
+} fd_server_config;
+
+typedef struct fd_server_stats {
+    int64_t submitted, admitted, completed, batches, queued;
+    int64_t inflight_bytes, max_inflight_bytes;
+} fd_server_stats;
+
+/* cfg may be NULL (all defaults).  The server owns its streams, events,
+ * status buffers and per-slot workspaces (grown on demand with hipMalloc). */
+fd_status fd_server_create(const fd_server_config *cfg, fd_server **out);
+/* Queue one request; *ticket identifies it.  Host-visible errors of the column
+ * return FD_EINVAL and queue nothing.  Never blocks on the device. */
+fd_status fd_server_submit(fd_server *server, const fd_column *request, uint64_t *ticket);
+/* Wait for a request: its fd_status and its latency (microseconds from
+ * submission to the host seeing its batch complete).  Each ticket is waited
+ * for once. */
+fd_status fd_server_wait(fd_server *server, uint64_t ticket, int32_t *status, double *latency_us);
+fd_status fd_server_get_stats(fd_server *server, fd_server_stats *out);
+/* Completes every queued request, then frees the server. */
+fd_status fd_server_destroy(fd_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,9 @@ Names follow the C ABI:
   * ``decode``                           - convenience: sizes and allocates the
                                            outputs (two device passes);
   * ``batch_decode``                     - many columns, one submission (or one
-                                           cached HIP graph), autotuned tiles.
+                                           cached HIP graph), autotuned tiles;
+  * ``Server`` (fd_server)               - served decode: continuous batching
+                                           of requests under an HBM budget.
 """
 from __future__ import annotations
 
@@ -55,6 +57,17 @@ class Column(ctypes.Structure):
     _fields_ = [("dict", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("n_codes", ctypes.c_int64),
                 ("code_offsets", ctypes.c_void_p), ("index_bits", ctypes.c_int32), ("n_strings", ctypes.c_int64),
                 ("out_offsets", ctypes.c_void_p), ("out_bytes", ctypes.c_void_p), ("out_capacity", ctypes.c_int64)]
+
+
+class ServerConfig(ctypes.Structure):
+    """fd_server_config: HBM budget (bytes), stream slots, requests per batch (0 = default)."""
+    _fields_ = [("max_inflight_bytes", ctypes.c_int64), ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("queued", ctypes.c_int64), ("inflight_bytes", ctypes.c_int64),
+                ("max_inflight_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -100,6 +113,16 @@ def lib():
     L.fd_batch_workspace_size.argtypes = [ctypes.POINTER(Column), I32, ctypes.POINTER(Tuning), ctypes.POINTER(S)]
     L.batch_decode.restype = ctypes.c_int
     L.batch_decode.argtypes = [ctypes.POINTER(Column), I32, ctypes.POINTER(Tuning), P, S, P, U, P]
+    L.fd_server_create.restype = ctypes.c_int
+    L.fd_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
+    L.fd_server_submit.restype = ctypes.c_int
+    L.fd_server_submit.argtypes = [P, ctypes.POINTER(Column), ctypes.POINTER(ctypes.c_uint64)]
+    L.fd_server_wait.restype = ctypes.c_int
+    L.fd_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
+    L.fd_server_get_stats.restype = ctypes.c_int
+    L.fd_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.fd_server_destroy.restype = ctypes.c_int
+    L.fd_server_destroy.argtypes = [P]
     _lib = L
     return L
 
@@ -298,3 +321,61 @@ def batch_decode(cols, workspace, status=None, tuning=None, async_=False, graph=
     flags = (ASYNC if async_ else 0) | (GRAPH if graph else 0)
     return lib().batch_decode(arr, len(cols), _tuning(tuning), _ptr(workspace), workspace.numel(), _ptr(status),
                               flags, _stream_handle(stream))
+
+
+# --------------------------------------------------------------------------- #
+# served decode
+# --------------------------------------------------------------------------- #
+class Server:
+    """fd_server: continuous batching of decode requests on the current device.
+
+    ``submit`` takes a column tuple (Dict, codes, code_off, out_off, out_bytes)
+    whose tensors must stay alive until ``wait`` returns for its ticket."""
+
+    def __init__(self, max_inflight_bytes: int = 0, n_slots: int = 0, max_batch: int = 0):
+        self._h = ctypes.c_void_p(0)
+        cfg = ServerConfig(int(max_inflight_bytes), int(n_slots), int(max_batch))
+        st = lib().fd_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
+        if st:
+            raise DecodeError(st, "fd_server_create")
+
+    def submit(self, col) -> int:
+        arr = make_columns([col])
+        t = ctypes.c_uint64(0)
+        st = lib().fd_server_submit(self._h, arr, ctypes.byref(t))
+        if st:
+            raise DecodeError(st, "fd_server_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(fd_status, latency in microseconds) of a request."""
+        s = ctypes.c_int32(-1)
+        lat = ctypes.c_double(0.0)
+        st = lib().fd_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(s), ctypes.byref(lat))
+        if st:
+            raise DecodeError(st, "fd_server_wait")
+        return int(s.value), float(lat.value)
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        st = lib().fd_server_get_stats(self._h, ctypes.byref(out))
+        if st:
+            raise DecodeError(st, "fd_server_get_stats")
+        return {k: int(getattr(out, k)) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().fd_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,299 @@
+// Served decode: continuous batching of decode requests on one GPU.
+//
+// Requests (one column each, prepared dictionaries, caller-owned device
+// buffers) are queued by fd_server_submit.  A scheduler thread owns S stream
+// "slots".  Whenever a slot is free and requests are waiting, it admits them
+// in arrival order while the bytes they hold on the device (codes, offsets,
+// output capacity, their share of the workspace) stay within the HBM budget,
+// up to a batch limit, and launches them as one asynchronous batch_decode on
+// the slot's stream.  Requests that arrive while other batches run are
+// admitted as soon as a slot and budget free up, so batches overlap on the
+// device.  Completion is observed through one event per slot; the latency of
+// a request runs from its submission to the host seeing its batch complete.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "fastdecode.h"
+#include "fd_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket;
+    fd_column col;
+    int64_t bytes;              // device bytes the request holds while admitted
+    Clock::time_point t_submit;
+};
+
+struct Done {
+    int32_t status = -1;
+    double latency_us = 0.0;
+    bool done = false;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t* status = nullptr;  // device: max_batch + 1 statuses
+    int32_t* host_status = nullptr;
+    bool busy = false;
+    std::vector<Request> reqs;
+    int64_t bytes = 0;
+};
+
+int64_t request_bytes(const fd_column& c) {
+    const int64_t cb = (c.dict && c.dict->codec == FD_ONPAIR16) ? 2 : 1;
+    const int64_t ob = c.index_bits == 64 ? 8 : 4;
+    return c.n_codes * cb + 2 * (c.n_strings + 1) * ob + c.out_capacity;
+}
+
+}  // namespace
+
+struct fd_server {
+    fd_server_config cfg{};
+    int device = 0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::unordered_map<uint64_t, Done> done;
+    uint64_t next_ticket = 1;
+    int64_t inflight_bytes = 0;
+    bool stop = false;
+    fd_server_stats stats{};
+    std::thread thread;
+
+    void run();
+    bool launch(Slot& s, std::unique_lock<std::mutex>& lk);
+    void complete(Slot& s, std::unique_lock<std::mutex>& lk);
+};
+
+bool fd_server::launch(Slot& s, std::unique_lock<std::mutex>& lk) {
+    // admit in arrival order within the budget and the batch limit
+    std::vector<Request> take;
+    int64_t bytes = 0;
+    while (!queue.empty() && (int32_t)take.size() < cfg.max_batch) {
+        const Request& r = queue.front();
+        if (inflight_bytes + bytes + r.bytes > cfg.max_inflight_bytes && !(take.empty() && inflight_bytes == 0))
+            break;            // head-of-line waits for memory (a lone request larger than the budget still runs)
+        bytes += r.bytes;
+        take.push_back(r);
+        queue.pop_front();
+    }
+    if (take.empty()) return false;
+    inflight_bytes += bytes;
+    stats.batches += 1;
+    stats.admitted += (int64_t)take.size();
+    stats.max_inflight_bytes = std::max(stats.max_inflight_bytes, inflight_bytes);
+    lk.unlock();
+    std::vector<fd_column> cols(take.size());
+    for (size_t i = 0; i < take.size(); i++) cols[i] = take[i].col;
+    const fd_tuning tu = {0, 0, 0, 0};
+    size_t need = 0;
+    fd_status rc = fd_batch_workspace_size(cols.data(), (int32_t)cols.size(), &tu, &need);
+    if (rc == FD_OK && need > s.ws_bytes) {
+        if (s.ws) (void)hipFree(s.ws);
+        s.ws = nullptr;
+        s.ws_bytes = 0;
+        const size_t cap = std::max(need + need / 4, (size_t)1 << 20);
+        if (hipMalloc(&s.ws, cap) == hipSuccess) s.ws_bytes = cap;
+        else rc = FD_ENOMEM;
+    }
+    if (rc == FD_OK)
+        rc = batch_decode(cols.data(), (int32_t)cols.size(), &tu, s.ws, s.ws_bytes, s.status, FD_ASYNC, s.stream);
+    if (rc == FD_OK && hipMemcpyAsync(s.host_status, s.status, (cols.size() + 1) * sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+        rc = FD_EHIP;
+    if (rc == FD_OK && hipEventRecord(s.event, s.stream) != hipSuccess) rc = FD_EHIP;
+    lk.lock();
+    s.reqs.swap(take);
+    s.bytes = bytes;
+    s.busy = true;
+    if (rc != FD_OK) {
+        // nothing ran: report the failure on every request of the batch
+        for (size_t i = 0; i < s.reqs.size(); i++) s.host_status[i] = rc;
+        s.host_status[s.reqs.size()] = rc;
+        (void)hipStreamSynchronize(s.stream);
+    }
+    return true;
+}
+
+void fd_server::complete(Slot& s, std::unique_lock<std::mutex>&) {
+    const Clock::time_point now = Clock::now();
+    for (size_t i = 0; i < s.reqs.size(); i++) {
+        Done& d = done[s.reqs[i].ticket];
+        d.status = s.host_status[i];
+        d.latency_us = std::chrono::duration<double, std::micro>(now - s.reqs[i].t_submit).count();
+        d.done = true;
+        stats.completed += 1;
+    }
+    inflight_bytes -= s.bytes;
+    s.bytes = 0;
+    s.reqs.clear();
+    s.busy = false;
+    cv_done.notify_all();
+}
+
+void fd_server::run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        bool any_busy = false;
+        for (Slot& s : slots) {
+            if (!s.busy) continue;
+            lk.unlock();
+            const hipError_t q = hipEventQuery(s.event);
+            lk.lock();
+            if (q == hipSuccess) complete(s, lk);
+            else if (q != hipErrorNotReady) {          // a device error: fail the batch
+                for (size_t i = 0; i < s.reqs.size(); i++) s.host_status[i] = FD_EHIP;
+                complete(s, lk);
+            } else {
+                any_busy = true;
+            }
+        }
+        for (Slot& s : slots) {
+            if (!s.busy && !queue.empty()) {
+                if (launch(s, lk)) any_busy = true;
+            }
+        }
+        if (stop && queue.empty() && !any_busy) break;
+        if (any_busy) {
+            // poll the events of running batches without holding the lock
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        }
+    }
+}
+
+extern "C" {
+
+fd_status fd_server_create(const fd_server_config* cfg, fd_server** out) {
+    if (!out) return FD_EINVAL;
+    *out = nullptr;
+    fd_server_config c = cfg ? *cfg : fd_server_config{};
+    if (c.max_inflight_bytes < 0 || c.n_slots < 0 || c.max_batch < 0 || c.n_slots > 64 || c.max_batch > 65536)
+        return FD_EINVAL;
+    if (c.max_inflight_bytes == 0) c.max_inflight_bytes = (int64_t)16 << 30;
+    if (c.n_slots == 0) c.n_slots = 4;
+    if (c.max_batch == 0) c.max_batch = 64;
+    fd_server* s = new (std::nothrow) fd_server;
+    if (!s) return FD_ENOMEM;
+    s->cfg = c;
+    if (hipGetDevice(&s->device) != hipSuccess) { delete s; return FD_EHIP; }
+    s->slots.resize(c.n_slots);
+    bool ok = true;
+    for (Slot& sl : s->slots) {
+        ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipMalloc((void**)&sl.status, (c.max_batch + 1) * sizeof(int32_t)) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&sl.host_status, (c.max_batch + 1) * sizeof(int32_t),
+                                 hipHostMallocDefault) == hipSuccess;
+        if (!ok) break;
+    }
+    if (!ok) {
+        for (Slot& sl : s->slots) {
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+            if (sl.event) (void)hipEventDestroy(sl.event);
+            if (sl.status) (void)hipFree(sl.status);
+            if (sl.host_status) (void)hipHostFree(sl.host_status);
+        }
+        delete s;
+        return FD_EHIP;
+    }
+    try {
+        s->thread = std::thread([s] { s->run(); });
+    } catch (...) {
+        delete s;
+        return FD_ENOMEM;
+    }
+    *out = s;
+    return FD_OK;
+}
+
+fd_status fd_server_submit(fd_server* s, const fd_column* req, uint64_t* ticket) {
+    if (!s || !req || !ticket) return FD_EINVAL;
+    // the host-visible checks of batch_decode, now, so that a bad request fails its submission
+    size_t ws = 0;
+    const fd_tuning tu = {0, 0, 0, 0};
+    if (fd_batch_workspace_size(req, 1, &tu, &ws) != FD_OK) return FD_EINVAL;
+    try {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return FD_EINVAL;
+        Request r;
+        r.ticket = s->next_ticket++;
+        r.col = *req;
+        r.bytes = request_bytes(*req) + (int64_t)ws;
+        r.t_submit = Clock::now();
+        s->queue.push_back(r);
+        s->done[r.ticket] = Done();
+        s->stats.submitted += 1;
+        *ticket = r.ticket;
+    } catch (...) {
+        return FD_ENOMEM;
+    }
+    s->cv_work.notify_one();
+    return FD_OK;
+}
+
+fd_status fd_server_wait(fd_server* s, uint64_t ticket, int32_t* status, double* latency_us) {
+    if (!s) return FD_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->done.find(ticket);
+    if (it == s->done.end()) return FD_EINVAL;
+    s->cv_done.wait(lk, [&] { return s->done[ticket].done; });
+    const Done d = s->done[ticket];
+    s->done.erase(ticket);
+    if (status) *status = d.status;
+    if (latency_us) *latency_us = d.latency_us;
+    return FD_OK;
+}
+
+fd_status fd_server_get_stats(fd_server* s, fd_server_stats* out) {
+    if (!s || !out) return FD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->inflight_bytes = s->inflight_bytes;
+    out->queued = (int64_t)s->queue.size();
+    return FD_OK;
+}
+
+fd_status fd_server_destroy(fd_server* s) {
+    if (!s) return FD_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->thread.joinable()) s->thread.join();
+    for (Slot& sl : s->slots) {
+        (void)hipStreamSynchronize(sl.stream);
+        (void)hipStreamDestroy(sl.stream);
+        (void)hipEventDestroy(sl.event);
+        if (sl.ws) (void)hipFree(sl.ws);
+        (void)hipFree(sl.status);
+        (void)hipHostFree(sl.host_status);
+    }
+    delete s;
+    return FD_OK;
+}
+
+}  // extern "C"
