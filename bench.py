@@ -18,7 +18,13 @@ Prints one JSON line:
   cpu_baseline the CPU oracle on this host's cores over the same column
   bit_exact    GPU output == the generated source text (bytes and offsets)
 
-  python bench.py [--workload fsst_logs|onpair_urls|fsst_small] [--steps K] [--warmup W]
+  python bench.py [--workload fsst_logs|onpair_urls|fsst_small|batch256|serve] [--steps K] [--warmup W]
+
+The default run (fsst_logs) also reports, in "batch" and "serve", short
+runs of the batched workload (256 columns in one replayed HIP graph, against
+the same columns decoded one call each) and of the served workload
+(Poisson arrivals into the continuous-batching server, p50/p99 latency);
+--no-extra skips them.
 """
 from __future__ import annotations
 
@@ -33,10 +39,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+METRIC = "decoded GB/s per GPU (fraction of HBM peak), bit-exact; p50/p99 latency served"
 WORKLOADS = {
     "fsst_logs": dict(codec="fsst8", desc="FSST-8 log lines, 1 GiB decoded, int64 offsets"),
     "onpair_urls": dict(codec="onpair16", desc="OnPair-16 URL/identifier strings, 1 GiB decoded, int64 offsets"),
     "fsst_small": dict(codec="fsst8", desc="FSST-8 printable strings, 10,000 strings, int32 offsets"),
+    "batch256": dict(codec="mixed", desc="256 columns, decoded sizes log-uniform 4 KB-64 MB, FSST-8 / OnPair-16 "
+                                        "50/50, a dictionary per column, one replayed HIP graph"),
+    "serve": dict(codec="mixed", desc="Poisson arrivals of chunks log-uniform 64 KB-32 MB, 32 device-resident "
+                                     "dictionaries, 16 GB in flight, continuous batching"),
 }
 KERNEL_SOURCES = ["paper_2609_15034_amd/csrc/fd_kernels.hip", "paper_2609_15034_amd/csrc/fd_internal.h",
                   "paper_2609_15034_amd/csrc/fd_host.cpp"]
@@ -107,6 +118,190 @@ def read_traffic(workload: str, src_hash: str):
     return t
 
 
+def _upload_column(col, dev):
+    import numpy as np
+    import torch
+    codes_np = col.codes if col.codec == "fsst8" else col.codes.view(np.int16)
+    return torch.from_numpy(codes_np).to(dev), torch.from_numpy(col.code_off).to(dev)
+
+
+def _events_time(fn, steps, warmup):
+    """Mean seconds per call of fn() over `steps` calls after `warmup`, timed
+    with events on the current stream (the stream the library launches on)."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record()
+    for i in range(steps):
+        fn()
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) / 1e3 for i in range(steps)])
+    return float(per.mean()), per
+
+
+def run_batch(steps: int, warmup: int, seed: int | None, n_cols: int = 256, max_bytes: int = 64 << 20,
+              check: bool = True, cpu: bool = True):
+    """The batched workload: returns a result dict (see the module docstring)."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2609_15034_amd as fd
+    t0 = time.time()
+    cols = datagen.batch_columns(seed=seed or 4, n_cols=n_cols, max_bytes=max_bytes)
+    D = sum(c.decoded_bytes for c in cols)
+    log(f"[batch] generated {n_cols} columns, {D / 1e9:.3f} GB decoded in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda")
+    tups, dicts, outs = [], [], []
+    for c in cols:
+        codes, code_off = _upload_column(c, dev)
+        d = fd.Dict(c.codec, torch.from_numpy(c.dict_bytes).to(dev), torch.from_numpy(c.dict_lens).to(dev))
+        out = torch.empty(c.decoded_bytes, dtype=torch.uint8, device=dev)
+        out_off = torch.empty(c.n_strings + 1, dtype=code_off.dtype, device=dev)
+        dicts.append(d)
+        outs.append((out, out_off))
+        tups.append((d, codes, code_off, out_off, out))
+    ws = torch.empty(fd.batch_workspace_size(tups), dtype=torch.uint8, device=dev)
+    status = torch.zeros(len(tups) + 1, dtype=torch.int32, device=dev)
+    t1 = time.time()
+    st = fd.batch_decode(tups, ws, status=status)             # first call: the autotuner picks tile sizes
+    if st != fd.OK:
+        raise fd.DecodeError(st, "batch_decode")
+    log(f"[batch] autotuned in {time.time() - t1:.1f}s")
+
+    def step():
+        if fd.batch_decode(tups, ws, status=status, async_=True, graph=True) != fd.OK:
+            raise fd.DecodeError(-1, "batch_decode")
+    mean_s, per = _events_time(step, steps, warmup)
+    if int(status[-1].item()) != fd.OK:
+        raise fd.DecodeError(int(status[-1].item()), "batch_decode")
+    # the same columns, one fd_decode call each (the single-column mode)
+    wss = [fd.alloc_workspace(c.codec, t[1].numel(), c.n_strings) for c, t in zip(cols, tups)]
+
+    def loop():
+        for t, w in zip(tups, wss):
+            if fd.decode_into(t[0], t[1], t[2], t[3], t[4], w, status=status[:1], async_=True) != fd.OK:
+                raise fd.DecodeError(-1, "fd_decode")
+    loop_s, _ = _events_time(loop, max(2, steps // 4), 1)
+    bit_exact = None
+    if check:
+        ok = True
+        for c, (out, out_off) in zip(cols, outs):
+            ok &= bool(torch.equal(out.cpu(), torch.from_numpy(c.text)))
+            ok &= bool(np.array_equal(out_off.cpu().numpy().astype(np.int64), c.text_off))
+        bit_exact = ok
+    B_alg = sum(algorithmic_bytes(c) for c in cols)
+    res = {"value": round(D / mean_s / 1e9, 2), "decoded_bytes": int(D), "n_cols": n_cols,
+           "ms_per_step": round(mean_s * 1e3, 4), "per_column_calls_GBps": round(D / loop_s / 1e9, 2),
+           "batch_over_per_column": round(loop_s / mean_s, 3),
+           "step_us": {"min": round(float(per.min()) * 1e6, 1), "p50": round(float(np.median(per)) * 1e6, 1)},
+           "roofline": {"bound": "hbm", "achieved": round(B_alg / mean_s / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                        "unit": "GB/s", "frac": round(B_alg / mean_s / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
+                        "algorithmic_bytes": int(B_alg)},
+           "bit_exact": bit_exact}
+    if cpu:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        sample = [c for c in cols if c.decoded_bytes <= (32 << 20)][:64]
+        tot_t = tot_b = 0
+        for c in sample:
+            t_cpu, nb, _ = oracle.time_decode(c.codec, c.codes, c.code_off, c.dict_bytes, c.dict_lens,
+                                              threads=threads, repeats=1)
+            tot_t += t_cpu
+            tot_b += nb
+        res["cpu_baseline"] = {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": threads,
+                               "kind": "oracle", "sample": f"{len(sample)} columns of the batch "
+                                                           f"({tot_b} decoded bytes), one pass"}
+    log(f"[batch] {res['value']} GB/s (per-column calls {res['per_column_calls_GBps']} GB/s)")
+    return res
+
+
+def run_serve(seed: int | None, n_requests: int = 400, load: float = 0.7, budget: int = 16 << 30,
+              n_slots: int = 4, max_batch: int = 64, check: bool = True, n_chunks: int = 48):
+    """The served workload: Poisson arrivals at `load` x the server's measured
+    batch capacity; returns a result dict with p50 / p99 latency."""
+    import threading
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2609_15034_amd as fd
+    t0 = time.time()
+    pool = datagen.serve_pool(seed=seed or 5, n_chunks=n_chunks)
+    log(f"[serve] generated {len(pool.dicts)} dictionaries, {len(pool.chunks)} chunks "
+        f"({sum(c.decoded_bytes for c in pool.chunks) / 1e6:.1f} MB) in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda")
+    dicts = [fd.Dict(codec, torch.from_numpy(db).to(dev), torch.from_numpy(dl).to(dev))
+             for codec, db, dl in pool.dicts]
+    inputs = [_upload_column(c, dev) for c in pool.chunks]
+    rng = np.random.default_rng((seed or 5) + 1)
+    pick = rng.integers(0, len(pool.chunks), size=n_requests)
+    reqs = []
+    for i in pick:
+        c = pool.chunks[i]
+        out = torch.empty(c.decoded_bytes, dtype=torch.uint8, device=dev)
+        out_off = torch.empty(c.n_strings + 1, dtype=inputs[i][1].dtype, device=dev)
+        reqs.append((dicts[pool.chunk_dict[i]], inputs[i][0], inputs[i][1], out_off, out))
+    sizes = np.array([pool.chunks[i].decoded_bytes for i in pick], np.float64)
+    # capacity: the whole pool as one batch
+    tups = [(dicts[pool.chunk_dict[i]], inputs[i][0], inputs[i][1],
+             torch.empty(c.n_strings + 1, dtype=inputs[i][1].dtype, device=dev),
+             torch.empty(c.decoded_bytes, dtype=torch.uint8, device=dev)) for i, c in enumerate(pool.chunks)]
+    tu = {"mode": 0, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    ws = torch.empty(fd.batch_workspace_size(tups, tu), dtype=torch.uint8, device=dev)
+    cap_s, _ = _events_time(lambda: fd.batch_decode(tups, ws, tuning=tu, async_=True,
+                                                    status=torch.zeros(len(tups) + 1, dtype=torch.int32,
+                                                                       device=dev)), 5, 2)
+    cap_bps = sum(c.decoded_bytes for c in pool.chunks) / cap_s
+    rate = load * cap_bps / sizes.mean()                        # requests per second
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    log(f"[serve] capacity {cap_bps / 1e9:.1f} GB/s, offered {load * cap_bps / 1e9:.1f} GB/s = "
+        f"{rate:.0f} requests/s")
+    torch.cuda.synchronize()
+    tickets = [0] * n_requests
+    with fd.Server(max_inflight_bytes=budget, n_slots=n_slots, max_batch=max_batch) as srv:
+        t_start = time.perf_counter()
+
+        def producer():
+            for k in range(n_requests):
+                dt = arrivals[k] - (time.perf_counter() - t_start)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[k] = srv.submit(reqs[k])
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t_start
+        stats = srv.stats()
+    sts = np.array([r[0] for r in res])
+    lat = np.array([r[1] for r in res]) / 1e3                    # ms
+    if np.any(sts != 0):
+        raise fd.DecodeError(int(sts[sts != 0][0]), "served decode")
+    bit_exact = None
+    if check:
+        ok = True
+        for k, i in enumerate(pick):
+            ok &= bool(torch.equal(reqs[k][4].cpu(), torch.from_numpy(pool.chunks[i].text)))
+        bit_exact = ok
+    D = float(sizes.sum())
+    out = {"value": round(D / wall / 1e9, 2), "unit": "GB/s", "n_requests": n_requests,
+           "offered_GBps": round(load * cap_bps / 1e9, 2), "batch_capacity_GBps": round(cap_bps / 1e9, 2),
+           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                          "p99": round(float(np.percentile(lat, 99)), 3),
+                          "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+           "mean_request_MB": round(float(sizes.mean()) / 1e6, 2), "budget_bytes": budget,
+           "max_inflight_bytes": stats["max_inflight_bytes"], "batches": stats["batches"],
+           "mean_batch": round(stats["admitted"] / max(stats["batches"], 1), 2), "slots": n_slots,
+           "bit_exact": bit_exact}
+    log(f"[serve] {out['value']} GB/s, p50 {out['latency_ms']['p50']} ms, p99 {out['latency_ms']['p99']} ms, "
+        f"mean batch {out['mean_batch']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +314,7 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="workgroups (0 = all resident)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the output check")
+    ap.add_argument("--no-extra", action="store_true", help="default run: skip the batched and served legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
@@ -141,6 +337,24 @@ def main():
     if args.copy_calibration:
         gbps = copy_calibration(args.copy_calibration)
         print(json.dumps({"copy_bytes": args.copy_calibration, "copy_GBps": round(gbps, 1)}))
+        return
+
+    if args.workload in ("batch256", "serve"):
+        if args.workload == "batch256":
+            r = run_batch(args.steps, args.warmup, args.seed, check=not args.no_check, cpu=not args.no_cpu)
+            cfg = {"workload": "batch256", "description": WORKLOADS["batch256"]["desc"],
+                   "n_cols": r["n_cols"], "decoded_bytes": r["decoded_bytes"]}
+            ms, steps, warmup = r["ms_per_step"], args.steps, args.warmup
+        else:
+            r = run_serve(args.seed, check=not args.no_check)
+            cfg = {"workload": "serve", "description": WORKLOADS["serve"]["desc"], "n_requests": r["n_requests"],
+                   "offered_GBps": r["offered_GBps"], "budget_bytes": r["budget_bytes"]}
+            ms, steps, warmup = None, r["n_requests"], 0
+        line = {"metric": METRIC, "value": r["value"], "unit": "GB/s", "n_gpus": 1, "steps": steps,
+                "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": cfg}
+        line.update({k: v for k, v in r.items() if k not in ("value",)})
+        print(json.dumps(line), flush=True)
         return
 
     t0 = time.time()
@@ -221,7 +435,7 @@ def main():
         log(f"[bench] cpu oracle: {cpu['value']} GB/s on {threads} threads")
 
     res = {
-        "metric": "decoded GB/s per GPU (fraction of HBM peak), bit-exact",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -248,6 +462,14 @@ def main():
         "cpu_baseline": cpu,
         "kernel_source_sha": src_hash,
     }
+    if args.workload == "fsst_logs" and not args.no_extra:
+        # the batched and served workloads, short runs
+        for key, fn in (("batch", lambda: run_batch(10, 2, None, check=not args.no_check, cpu=False)),
+                        ("serve", lambda: run_serve(None, n_requests=300, check=not args.no_check))):
+            try:
+                res[key] = fn()
+            except Exception as e:       # report, never lose the main line
+                res[key] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(res), flush=True)
 
 
