@@ -325,12 +325,13 @@ class ServePool:
     chunk_dict: list[int]
 
 
-def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 48, min_bytes: int = 64 << 10,
+def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 128, min_bytes: int = 64 << 10,
                max_bytes: int = 32 << 20, threads: int | None = None, keep_text: bool = True) -> ServePool:
     """The served workload: n_dicts dictionaries (half FSST-8 trained on log
     samples, half OnPair-16 trained on URL samples, each from its own seed) and
     a pool of request chunks with decoded sizes log-uniform in [min_bytes,
-    max_bytes], each of fresh text encoded with a dictionary drawn at random."""
+    max_bytes], each of fresh text encoded with one of the dictionaries (chunk
+    i uses dictionary i mod n_dicts, so 128 chunks give 4 per dictionary)."""
     rng = np.random.default_rng(seed)
     dicts = []
     for k in range(n_dicts):
@@ -344,7 +345,7 @@ def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 48, min_bytes: 
     sizes = np.exp(rng.uniform(np.log(min_bytes), np.log(max_bytes), n_chunks)).astype(np.int64)
     chunks, which = [], []
     for i in range(n_chunks):
-        k = int(rng.integers(0, n_dicts))
+        k = i % n_dicts
         codec, db, dl = dicts[k]
         cseed = seed * 100_003 + i
         if codec == "fsst8":
