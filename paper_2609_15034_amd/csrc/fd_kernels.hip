@@ -519,49 +519,87 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
 // result does not depend on the output position, so it can overlap the
 // look-back.
 // --------------------------------------------------------------------------
+// 128 bits as two 64-bit halves (little-endian byte order: byte 0 is the low
+// byte of lo)
+struct U128 {
+    uint64_t lo, hi;
+};
+
+// v << (8 * o) truncated to 128 bits, o in 0..15
+__device__ __forceinline__ U128 shl_bytes(U128 v, uint32_t o) {
+    const uint32_t sh = 8u * o;
+    U128 r;
+    if (sh == 0) {
+        r = v;
+    } else if (sh < 64) {
+        r.lo = v.lo << sh;
+        r.hi = (v.hi << sh) | (v.lo >> (64u - sh));
+    } else {
+        r.lo = 0;
+        r.hi = v.lo << (sh - 64u);
+    }
+    return r;
+}
+
+// Every token (FSST-8: every pair of tokens) is written as a whole 16-byte
+// entry at its offset; the lane's next entry overwrites the excess (the
+// copy-and-advance idea of OnPair's CPU loop).  The excess of a lane's last
+// entries lands in the first 16 bytes of the next lane, which each lane also
+// builds in registers (`head`, its entries are zero past their lengths) and
+// writes back once every lane is done (fixup).  No write is ever narrower than
+// 16 bytes: LDS stores at byte-granular addresses cost several times an aligned
+// one whatever their width.
 template <typename S>
 __device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], uint32_t lit, const uint32_t (&lenp)[4],
-                                                int& q, int qend) {
+                                                int& q, int q0, U128& head) {
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
-        const uint32_t l = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
-        const uint32_t bj = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
-        uint64_t v = s.fsst_tab[bj];
-        if ((lit >> j) & 1u) v = bj;
-        if (q + 8 <= qend) {
-            // the whole entry; the excess lands inside the lane's own range and is
-            // overwritten by its next tokens
-            lds_put8(&s.stage[q], v);
+    for (int j = 0; j < 16; j += 2) {
+        const uint32_t l0 = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        const uint32_t l1 = (lenp[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xffu;
+        const uint32_t b0 = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        const uint32_t b1 = (w[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xffu;
+        uint64_t v0 = s.fsst_tab[b0];
+        uint64_t v1 = s.fsst_tab[b1];
+        if ((lit >> j) & 1u) v0 = b0;
+        if ((lit >> (j + 1)) & 1u) v1 = b1;
+        if (l0 == 0) v0 = 0;                  // codes outside the range carry no bytes
+        if (l1 == 0) v1 = 0;
+        // the pair: v0 | v1 << 8 * l0 over 128 bits, l0 in 0..8
+        U128 pr;
+        if (l0 >= 8) {
+            pr.lo = v0;
+            pr.hi = v1;
         } else {
-            // the lane's last bytes: exact length (l in 0..7)
-            const uint32_t o4 = l & 4u, o2 = l & 6u;
-            if (l & 4u) lds_put4(&s.stage[q], (uint32_t)v);
-            if (l & 2u) lds_put2(&s.stage[q + (int)o4], (uint32_t)(v >> (8 * o4)));
-            if (l & 1u) s.stage[q + (int)o2] = (uint8_t)(v >> (8 * o2));
+            pr.lo = v0 | (v1 << (8u * l0));
+            pr.hi = (v1 >> 1) >> (63u - 8u * l0);
         }
-        q += (int)l;
-        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        const u32x4 v = {(uint32_t)pr.lo, (uint32_t)(pr.lo >> 32), (uint32_t)pr.hi, (uint32_t)(pr.hi >> 32)};
+        lds_put16(&s.stage[q], v);
+        const uint32_t qr = (uint32_t)(q - q0);
+        if (qr < 16u) {
+            const U128 sh = shl_bytes(pr, qr);
+            head.lo |= sh.lo;
+            head.hi |= sh.hi;
+        }
+        q += (int)(l0 + l1);
+        if ((j & 3) == 2) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
 template <typename S>
-__device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const uint32_t (&lenp)[2], int& q, int qend) {
+__device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const uint32_t (&lenp)[2], int& q, int q0,
+                                                  U128& head) {
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const uint32_t l = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
         const u32x4 v = tok[j];
-        if (q + 16 <= qend) {
-            lds_put16(&s.stage[q], v);
-        } else {
-            const uint64_t lo = ((uint64_t)v.y << 32) | v.x, hi = ((uint64_t)v.w << 32) | v.z;
-            const uint32_t o8 = l & 8u, o4 = l & 12u, o2 = l & 14u;   // l in 0..15
-            const uint64_t r = o8 ? hi : lo;
-            if (l & 8u) lds_put8(&s.stage[q], lo);
-            if (l & 4u) lds_put4(&s.stage[q + (int)o8], (uint32_t)r);
-            const uint64_t r2 = (l & 4u) ? (r >> 32) : r;
-            if (l & 2u) lds_put2(&s.stage[q + (int)o4], (uint32_t)r2);
-            const uint64_t r3 = (l & 2u) ? (r2 >> 16) : r2;
-            if (l & 1u) s.stage[q + (int)o2] = (uint8_t)r3;
+        lds_put16(&s.stage[q], v);
+        const uint32_t qr = (uint32_t)(q - q0);
+        if (qr < 16u && l != 0) {
+            const U128 t = {((uint64_t)v.y << 32) | v.x, ((uint64_t)v.w << 32) | v.z};
+            const U128 sh = shl_bytes(t, qr);
+            head.lo |= sh.lo;
+            head.hi |= sh.hi;
         }
         q += (int)l;
         if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -569,29 +607,45 @@ __device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const 
 }
 
 template <int CODEC, typename S>
-__device__ __forceinline__ void assemble(S& s, const Lane<CODEC>& L, int win) {
+__device__ __forceinline__ void assemble(S& s, const Lane<CODEC>& L, int win, int c, U128& head) {
     using C = Cfg<CODEC>;
-    constexpr int P = C::P;
     constexpr uint32_t K = kWin - C::CPL * C::W;
     if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
-    int q = (int)(L.lane_pre - s.wbase[win]);
-    const int qend = q + (int)L.tot;
+    // the chunk starts after the lane's earlier chunks
+    uint32_t cbase = 0;
+#pragma unroll
+    for (int cc = 0; cc < C::P; cc++)
+#pragma unroll
+        for (int i = 0; i < C::CPC / 4; i++)
+            if (cc < c) cbase = __builtin_amdgcn_sad_u8(L.lenp[cc][i], 0u, cbase);
+    const int lane0 = (int)(L.lane_pre - s.wbase[win]);
+    int q = lane0 + (int)cbase;
     // opaque copies: keeps the compiler from hoisting every per-code predicate
     // out of the window loop (they would all stay live)
-    uint32_t lit = L.lit, lenp[P][C::CPC / 4], w[P][4];
+    uint32_t lit = L.lit >> (C::CPC * c), lenp[C::CPC / 4], w[4];
     asm volatile("" : "+v"(lit));
 #pragma unroll
-    for (int c = 0; c < P; c++) {
+    for (int i = 0; i < C::CPC / 4; i++) { lenp[i] = L.lenp[c][i]; asm volatile("" : "+v"(lenp[i])); }
 #pragma unroll
-        for (int i = 0; i < C::CPC / 4; i++) { lenp[c][i] = L.lenp[c][i]; asm volatile("" : "+v"(lenp[c][i])); }
-#pragma unroll
-        for (int i = 0; i < 4; i++) { w[c][i] = L.w[c][i]; asm volatile("" : "+v"(w[c][i])); }
-    }
-#pragma unroll
-    for (int c = 0; c < P; c++) {
-        if constexpr (CODEC == kFsst8) fsst_chunk_emit(s, w[c], lit >> (16 * c), lenp[c], q, qend);
-        else onpair_chunk_emit(s, &L.tok[c * 8], lenp[c], q, qend);
-    }
+    for (int i = 0; i < 4; i++) { w[i] = L.w[c][i]; asm volatile("" : "+v"(w[i])); }
+    if constexpr (CODEC == kFsst8) fsst_chunk_emit(s, w, lit, lenp, q, lane0, head);
+    else onpair_chunk_emit(s, &L.tok[c * 8], lenp, q, lane0, head);
+}
+
+// After every lane of the workgroup has assembled window `win`: each lane's
+// first 16 bytes, overwritten by the excess of the lane before, are written
+// back from `head`.  The first lane of a window has nothing to repair (and is
+// the only lane that can start with codes outside the range).
+template <int CODEC, typename S>
+__device__ __forceinline__ void fixup(S& s, const Lane<CODEC>& L, int win, const U128& head) {
+    using C = Cfg<CODEC>;
+    constexpr uint32_t K = kWin - C::CPL * C::W;
+    if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
+    const int lane0 = (int)(L.lane_pre - s.wbase[win]);
+    if (lane0 == 0) return;
+    const u32x4 v = {(uint32_t)head.lo, (uint32_t)(head.lo >> 32), (uint32_t)head.hi, (uint32_t)(head.hi >> 32)};
+    if (L.tot >= 16) lds_put16(&s.stage[lane0], v);
+    else lds_put_exact16(&s.stage[lane0], v, L.tot);
 }
 
 // Drain window `win` (super-pass output bytes [wbase[win], wbase[win+1]))
@@ -609,14 +663,29 @@ __device__ __forceinline__ void drain(S& s, const DecodeParams& p, int64_t O, in
     const int nch = (shift + len + 15) >> 4;
     for (int c = threadIdx.x; c < nch; c += kWG) {
         const int s0 = c * 16 - shift;
-        const int lo = max(s0, 0), hi = min(s0 + 16, hi_all);
-        if (lo == s0 && hi == s0 + 16) {
+        if (s0 >= 0 && s0 + 16 <= hi_all) {
+            // five dword-aligned LDS reads realigned in registers (a byte-granular
+            // 16-byte LDS read costs several times as much)
+            const uint32_t* sw = (const uint32_t*)&s.stage[s0 & ~3];
+            const uint32_t r = (uint32_t)s0 & 3u;
+            const uint32_t d0 = sw[0], d1 = sw[1], d2 = sw[2], d3 = sw[3], d4 = sw[4];
             u32x4 v;
-            __builtin_memcpy(&v, &s.stage[s0], 16);
+            v.x = __builtin_amdgcn_alignbyte(d1, d0, r);
+            v.y = __builtin_amdgcn_alignbyte(d2, d1, r);
+            v.z = __builtin_amdgcn_alignbyte(d3, d2, r);
+            v.w = __builtin_amdgcn_alignbyte(d4, d3, r);
             __builtin_nontemporal_store(v, (u32x4*)(p.out + X + s0));
-        } else {
-            for (int y = lo; y < hi; y++) p.out[X + y] = s.stage[y];
         }
+    }
+    // the partial chunks: the first one and the one holding the last byte
+    // below the capacity, one byte per lane
+    if (threadIdx.x < 32 && hi_all > 0) {
+        const int c_last = (shift + hi_all - 1) >> 4;
+        const int c = threadIdx.x < 16 ? 0 : c_last;
+        const int s0 = c * 16 - shift;
+        const bool full = s0 >= 0 && s0 + 16 <= hi_all;
+        const int y = s0 + (int)(threadIdx.x & 15u);
+        if (!full && (threadIdx.x < 16 || c_last != 0) && y >= 0 && y < hi_all) p.out[X + y] = s.stage[y];
     }
 }
 
@@ -668,6 +737,8 @@ __device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom&
 struct LookBack {
     uint64_t in_v;      // this lane's in-block aggregate (first round)
     uint64_t blk_v;     // this lane's block state (first round)
+    uint64_t inb = 0;   // sum of the earlier tiles of the block, once known
+    bool inb_ok = false;
 };
 
 __device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
@@ -684,6 +755,29 @@ __device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t,
     if (idx >= 0) lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Midway through the tile's assembly: when the first-round aggregates of the
+// earlier tiles of the block have all arrived, their sum is known, and the last
+// tile of a block publishes the block aggregate now rather than after its own
+// assembly (the next block's tiles look for it at about the same time).  Values
+// still missing or stale are loaded again, so that the completion finds them.
+__device__ __forceinline__ void lookback_mid(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
+    const unsigned lane = threadIdx.x & 63;
+    const int64_t blk = t >> kBlkShift;
+    const int jt = (int)(t & (kBlk - 1));
+    if (__ballot((lb.in_v & kFlagMask) == 0) == 0) {
+        lb.inb = wave_sum_u64(lb.in_v & kValueMask);
+        lb.inb_ok = true;
+        if (jt == kBlk - 1 && lane == 0)
+            __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagAgg | (lb.inb + A)), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    } else if ((int)lane < jt) {
+        lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int64_t idx = blk - 1 - (int64_t)lane;
+    if (idx >= 0 && (lb.blk_v & kFlagMask) != kFlagIncl)
+        lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Completes the look-back; returns the exclusive prefix of tile t.
 __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64_t t, uint64_t A, LookBack lb) {
     const unsigned lane = threadIdx.x & 63;
@@ -691,19 +785,24 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
     const int jt = (int)(t & (kBlk - 1));
     bool fail = false;
     uint32_t spins = 0;
-    uint64_t inb = 0;
-    for (;;) {
+    uint64_t inb = lb.inb;
+    for (; !lb.inb_ok;) {
         if (__ballot((lb.in_v & kFlagMask) == 0) == 0) {
             inb = wave_sum_u64(lb.in_v & kValueMask);
             break;
         }
         if (++spins >= kSpinLimit) { fail = true; break; }
         __builtin_amdgcn_s_sleep(1);
+        // both first-round values again in one round trip (the block states read
+        // at issue are as stale as the tile aggregates)
         if ((int)lane < jt)
             lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t idx = blk - 1 - (int64_t)lane;
+        if (idx >= 0 && (lb.blk_v & kFlagMask) != kFlagIncl)
+            lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (jt == kBlk - 1 && lane == 0)
+    if (!lb.inb_ok && jt == kBlk - 1 && lane == 0)
         __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagAgg | (inb + A)), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     uint64_t bb = 0;
@@ -734,6 +833,11 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
                            __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
+
+// Waves per SIMD the decode kernels are compiled for: four FSST-8 workgroups
+// per CU (128 VGPRs); OnPair-16 keeps its 64 registers of gathered token
+// entries and runs three.
+template <int CODEC> constexpr int kMinWaves = CODEC == kFsst8 ? 4 : 3;
 
 // --------------------------------------------------------------------------
 // where a launch's tiles come from: one column, or a batch of columns whose
@@ -784,13 +888,16 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     const int64_t n_all = src.n_tiles();
     unsigned* const ctr = src.counter();
 
-    // ---- prologue: the first two tiles of this workgroup ----
-    if (tid == 0) {
-        s.nb[0] = (int64_t)atomicAdd(ctr, 1u);
-        s.nb[1] = (int64_t)atomicAdd(ctr, 1u);
-    }
+    // ---- prologue: the first tile of this workgroup ----
+    // A workgroup requests its next tile only once the current tile's cursor is
+    // known, and loads it during the current tile's drain: tiles then start in
+    // about the order of their ids, so a tile's look-back finds its
+    // predecessors' totals already published (requesting tiles further ahead
+    // spreads the start of consecutive tiles over a whole tile's time, and the
+    // look-back waits for the latest of them).
+    if (tid == 0) s.nb[0] = (int64_t)atomicAdd(ctr, 1u);
     __syncthreads();
-    int64_t v = uniform64(s.nb[0]), vn = uniform64(s.nb[1]);   // global tile ids
+    int64_t v = uniform64(s.nb[0]);                          // global tile id
     __syncthreads();
     int col = 0, table_col = -1;
     if (v < n_all) col = src.column(v, 0);
@@ -819,16 +926,8 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             CODEC == kOnpair16 ? (const void*)p.tok_len : (const void*)p.codes, CODEC == kOnpair16 ? 65536u : 0u);
         const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
             CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes, CODEC == kOnpair16 ? 65536u * 16u : 0u);
-        // the tile after this one, and its column
-        const bool has_next = vn < n_all;
-        const int coln = has_next ? src.column(vn, col) : col;
-        const int64_t tn = vn - src.first(coln);
-        const DecodeParams& pn = src.params(coln);
-
-        // (A) the tile's code offsets into LDS, validation, id of the tile after the next
-        // (the atomic's result is only needed at the end of the iteration)
-        uint32_t nid = 0;
-        if (tid == 0) nid = atomicAdd(ctr, 1u);
+        // (A) the tile's code offsets into LDS, validation
+        uint32_t nid = 0;               // the next tile's id (requested once the cursor is known)
         int64_t cur_reg = 0;
 #pragma unroll
         for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
@@ -849,21 +948,17 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             bad = __syncthreads_or(bad);
             if (bad && tid == 0) record_error(p.err, kRankOffsets, FD_EOFFSETS);
         }
-        if (has_next) coff_load<CODEC, IDX>(pn, tn, cr);       // next tile's offsets (in flight)
 
         // One super-pass (the common case): lengths, look-back issued, window 0
         // assembled, next tile prefetched, look-back completed, drain, offsets.
         // Several super-passes: the lengths of all of them first (tile total,
         // blocking look-back), then each super-pass again with its emit.
         Lane<CODEC> L;
-        int64_t nc0 = 0, nc1 = 0;      // first / last code offset of the next tile
-        uint32_t wn[P][4];
         uint32_t carry = 0;
         int64_t cursor = 0;
         uint64_t tile_total = 0, sp_base = 0;
         const int nsp = g.nsp;
         const int iters = nsp <= 1 ? 1 : 2 * nsp;
-        bool prefetched = false;
         for (int it = 0; it < iters; it++) {
             const bool counting = nsp > 1 && it < nsp;
             const int sp = nsp <= 1 ? 0 : (counting ? it : it - nsp);
@@ -895,11 +990,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                     }
                     __syncthreads();
                     cursor = uniform64(s.cursor);
+                    if (tid == 0) nid = atomicAdd(ctr, 1u);
                 }
                 continue;
             }
             const bool single = nsp <= 1;
             LookBack lb{};
+            U128 head{0, 0};            // the lane's first 16 output bytes in the window being assembled
             if (single) {
                 tile_total = tsp;
                 if constexpr (MODE == kModeTotals) {
@@ -909,15 +1006,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 }
             }
             if constexpr (MODE != kModeTotals) {
-                if (nsp >= 1) assemble<CODEC>(s, L, 0);
-            }
-            if (!prefetched) {
-                prefetched = true;
-                if (has_next) {
-                    const Geom gn = geom_from_regs<CODEC>(s, pn, tn, cr);     // one barrier
-                    nc0 = uniform64(s.nb[0]);
-                    nc1 = uniform64(s.nb[1]);
-                    codes_load<CODEC>(pn, gn, 0, wn);
+                if (nsp >= 1) {
+                    assemble<CODEC>(s, L, 0, 0, head);
+                    if constexpr (MODE == kModeLookback) {
+                        if (single && wv == 0) lookback_mid(p, t, tsp, lb);
+                    }
+#pragma unroll
+                    for (int c = 1; c < P; c++) assemble<CODEC>(s, L, 0, c, head);
                 }
             }
             if (single) {
@@ -931,6 +1026,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 }
             }
             __syncthreads();
+            if (single && tid == 0) nid = atomicAdd(ctr, 1u);
             if constexpr (MODE != kModeTotals) {
                 if (single) cursor = uniform64(s.cursor);
                 if (nsp >= 1) {
@@ -939,9 +1035,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                     for (int win = 0; win < nwin; win++) {
                         if (win > 0) {
                             __syncthreads();
-                            assemble<CODEC>(s, L, win);
+                            head = U128{0, 0};
+#pragma unroll
+                            for (int c = 0; c < P; c++) assemble<CODEC>(s, L, win, c, head);
                             __syncthreads();
                         }
+                        fixup<CODEC>(s, L, win, head);
+                        __syncthreads();
                         drain(s, p, O, win);
                     }
                     offsets<CODEC, IDX>(s, p, g, sp, O);
@@ -964,15 +1064,16 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         }
         if (tid == 0) s.next_id = (int32_t)nid;
         __syncthreads();
-        if (has_next) g = make_geom<CODEC>(pn, tn, nc0, nc1);
-        v = vn;
-        col = coln;
-        t = tn;
-        vn = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
-#pragma unroll
-        for (int c = 0; c < P; c++)
-#pragma unroll
-            for (int i = 0; i < 4; i++) wc[c][i] = wn[c][i];
+        // the next tile: its offsets, geometry (one barrier) and codes
+        v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+        if (v < n_all) {
+            col = src.column(v, col);
+            t = v - src.first(col);
+            const DecodeParams& pn = src.params(col);
+            coff_load<CODEC, IDX>(pn, t, cr);
+            g = geom_from_regs<CODEC>(s, pn, t, cr);
+            codes_load<CODEC>(pn, g, 0, wc);
+        }
     }
 }
 
@@ -981,7 +1082,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
 // offset width (the statuses of a batch are collected by k_batch_status)
 // --------------------------------------------------------------------------
 template <int CODEC, typename IDX, int MODE>
-__global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
+__global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode(DecodeParams p) {
     __shared__ SmemT<CODEC> s;
     decode_tiles<CODEC, IDX, MODE>(s, OneColumn{p});
 
@@ -1002,7 +1103,7 @@ __global__ void __launch_bounds__(kWG) k_decode(DecodeParams p) {
 }
 
 template <int CODEC, typename IDX>
-__global__ void __launch_bounds__(kWG) k_decode_batch(const DecodeParams* __restrict__ cols,
+__global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode_batch(const DecodeParams* __restrict__ cols,
                                                       const int64_t* __restrict__ first_tile, int32_t n_cols,
                                                       int64_t total, unsigned* ctr) {
     __shared__ SmemT<CODEC> s;
