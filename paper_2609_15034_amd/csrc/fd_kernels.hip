@@ -728,38 +728,80 @@ __device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom&
 }
 
 // --------------------------------------------------------------------------
-// two-level decoupled look-back (wave 0 only).  Block kBlk tiles: a tile sums
-// the aggregates of the earlier tiles of its block, the last tile of a block
-// publishes the block aggregate, and block totals are combined by a decoupled
-// look-back over earlier blocks.  Split in two halves so that the loads of the
-// first round overlap the assembly.
+// decoupled look-back over tiles grouped in blocks of kBlk (wave 0 only).  The
+// exclusive prefix of tile t of block b is the sum of the aggregates of the
+// earlier tiles of block b plus the inclusive prefix of block b - 1, which
+// comes from the block states (empty, the block's aggregate, or its inclusive
+// prefix) by walking back over aggregates to the first inclusive prefix.  The
+// last tile of a block publishes the block's aggregate and then its inclusive
+// prefix.  With PREV, a tile that finds block b - 1's state still empty sums
+// the aggregates of that block's kBlk tiles instead (each published as soon as
+// its tile knew its total, long before the block's last tile learns the
+// block's), and the first kHelpers tiles of block b also publish block b - 1's
+// inclusive prefix.  Publishers of one state all write the same value; a state
+// overwritten by an older kind is still correct.  Split in parts so that the
+// loads of the first round overlap the assembly.
 // --------------------------------------------------------------------------
+constexpr int kHelpers = 2;
+
 struct LookBack {
-    uint64_t in_v;      // this lane's in-block aggregate (first round)
-    uint64_t blk_v;     // this lane's block state (first round)
+    uint64_t in_v;      // lane l: aggregate of tile l of the block (l < jt)
+    uint64_t prev_v;    // lane l: aggregate of tile l of the previous block
+    uint64_t blk_v;     // lane l: state of block b - 1 - l
     uint64_t inb = 0;   // sum of the earlier tiles of the block, once known
     bool inb_ok = false;
 };
 
+__device__ __forceinline__ uint64_t lb_load(const unsigned long long* a) {
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void lb_publish(unsigned long long* a, uint64_t v) {
+    __hip_atomic_store(a, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the missing values of the first round, again (one round trip)
+template <bool PREV>
+__device__ __forceinline__ void lb_reload(const DecodeParams& p, int64_t blk, int jt, LookBack& lb) {
+    const unsigned lane = threadIdx.x & 63;
+    if ((int)lane < jt && (lb.in_v & kFlagMask) == 0) lb.in_v = lb_load(&p.tagg[(blk << kBlkShift) + lane]);
+    if (PREV && blk >= 1 && (lb.prev_v & kFlagMask) == 0)
+        lb.prev_v = lb_load(&p.tagg[((blk - 1) << kBlkShift) + lane]);
+    const int64_t idx = blk - 1 - (int64_t)lane;
+    if (idx >= 0 && (lb.blk_v & kFlagMask) != kFlagIncl) lb.blk_v = lb_load(&p.bstate[idx]);
+}
+
+template <bool PREV>
 __device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
     const unsigned lane = threadIdx.x & 63;
     const int64_t blk = t >> kBlkShift;
     const int jt = (int)(t & (kBlk - 1));
     if (lane == 0)
         __hip_atomic_store(&p.tagg[t], (unsigned long long)(kFlagAgg | A), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    lb.in_v = kFlagAgg;
-    if ((int)lane < jt)
-        lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t idx = blk - 1 - (int64_t)lane;
-    lb.blk_v = kFlagIncl;
-    if (idx >= 0) lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // values that are not needed start as found (an aggregate of 0 / an
+    // inclusive prefix of 0), the others as empty
+    lb.in_v = (int)lane < jt ? 0ull : kFlagAgg;
+    lb.prev_v = PREV && blk >= 1 ? 0ull : kFlagAgg;
+    lb.blk_v = blk - 1 - (int64_t)lane >= 0 ? 0ull : kFlagIncl;
+    lb_reload<PREV>(p, blk, jt, lb);
 }
 
-// Midway through the tile's assembly: when the first-round aggregates of the
-// earlier tiles of the block have all arrived, their sum is known, and the last
-// tile of a block publishes the block aggregate now rather than after its own
-// assembly (the next block's tiles look for it at about the same time).  Values
-// still missing or stale are loaded again, so that the completion finds them.
+// Block b - 1's aggregate from its tiles, when its state is still empty and
+// every tile's aggregate has arrived (lane 0 holds block b - 1's state).
+__device__ __forceinline__ bool lb_prev_from_tiles(LookBack& lb, uint64_t& agg) {
+    const unsigned lane = threadIdx.x & 63;
+    const uint64_t v0 = __shfl(lb.blk_v, 0);
+    if ((v0 & kFlagMask) != 0 || __ballot((lb.prev_v & kFlagMask) == 0) != 0) return false;
+    agg = wave_sum_u64(lb.prev_v & kValueMask);
+    if (lane == 0) lb.blk_v = kFlagAgg | agg;
+    return true;
+}
+
+// Midway through the tile's assembly: the sums known from the first round are
+// taken and published (the block aggregate by the block's last tile, the
+// previous block's aggregate by whoever sees all its tiles), and the values
+// still missing are loaded again.
+template <bool PREV>
 __device__ __forceinline__ void lookback_mid(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
     const unsigned lane = threadIdx.x & 63;
     const int64_t blk = t >> kBlkShift;
@@ -767,18 +809,15 @@ __device__ __forceinline__ void lookback_mid(const DecodeParams& p, int64_t t, u
     if (__ballot((lb.in_v & kFlagMask) == 0) == 0) {
         lb.inb = wave_sum_u64(lb.in_v & kValueMask);
         lb.inb_ok = true;
-        if (jt == kBlk - 1 && lane == 0)
-            __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagAgg | (lb.inb + A)), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    } else if ((int)lane < jt) {
-        lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (jt == kBlk - 1 && lane == 0) lb_publish(&p.bstate[blk], kFlagAgg | (lb.inb + A));
     }
-    const int64_t idx = blk - 1 - (int64_t)lane;
-    if (idx >= 0 && (lb.blk_v & kFlagMask) != kFlagIncl)
-        lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t agg;
+    if (PREV && blk >= 1) (void)lb_prev_from_tiles(lb, agg);
+    lb_reload<PREV>(p, blk, jt, lb);
 }
 
 // Completes the look-back; returns the exclusive prefix of tile t.
+template <bool PREV>
 __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64_t t, uint64_t A, LookBack lb) {
     const unsigned lane = threadIdx.x & 63;
     const int64_t blk = t >> kBlkShift;
@@ -793,22 +832,17 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
         }
         if (++spins >= kSpinLimit) { fail = true; break; }
         __builtin_amdgcn_s_sleep(1);
-        // both first-round values again in one round trip (the block states read
-        // at issue are as stale as the tile aggregates)
-        if ((int)lane < jt)
-            lb.in_v = __hip_atomic_load(&p.tagg[(blk << kBlkShift) + lane], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-        const int64_t idx = blk - 1 - (int64_t)lane;
-        if (idx >= 0 && (lb.blk_v & kFlagMask) != kFlagIncl)
-            lb.blk_v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        lb_reload<PREV>(p, blk, jt, lb);     // all first-round values in one round trip
     }
-    if (!lb.inb_ok && jt == kBlk - 1 && lane == 0)
-        __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagAgg | (inb + A)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    if (!lb.inb_ok && jt == kBlk - 1 && lane == 0) lb_publish(&p.bstate[blk], kFlagAgg | (inb + A));
+    // walk back over the block states: lane l holds block j - l
     uint64_t bb = 0;
     int64_t j = blk - 1;
-    uint64_t v = lb.blk_v;
+    bool prev_incl = false;              // block b - 1's inclusive prefix was published
     while (j >= 0 && !fail) {
+        uint64_t agg;
+        if (PREV && j == blk - 1) (void)lb_prev_from_tiles(lb, agg);
+        const uint64_t v = lb.blk_v;
         const uint64_t fl = v & kFlagMask;
         const uint64_t incl = __ballot(fl == kFlagIncl);
         const uint64_t empty = __ballot(fl == 0);
@@ -817,20 +851,28 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
         if (empty & need) {
             if (++spins >= kSpinLimit) { fail = true; break; }
             __builtin_amdgcn_s_sleep(1);
+            if (j == blk - 1) {
+                lb_reload<PREV>(p, blk, 0, lb);
+            } else {
+                const int64_t idx = j - (int64_t)lane;
+                if (idx >= 0 && fl != kFlagIncl) lb.blk_v = lb_load(&p.bstate[idx]);
+            }
         } else {
+            if (j == blk - 1 && (incl & 1ull)) prev_incl = true;
             bb += wave_sum_u64(((int)lane <= first) ? (v & kValueMask) : 0ull);
             if (incl) break;
             j -= 64;
+            const int64_t idx = j - (int64_t)lane;
+            lb.blk_v = kFlagIncl;
+            if (idx >= 0) lb.blk_v = lb_load(&p.bstate[idx]);
         }
-        const int64_t idx = j - (int64_t)lane;
-        v = kFlagIncl;
-        if (idx >= 0) v = __hip_atomic_load(&p.bstate[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (fail && lane == 0) record_error(p.err, kRankInternal, FD_EHIP);
     const uint64_t excl = bb + inb;
-    if (jt == kBlk - 1 && lane == 0)
-        __hip_atomic_store(&p.bstate[blk], (unsigned long long)(kFlagIncl | (excl + A)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    if (!fail && lane == 0) {
+        if (PREV && blk >= 1 && !prev_incl && jt < kHelpers) lb_publish(&p.bstate[blk - 1], kFlagIncl | bb);
+        if (jt == kBlk - 1) lb_publish(&p.bstate[blk], kFlagIncl | (excl + A));
+    }
     return excl;
 }
 
@@ -838,6 +880,11 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
 // per CU (128 VGPRs); OnPair-16 keeps its 64 registers of gathered token
 // entries and runs three.
 template <int CODEC> constexpr int kMinWaves = CODEC == kFsst8 ? 4 : 3;
+
+// Whether the look-back sums the previous block's tiles (measured: FSST-8
+// gains, OnPair-16, whose tiles publish later and wait mostly inside their
+// own block, loses to the extra loads).
+template <int CODEC> constexpr bool kPrevTiles = CODEC == kFsst8;
 
 // --------------------------------------------------------------------------
 // where a launch's tiles come from: one column, or a batch of columns whose
@@ -981,8 +1028,8 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                     } else if constexpr (MODE == kModeLookback) {
                         if (wv == 0) {
                             LookBack lb;
-                            lookback_issue(p, t, tile_total, lb);
-                            const uint64_t ex = lookback_finish(p, t, tile_total, lb);
+                            lookback_issue<kPrevTiles<CODEC>>(p, t, tile_total, lb);
+                            const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tile_total, lb);
                             if (tid == 0) s.cursor = (int64_t)ex;
                         }
                     } else {
@@ -1002,14 +1049,14 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 if constexpr (MODE == kModeTotals) {
                     if (tid == 0) p.tagg[t] = tsp;
                 } else if constexpr (MODE == kModeLookback) {
-                    if (wv == 0) lookback_issue(p, t, tsp, lb);
+                    if (wv == 0) lookback_issue<kPrevTiles<CODEC>>(p, t, tsp, lb);
                 }
             }
             if constexpr (MODE != kModeTotals) {
                 if (nsp >= 1) {
                     assemble<CODEC>(s, L, 0, 0, head);
                     if constexpr (MODE == kModeLookback) {
-                        if (single && wv == 0) lookback_mid(p, t, tsp, lb);
+                        if (single && wv == 0) lookback_mid<kPrevTiles<CODEC>>(p, t, tsp, lb);
                     }
 #pragma unroll
                     for (int c = 1; c < P; c++) assemble<CODEC>(s, L, 0, c, head);
@@ -1018,7 +1065,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             if (single) {
                 if constexpr (MODE == kModeLookback) {
                     if (wv == 0) {
-                        const uint64_t ex = lookback_finish(p, t, tsp, lb);
+                        const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tsp, lb);
                         if (tid == 0) s.cursor = (int64_t)ex;
                     }
                 } else if constexpr (MODE == kModeExpand) {
