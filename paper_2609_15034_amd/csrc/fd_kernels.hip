@@ -198,6 +198,7 @@ template <int CODEC> struct SmemT {
     uint64_t fsst_tab[CODEC == kFsst8 ? 256 : 1];
     uint8_t fsst_len[CODEC == kFsst8 ? 256 : 4];
     uint32_t wsum[kNWave];
+    uint32_t wlast[kNWave];               // total of each wave's last lane
     uint32_t wpar[kNWave];
     int64_t nb[2];                        // first / last code offset of the next tile
     int64_t cursor;
@@ -484,7 +485,10 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
     wave_record_error(p.err, errkey);
     L.tot = tot;
     const uint32_t incl = wave_incl_scan(tot);
-    if (lane == 63) s.wsum[wv] = incl;
+    if (lane == 63) {
+        s.wsum[wv] = incl;
+        s.wlast[wv] = tot;
+    }
     __builtin_memcpy(&s.pre8[tid * P * CPC], pre8w, P * CPC);
 #pragma unroll
     for (int c = 0; c < P; c++) s.cbase[tid * P + c] = cb[c];
@@ -498,12 +502,14 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
     }
     L.lane_pre = basew + incl - tot;
     s.lane_pre[tid] = L.lane_pre;
-    __syncthreads();
-    // staging windows: window of a lane = lane_pre / K; first lanes record bases
+    // staging windows: window of a lane = lane_pre / K; first lanes record bases.
+    // The previous lane's prefix is this one's minus its total.
     {
         constexpr uint32_t K = kWin - C::CPL * C::W;   // a lane writes at most CPL * W bytes
         const uint32_t wl = L.lane_pre / K;
-        const uint32_t wprev = tid ? s.lane_pre[tid - 1] / K : 0xffffffffu;
+        const uint32_t tprev = __shfl_up(tot, 1u);
+        const uint32_t pprev = lane ? L.lane_pre - tprev : (wv ? basew - s.wlast[wv - 1] : 0u);
+        const uint32_t wprev = tid ? pprev / K : 0xffffffffu;
         if (wl != wprev) s.wbase[wl] = L.lane_pre;
         if (tid == kWG - 1) {
             s.nwin = wl + 1;
@@ -886,6 +892,12 @@ template <int CODEC> constexpr int kMinWaves = CODEC == kFsst8 ? 4 : 3;
 // own block, loses to the extra loads).
 template <int CODEC> constexpr bool kPrevTiles = CODEC == kFsst8;
 
+// Whether the next tile's id is requested before the look-back completes and
+// its offsets are loaded before the drain (FSST-8), or the id once the cursor
+// is known and the offsets after the drain (OnPair-16, whose look-back waits
+// longer and varies more: requesting earlier lets tiles start out of order).
+template <int CODEC> constexpr bool kEarlyNext = CODEC == kFsst8;
+
 // --------------------------------------------------------------------------
 // where a launch's tiles come from: one column, or a batch of columns whose
 // tiles are numbered consecutively (column c owns ids first_tile[c] ..
@@ -936,12 +948,12 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     unsigned* const ctr = src.counter();
 
     // ---- prologue: the first tile of this workgroup ----
-    // A workgroup requests its next tile only once the current tile's cursor is
-    // known, and loads it during the current tile's drain: tiles then start in
-    // about the order of their ids, so a tile's look-back finds its
-    // predecessors' totals already published (requesting tiles further ahead
-    // spreads the start of consecutive tiles over a whole tile's time, and the
-    // look-back waits for the latest of them).
+    // A workgroup requests its next tile only as the current tile's look-back
+    // completes, and loads its offsets during the current tile's drain: tiles
+    // then start in about the order of their ids, so a tile's look-back finds
+    // its predecessors' totals already published (requesting tiles further
+    // ahead spreads the start of consecutive tiles over a whole tile's time,
+    // and the look-back waits for the latest of them).
     if (tid == 0) s.nb[0] = (int64_t)atomicAdd(ctr, 1u);
     __syncthreads();
     int64_t v = uniform64(s.nb[0]);                          // global tile id
@@ -974,7 +986,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
             CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes, CODEC == kOnpair16 ? 65536u * 16u : 0u);
         // (A) the tile's code offsets into LDS, validation
-        uint32_t nid = 0;               // the next tile's id (requested once the cursor is known)
+        uint32_t nid = 0;               // the next tile's id (requested as the look-back completes)
         int64_t cur_reg = 0;
 #pragma unroll
         for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
@@ -992,8 +1004,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 if (t == 0 && s.coff[0] < 0) bad = true;
                 if (g.i0 + g.ns == p.n_strings && s.coff[g.ns] > p.n_codes) bad = true;
             }
-            bad = __syncthreads_or(bad);
-            if (bad && tid == 0) record_error(p.err, kRankOffsets, FD_EOFFSETS);
+            if (bad) record_error(p.err, kRankOffsets, FD_EOFFSETS);
         }
 
         // One super-pass (the common case): lengths, look-back issued, window 0
@@ -1001,6 +1012,8 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         // Several super-passes: the lengths of all of them first (tile total,
         // blocking look-back), then each super-pass again with its emit.
         Lane<CODEC> L;
+        int64_t nv = n_all, nt = 0;     // the next tile (known from the cursor barrier on)
+        int ncol = col;
         uint32_t carry = 0;
         int64_t cursor = 0;
         uint64_t tile_total = 0, sp_base = 0;
@@ -1023,6 +1036,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             if (counting) {
                 tile_total += tsp;
                 if (it == nsp - 1) {
+                    if (kEarlyNext<CODEC> && tid == 0) nid = atomicAdd(ctr, 1u);
                     if constexpr (MODE == kModeTotals) {
                         if (tid == 0) p.tagg[t] = tile_total;
                     } else if constexpr (MODE == kModeLookback) {
@@ -1035,9 +1049,19 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                     } else {
                         if (tid == 0) s.cursor = cur_reg;
                     }
+                    if (kEarlyNext<CODEC> && tid == 0) s.next_id = (int32_t)nid;
                     __syncthreads();
                     cursor = uniform64(s.cursor);
-                    if (tid == 0) nid = atomicAdd(ctr, 1u);
+                    if constexpr (kEarlyNext<CODEC>) {
+                        nv = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+                        if (nv < n_all) {
+                            ncol = src.column(nv, col);
+                            nt = nv - src.first(ncol);
+                            coff_load<CODEC, IDX>(src.params(ncol), nt, cr);
+                        }
+                    } else {
+                        if (tid == 0) nid = atomicAdd(ctr, 1u);
+                    }
                 }
                 continue;
             }
@@ -1063,6 +1087,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 }
             }
             if (single) {
+                if (kEarlyNext<CODEC> && tid == 0) nid = atomicAdd(ctr, 1u);
                 if constexpr (MODE == kModeLookback) {
                     if (wv == 0) {
                         const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tsp, lb);
@@ -1071,9 +1096,21 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 } else if constexpr (MODE == kModeExpand) {
                     if (tid == 0) s.cursor = cur_reg;
                 }
+                if (kEarlyNext<CODEC> && tid == 0) s.next_id = (int32_t)nid;
             }
             __syncthreads();
-            if (single && tid == 0) nid = atomicAdd(ctr, 1u);
+            if (single) {
+                if constexpr (kEarlyNext<CODEC>) {
+                    nv = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+                    if (nv < n_all) {
+                        ncol = src.column(nv, col);
+                        nt = nv - src.first(ncol);
+                        coff_load<CODEC, IDX>(src.params(ncol), nt, cr);
+                    }
+                } else {
+                    if (tid == 0) nid = atomicAdd(ctr, 1u);
+                }
+            }
             if constexpr (MODE != kModeTotals) {
                 if (single) cursor = uniform64(s.cursor);
                 if (nsp >= 1) {
@@ -1092,7 +1129,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                         drain(s, p, O, win);
                     }
                     offsets<CODEC, IDX>(s, p, g, sp, O);
-                    __syncthreads();
+                    if (it + 1 < iters) __syncthreads();     // the next super-pass rewrites the prefixes
                 }
             }
             sp_base += tsp;
@@ -1109,15 +1146,23 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 if (endv > p.out_cap) record_error(p.err, kRankCapacity, FD_ECAPACITY);
             }
         }
-        if (tid == 0) s.next_id = (int32_t)nid;
-        __syncthreads();
-        // the next tile: its offsets, geometry (one barrier) and codes
-        v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+        if constexpr (!kEarlyNext<CODEC>) {
+            if (tid == 0) s.next_id = (int32_t)nid;
+            __syncthreads();
+            nv = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+            if (nv < n_all) {
+                ncol = src.column(nv, col);
+                nt = nv - src.first(ncol);
+                coff_load<CODEC, IDX>(src.params(ncol), nt, cr);
+            }
+        }
+        // the next tile: geometry from its offsets (with kEarlyNext loaded since
+        // the cursor barrier; its barrier also ends this tile's use of LDS) and codes
+        v = nv;
         if (v < n_all) {
-            col = src.column(v, col);
-            t = v - src.first(col);
+            col = ncol;
+            t = nt;
             const DecodeParams& pn = src.params(col);
-            coff_load<CODEC, IDX>(pn, t, cr);
             g = geom_from_regs<CODEC>(s, pn, t, cr);
             codes_load<CODEC>(pn, g, 0, wc);
         }
