@@ -244,9 +244,12 @@ def run_batch(steps: int, warmup: int, seed: int | None, n_cols: int = 256, max_
 
 
 def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budget: int = 16 * 10**9,
-              n_slots: int = 4, max_batch: int = 64, check: bool = True, n_chunks: int = 128):
+              n_slots: int = 4, max_batch: int = 64, check: bool = True, n_chunks: int = 128,
+              sat_load: float = 1.5):
     """The served workload: Poisson arrivals at `load` x the server's measured
-    batch capacity; returns a result dict with p50 / p99 latency."""
+    batch capacity (latency at a moderate load), then at `sat_load` x capacity
+    (offered above capacity: the served rate the server sustains).  Returns a
+    result dict with p50 / p99 latency."""
     import threading
     import numpy as np
     import torch
@@ -260,16 +263,8 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
     dicts = [fd.Dict(codec, torch.from_numpy(db).to(dev), torch.from_numpy(dl).to(dev))
              for codec, db, dl in pool.dicts]
     inputs = [_upload_column(c, dev) for c in pool.chunks]
-    rng = np.random.default_rng((seed or 5) + 1)
-    pick = rng.integers(0, len(pool.chunks), size=n_requests)
-    reqs = []
-    for i in pick:
-        c = pool.chunks[i]
-        out = torch.empty(c.decoded_bytes, dtype=torch.uint8, device=dev)
-        out_off = torch.empty(c.n_strings + 1, dtype=inputs[i][1].dtype, device=dev)
-        reqs.append((dicts[pool.chunk_dict[i]], inputs[i][0], inputs[i][1], out_off, out))
     texts = [torch.from_numpy(c.text).to(dev) for c in pool.chunks] if check else None
-    sizes = np.array([pool.chunks[i].decoded_bytes for i in pick], np.float64)
+    pool_bytes = sum(c.decoded_bytes for c in pool.chunks)
     # capacity: the whole pool as one batch
     tups = [(dicts[pool.chunk_dict[i]], inputs[i][0], inputs[i][1],
              torch.empty(c.n_strings + 1, dtype=inputs[i][1].dtype, device=dev),
@@ -279,58 +274,88 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
     cap_s, _ = _events_time(lambda: fd.batch_decode(tups, ws, tuning=tu, async_=True,
                                                     status=torch.zeros(len(tups) + 1, dtype=torch.int32,
                                                                        device=dev)), 5, 2)
-    cap_bps = sum(c.decoded_bytes for c in pool.chunks) / cap_s
-    rate = load * cap_bps / sizes.mean()                        # requests per second
-    gaps = rng.exponential(1.0 / rate, size=n_requests)
-    arrivals = np.cumsum(gaps) - gaps[0]
-    log(f"[serve] capacity {cap_bps / 1e9:.1f} GB/s, offered {load * cap_bps / 1e9:.1f} GB/s = "
-        f"{rate:.0f} requests/s")
-    torch.cuda.synchronize()
-    tickets = [0] * n_requests
-    with fd.Server(max_inflight_bytes=budget, n_slots=n_slots, max_batch=max_batch) as srv:
-        t_start = time.perf_counter()
+    cap_bps = pool_bytes / cap_s
+    # the same chunks one call each (no batching): the rate a request loop without batching reaches
+    st1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    wss = [fd.alloc_workspace(c.codec, inputs[i][0].numel(), c.n_strings) for i, c in enumerate(pool.chunks)]
 
-        def producer():
-            for k in range(n_requests):
-                dt = arrivals[k] - (time.perf_counter() - t_start)
-                if dt > 0:
-                    time.sleep(dt)
-                tickets[k] = srv.submit(reqs[k])
-        th = threading.Thread(target=producer)
-        th.start()
-        th.join()
-        res = [srv.wait(t) for t in tickets]
-        wall = time.perf_counter() - t_start
-        stats = srv.stats()
-    sts = np.array([r[0] for r in res])
-    lat = np.array([r[1] for r in res]) / 1e3                    # ms
-    if np.any(sts != 0):
-        raise fd.DecodeError(int(sts[sts != 0][0]), "served decode")
-    bit_exact = None
-    if check:
-        ok = True
-        for k, i in enumerate(pick):
-            ok &= bool(torch.equal(reqs[k][4], texts[i]))
-        bit_exact = ok
-    # steady window: drop the first 5% of requests (arrival times) from the rate and the latencies
-    k0 = n_requests // 20
-    completion = arrivals + lat / 1e3
-    t_end = max(float(completion.max()), wall)
-    D = float(sizes[k0:].sum())
-    rate_window = t_end - float(arrivals[k0])
-    lat = lat[k0:]
-    out = {"value": round(D / rate_window / 1e9, 2), "unit": "GB/s", "n_requests": n_requests,
-           "steady_window": f"requests {k0}..{n_requests - 1} (first 5% dropped)", "load": load,
-           "offered_GBps": round(load * cap_bps / 1e9, 2), "batch_capacity_GBps": round(cap_bps / 1e9, 2),
-           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                          "p99": round(float(np.percentile(lat, 99)), 3),
-                          "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
-           "mean_request_MB": round(float(sizes.mean()) / 1e6, 2), "budget_bytes": budget,
-           "max_inflight_bytes": stats["max_inflight_bytes"], "batches": stats["batches"],
-           "mean_batch": round(stats["admitted"] / max(stats["batches"], 1), 2), "slots": n_slots,
-           "bit_exact": bit_exact}
-    log(f"[serve] {out['value']} GB/s, p50 {out['latency_ms']['p50']} ms, p99 {out['latency_ms']['p99']} ms, "
-        f"mean batch {out['mean_batch']}")
+    def one_each():
+        for i in range(len(pool.chunks)):
+            fd.decode_into(tups[i][0], tups[i][1], tups[i][2], tups[i][3], tups[i][4], wss[i], status=st1,
+                           async_=True)
+    each_s, _ = _events_time(one_each, 3, 1)
+    each_bps = pool_bytes / each_s
+    del wss
+    log(f"[serve] pool as one batch {cap_bps / 1e9:.1f} GB/s; one call per chunk {each_bps / 1e9:.1f} GB/s")
+
+    def serve_once(ld, n_req, rseed):
+        rng = np.random.default_rng(rseed)
+        pick = rng.integers(0, len(pool.chunks), size=n_req)
+        reqs = []
+        for i in pick:
+            c = pool.chunks[i]
+            out = torch.empty(c.decoded_bytes, dtype=torch.uint8, device=dev)
+            out_off = torch.empty(c.n_strings + 1, dtype=inputs[i][1].dtype, device=dev)
+            reqs.append((dicts[pool.chunk_dict[i]], inputs[i][0], inputs[i][1], out_off, out))
+        sizes = np.array([pool.chunks[i].decoded_bytes for i in pick], np.float64)
+        rate = ld * cap_bps / sizes.mean()                        # requests per second
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        log(f"[serve] load {ld}: offered {ld * cap_bps / 1e9:.1f} GB/s = {rate:.0f} requests/s")
+        torch.cuda.synchronize()
+        tickets = [0] * n_req
+        with fd.Server(max_inflight_bytes=budget, n_slots=n_slots, max_batch=max_batch) as srv:
+            t_start = time.perf_counter()
+
+            def producer():
+                for k in range(n_req):
+                    dt = arrivals[k] - (time.perf_counter() - t_start)
+                    if dt > 0:
+                        time.sleep(dt)
+                    tickets[k] = srv.submit(reqs[k])
+            th = threading.Thread(target=producer)
+            th.start()
+            th.join()
+            res = [srv.wait(t) for t in tickets]
+            wall = time.perf_counter() - t_start
+            stats = srv.stats()
+        sts = np.array([r[0] for r in res])
+        lat = np.array([r[1] for r in res]) / 1e3                    # ms
+        if np.any(sts != 0):
+            raise fd.DecodeError(int(sts[sts != 0][0]), "served decode")
+        bit_exact = None
+        if check:
+            ok = True
+            for k, i in enumerate(pick):
+                ok &= bool(torch.equal(reqs[k][4], texts[i]))
+            bit_exact = ok
+        # steady window: drop the first 5% of requests (arrival times) from the rate and the latencies
+        k0 = n_req // 20
+        completion = arrivals + lat / 1e3
+        t_end = max(float(completion.max()), wall)
+        D = float(sizes[k0:].sum())
+        rate_window = t_end - float(arrivals[k0])
+        lat = lat[k0:]
+        out = {"value": round(D / rate_window / 1e9, 2), "unit": "GB/s", "n_requests": n_req,
+               "steady_window": f"requests {k0}..{n_req - 1} (first 5% dropped)", "load": ld,
+               "offered_GBps": round(ld * cap_bps / 1e9, 2),
+               "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                              "p99": round(float(np.percentile(lat, 99)), 3),
+                              "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+               "mean_request_MB": round(float(sizes.mean()) / 1e6, 2),
+               "max_inflight_bytes": stats["max_inflight_bytes"], "batches": stats["batches"],
+               "mean_batch": round(stats["admitted"] / max(stats["batches"], 1), 2), "bit_exact": bit_exact}
+        log(f"[serve] load {ld}: {out['value']} GB/s, p50 {out['latency_ms']['p50']} ms, "
+            f"p99 {out['latency_ms']['p99']} ms, mean batch {out['mean_batch']}")
+        return out
+
+    out = serve_once(load, n_requests, (seed or 5) + 1)
+    sat = serve_once(sat_load, n_requests, (seed or 5) + 2)
+    out.update({"batch_capacity_GBps": round(cap_bps / 1e9, 2), "one_call_per_chunk_GBps": round(each_bps / 1e9, 2),
+                "budget_bytes": budget, "slots": n_slots,
+                "saturated": {k: sat[k] for k in ("value", "load", "offered_GBps", "latency_ms", "mean_batch",
+                                                  "batches", "max_inflight_bytes", "bit_exact")},
+                "saturated_over_capacity": round(sat["value"] * 1e9 / cap_bps, 3)})
     return out
 
 

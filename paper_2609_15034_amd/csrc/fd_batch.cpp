@@ -162,11 +162,13 @@ void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* 
     }
 }
 
-// Enqueue a planned batch whose table image is in pinned memory `host`.
+// Enqueue a planned batch whose table image is in pinned memory `host`;
+// `copied` (optional) is recorded once the image has been copied.
 hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* ws, const uint8_t* host,
-                   int32_t* status, hipStream_t st) {
+                   int32_t* status, hipStream_t st, hipEvent_t copied = nullptr) {
     hipError_t e = hipMemcpyAsync(ws + pl.off_table, host, pl.table_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
+    if (copied && (e = hipEventRecord(copied, st)) != hipSuccess) return e;
     unsigned long long* errs = (unsigned long long*)(ws + pl.off_errs);
     e = launch_batch_reset((unsigned long long*)ws, (int64_t)(pl.states_end / 8), errs, n, st);
     if (e != hipSuccess) return e;
@@ -186,7 +188,10 @@ hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
     return launch_batch_status(errs, n, status, (int32_t*)(ws + kBOffStatus), st);
 }
 
-// ---- pinned staging for the table image (reused once its last copy is done) ----
+// ---- pinned staging for the table image: a ring per device, each buffer
+// reused once the copy that read it is done (not the whole batch), so that
+// the host prepares the next batch while earlier ones run ----
+constexpr int kRing = 8;
 struct Staging {
     uint8_t* buf = nullptr;
     size_t cap = 0;
@@ -201,7 +206,8 @@ struct GraphEntry {
 };
 
 std::mutex g_bmu;
-Staging g_stage[64];
+Staging g_stage[64][kRing];
+int g_stage_next[64];
 std::unordered_map<uint64_t, int> g_tuned;                  // shape -> scale (percent)
 std::list<std::pair<uint64_t, GraphEntry>> g_graphs;        // most recent first
 constexpr size_t kMaxGraphs = 16;
@@ -243,7 +249,8 @@ uint64_t exact_key(const fd_column* cols, int32_t n, const void* ws, size_t ws_b
 // Plan and enqueue one batch decode (no graph), staging the table in pinned memory.
 fd_status run_once(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* ws, int32_t* status,
                    hipStream_t st, int dev) {
-    Staging& sg = g_stage[dev];
+    Staging& sg = g_stage[dev][g_stage_next[dev]];
+    g_stage_next[dev] = (g_stage_next[dev] + 1) % kRing;
     if (sg.pending) {
         if (hipEventSynchronize(sg.done) != hipSuccess) return FD_EHIP;
         sg.pending = false;
@@ -258,8 +265,7 @@ fd_status run_once(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
     }
     if (!sg.done && hipEventCreateWithFlags(&sg.done, hipEventDisableTiming) != hipSuccess) return FD_EHIP;
     fill_table(cols, n, pl, ws, sg.buf);
-    if (enqueue(cols, n, pl, ws, sg.buf, status, st) != hipSuccess) return FD_EHIP;
-    if (hipEventRecord(sg.done, st) != hipSuccess) return FD_EHIP;
+    if (enqueue(cols, n, pl, ws, sg.buf, status, st, sg.done) != hipSuccess) return FD_EHIP;
     sg.pending = true;
     return FD_OK;
 }

@@ -169,7 +169,7 @@ __device__ __forceinline__ uint32_t bits_to_byte_msb(uint32_t nib) { return (nib
 // --------------------------------------------------------------------------
 // configuration
 // --------------------------------------------------------------------------
-constexpr int kMaxWin = 8;    // staging windows per super-pass, at most (64 KiB / (kWin - 256) + 1 = 5)
+constexpr int kMaxWin = 8;    // staging windows per super-pass, at most (64 KiB / (WIN - 256) + 1 = 5)
 template <int CODEC> struct Cfg;
 template <> struct Cfg<kFsst8> {
     static constexpr int CB = 1;      // bytes per code
@@ -178,6 +178,7 @@ template <> struct Cfg<kFsst8> {
     static constexpr int CPL = 32;    // codes per lane
     static constexpr int W = 8;       // bytes written per token (fixed-stride entry)
     static constexpr int SB = kSbMaxFsst;
+    static constexpr int WIN = kWinFsst;   // LDS staging window (bytes)
 };
 template <> struct Cfg<kOnpair16> {
     static constexpr int CB = 2;
@@ -186,11 +187,12 @@ template <> struct Cfg<kOnpair16> {
     static constexpr int CPL = 16;
     static constexpr int W = 16;
     static constexpr int SB = kSbMax;
+    static constexpr int WIN = kWinOnpair;
 };
 
 template <int CODEC> struct SmemT {
     static constexpr int P = Cfg<CODEC>::P, CPC = Cfg<CODEC>::CPC, SB = Cfg<CODEC>::SB;
-    uint8_t stage[kWin + 16];             // staging window (+16: slack for the drain's 16-byte reads)
+    uint8_t stage[Cfg<CODEC>::WIN + 16];  // staging window (+16: slack for the drain's 16-byte reads)
     uint8_t pre8[kWG * P * CPC];          // per code: prefix inside its chunk | escape bit
     uint32_t lane_pre[kWG];               // per lane: exclusive prefix inside the super-pass
     uint16_t cbase[kWG * P];              // per chunk: prefix inside its lane
@@ -318,32 +320,47 @@ template <int CODEC> struct Lane {
 // escape code 255.
 template <typename S>
 __device__ void fsst_build_table(S& s, const DecodeParams& p) {
+    constexpr int CPT = 256 / kWG;     // codes per thread, consecutive
     const unsigned tid = threadIdx.x;
-    const unsigned c = tid;            // kWG == 256: one code per thread
-    uint32_t len = 0;
+    uint32_t len[CPT], tl = 0;
     bool bad = false;
-    if ((int)c < p.n_sym) {
-        len = p.dict_lens[c];
-        bad = (len == 0 || len > 8);
+#pragma unroll
+    for (int i = 0; i < CPT; i++) {
+        const int c = (int)tid * CPT + i;
+        len[i] = 0;
+        if (c < p.n_sym) {
+            len[i] = p.dict_lens[c];
+            bad |= (len[i] == 0 || len[i] > 8);
+        }
+        tl += len[i];
     }
     bad = __syncthreads_or(bad);
     if (bad) {
         if (tid == 0) record_error(p.err, kRankDict, FD_EBADDICT);
-        s.fsst_tab[c] = 0;
-        s.fsst_len[c] = (c == 255) ? 0 : 0x80;
+#pragma unroll
+        for (int i = 0; i < CPT; i++) {
+            const int c = (int)tid * CPT + i;
+            s.fsst_tab[c] = 0;
+            s.fsst_len[c] = (c == 255) ? 0 : 0x80;
+        }
         __syncthreads();
         return;
     }
     const unsigned lane = tid & 63, wv = tid >> 6;
-    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t incl = wave_incl_scan(tl);
     if (lane == 63) s.wsum[wv] = incl;
     __syncthreads();
-    uint32_t start = incl - len;
+    uint32_t start = incl - tl;
     for (unsigned i = 0; i < wv; i++) start += s.wsum[i];
-    uint64_t v = 0;
-    for (uint32_t j = 0; j < len; j++) v |= (uint64_t)p.dict_bytes[start + j] << (8 * j);
-    s.fsst_tab[c] = v;
-    s.fsst_len[c] = (c == 255) ? 0 : ((int)c < p.n_sym ? (uint8_t)len : (uint8_t)0x80);
+#pragma unroll
+    for (int i = 0; i < CPT; i++) {
+        const int c = (int)tid * CPT + i;
+        uint64_t v = 0;
+        for (uint32_t j = 0; j < len[i]; j++) v |= (uint64_t)p.dict_bytes[start + j] << (8 * j);
+        start += len[i];
+        s.fsst_tab[c] = v;
+        s.fsst_len[c] = (c == 255) ? 0 : (c < p.n_sym ? (uint8_t)len[i] : (uint8_t)0x80);
+    }
     __syncthreads();
 }
 
@@ -405,7 +422,7 @@ __device__ __forceinline__ uint32_t onpair_chunk_lengths(const uint32_t (&lv)[8]
 // lane_pre and the staging windows to LDS and returns the super-pass total.
 // `carry` is the FSST-8 escape parity entering the super-pass (updated).
 // Windows are runs of whole lanes: lane l belongs to window lane_pre / K with
-// K = kWin - (largest lane output), so no lane straddles a window edge.
+// K = WIN - (largest lane output), so no lane straddles a window edge.
 // --------------------------------------------------------------------------
 template <int CODEC, typename S>
 __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const Geom& g, int sp, Lane<CODEC>& L,
@@ -505,7 +522,7 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
     // staging windows: window of a lane = lane_pre / K; first lanes record bases.
     // The previous lane's prefix is this one's minus its total.
     {
-        constexpr uint32_t K = kWin - C::CPL * C::W;   // a lane writes at most CPL * W bytes
+        constexpr uint32_t K = C::WIN - C::CPL * C::W;   // a lane writes at most CPL * W bytes
         const uint32_t wl = L.lane_pre / K;
         const uint32_t tprev = __shfl_up(tot, 1u);
         const uint32_t pprev = lane ? L.lane_pre - tprev : (wv ? basew - s.wlast[wv - 1] : 0u);
@@ -615,7 +632,7 @@ __device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const 
 template <int CODEC, typename S>
 __device__ __forceinline__ void assemble(S& s, const Lane<CODEC>& L, int win, int c, U128& head) {
     using C = Cfg<CODEC>;
-    constexpr uint32_t K = kWin - C::CPL * C::W;
+    constexpr uint32_t K = C::WIN - C::CPL * C::W;
     if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
     // the chunk starts after the lane's earlier chunks
     uint32_t cbase = 0;
@@ -645,7 +662,7 @@ __device__ __forceinline__ void assemble(S& s, const Lane<CODEC>& L, int win, in
 template <int CODEC, typename S>
 __device__ __forceinline__ void fixup(S& s, const Lane<CODEC>& L, int win, const U128& head) {
     using C = Cfg<CODEC>;
-    constexpr uint32_t K = kWin - C::CPL * C::W;
+    constexpr uint32_t K = C::WIN - C::CPL * C::W;
     if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
     const int lane0 = (int)(L.lane_pre - s.wbase[win]);
     if (lane0 == 0) return;
