@@ -142,6 +142,8 @@ void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* 
             p.dict_bytes = col.dict->bytes;
             p.dict_lens = col.dict->lens;
             p.n_sym = col.dict->n;
+            p.fsst_tab = col.dict->fsst_tab;
+            p.fsst_len = col.dict->fsst_len;
             p.tok16 = col.dict->tok16;
             p.tok_len = col.dict->tok_len;
             p.out_off = col.out_offsets;

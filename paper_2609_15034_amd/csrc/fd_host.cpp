@@ -195,6 +195,8 @@ fd_status run_decode(const Args& a) {
             p.dict_bytes = a.dict->bytes;
             p.dict_lens = a.dict->lens;
             p.n_sym = a.dict->n;
+            p.fsst_tab = a.dict->fsst_tab;
+            p.fsst_len = a.dict->fsst_len;
         } else {
             p.dict_bytes = a.dict_bytes;
             p.dict_lens = a.dict_lens;
@@ -351,7 +353,7 @@ fd_status fd_dict_create(fd_codec codec, const uint8_t* dict_bytes, const uint8_
     // scratch: err word + bad flag
     const size_t hdr = 256;
     size_t bytes;
-    if (codec == FD_FSST8) bytes = hdr + 256 + 255 * 8;
+    if (codec == FD_FSST8) bytes = hdr + 256 + 255 * 8 + 8 + 256 * 8 + 256;
     else bytes = hdr + kTok16Bytes + kTokLenBytes;
     if (hipMalloc(&d->mem, bytes) != hipSuccess) { delete d; return FD_ENOMEM; }
     uint8_t* m = (uint8_t*)d->mem;
@@ -374,6 +376,39 @@ fd_status fd_dict_create(fd_codec codec, const uint8_t* dict_bytes, const uint8_
             }
             if (hipMemcpyAsync(lens, dict_lens, (size_t)n_tokens, hipMemcpyDeviceToDevice, st) != hipSuccess) goto fail;
             if (sum && hipMemcpyAsync(syms, dict_bytes, sum, hipMemcpyDeviceToDevice, st) != hipSuccess) goto fail;
+        }
+        // the decode table in the layout the kernels keep in LDS, built once here
+        {
+            uint8_t hl[256] = {0}, hs[256 * 8] = {0};
+            if (n_tokens > 0) {
+                if (hipMemcpyAsync(hl, dict_lens, (size_t)n_tokens, hipMemcpyDeviceToHost, st) != hipSuccess) goto fail;
+                if (hipStreamSynchronize(st) != hipSuccess) goto fail;
+                size_t sum = 0;
+                for (int i = 0; i < n_tokens; i++) sum += hl[i];
+                if (sum && hipMemcpyAsync(hs, dict_bytes, sum, hipMemcpyDeviceToHost, st) != hipSuccess) goto fail;
+                if (hipStreamSynchronize(st) != hipSuccess) goto fail;
+            }
+            unsigned long long* tab = (unsigned long long*)(m + hdr + 256 + 255 * 8 + 8);
+            uint8_t* tl = (uint8_t*)(tab + 256);
+            // host images, uploaded before this function returns (it synchronizes below)
+            unsigned long long htab[256] = {0};
+            uint8_t htl[256];
+            size_t at = 0;
+            for (int c = 0; c < 256; c++) {
+                if (c < n_tokens) {
+                    for (int j = 0; j < hl[c]; j++) htab[c] |= (unsigned long long)hs[at + j] << (8 * j);
+                    at += hl[c];
+                    htl[c] = hl[c];
+                } else {
+                    htl[c] = 0x80;
+                }
+                if (c == 255) htl[c] = 0;
+            }
+            if (hipMemcpyAsync(tab, htab, sizeof(htab), hipMemcpyHostToDevice, st) != hipSuccess) goto fail;
+            if (hipMemcpyAsync(tl, htl, sizeof(htl), hipMemcpyHostToDevice, st) != hipSuccess) goto fail;
+            if (hipStreamSynchronize(st) != hipSuccess) goto fail;
+            d->fsst_tab = tab;
+            d->fsst_len = tl;
         }
         d->lens = lens;
         d->bytes = syms;

@@ -49,6 +49,8 @@ struct DecodeParams {
     const uint8_t* dict_bytes;
     const uint8_t* dict_lens;
     int32_t n_sym;
+    const unsigned long long* fsst_tab;   // prepared table (256 zero-padded symbols), or null
+    const uint8_t* fsst_len;       // prepared lengths (0x80: not a symbol, 0: escape), or null
     // OnPair-16: prepared fixed-stride dictionary
     const uint4* tok16;
     const uint8_t* tok_len;
@@ -101,6 +103,8 @@ struct fd_dict {
     void* mem;              // single device allocation owned by the handle
     const uint8_t* bytes;   // FSST-8: packed symbols (copy)
     const uint8_t* lens;    // FSST-8: lengths (copy)
+    const unsigned long long* fsst_tab;   // FSST-8: the decode table, 256 zero-padded 8-byte symbols
+    const uint8_t* fsst_len;              // FSST-8: per code: length, 0x80 if not a symbol, 0 for 255
     const uint4* tok16;     // OnPair-16: fixed 16-byte entries, 65,536 of them
     const uint8_t* tok_len; // OnPair-16: 65,536 lengths (0 = invalid code)
 };

@@ -322,6 +322,16 @@ template <typename S>
 __device__ void fsst_build_table(S& s, const DecodeParams& p) {
     constexpr int CPT = 256 / kWG;     // codes per thread, consecutive
     const unsigned tid = threadIdx.x;
+    if (p.fsst_tab) {                  // prepared with the dictionary: a copy
+#pragma unroll
+        for (int i = 0; i < CPT; i++) {
+            const int c = (int)tid * CPT + i;
+            s.fsst_tab[c] = p.fsst_tab[c];
+            s.fsst_len[c] = p.fsst_len[c];
+        }
+        __syncthreads();
+        return;
+    }
     uint32_t len[CPT], tl = 0;
     bool bad = false;
 #pragma unroll
@@ -976,6 +986,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     int64_t v = uniform64(s.nb[0]);                          // global tile id
     __syncthreads();
     int col = 0, table_col = -1;
+    const void* table_src = nullptr;      // the prepared table in LDS (batches)
     if (v < n_all) col = src.column(v, 0);
     int64_t t = v - src.first(col);                           // tile inside its column
     CoffRegs<CODEC, IDX> cr;
@@ -992,9 +1003,12 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     while (v < n_all) {
         const DecodeParams& p = src.params(col);
         if constexpr (CODEC == kFsst8 && SRC::kBatch) {
-            if (col != table_col) {      // a column of the batch with another table
+            // a column of the batch with another table (columns of one
+            // prepared dictionary share it)
+            if (p.fsst_tab ? (const void*)p.fsst_tab != table_src : col != table_col) {
                 fsst_build_table(s, p);
                 table_col = col;
+                table_src = p.fsst_tab;
             }
         }
         // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
