@@ -105,6 +105,12 @@ bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, in
         g.cols.push_back(c);
         g.total += tiles;
     }
+    // inside a group, columns of one dictionary run back to back: a workgroup
+    // then keeps its LDS table, and the dictionary stays warm in L2
+    // (statuses stay per column, so the order is not visible)
+    for (Group& g : pl->groups)
+        std::stable_sort(g.cols.begin(), g.cols.end(),
+                         [&](int32_t a, int32_t b) { return (uintptr_t)cols[a].dict < (uintptr_t)cols[b].dict; });
     pl->states_end = off;
     pl->off_errs = align_up(off, 256);
     pl->off_table = align_up(pl->off_errs + (size_t)n * 8, 256);
