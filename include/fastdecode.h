@@ -173,8 +173,15 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                        expansion), reading the code stream twice (the
  *                        "sidecar regenerated at decode time" variant the
  *                        paper measures in its design overview).
- *   strings_per_tile  1..512; automatic = about 70% of one pass of codes per
- *                     tile (a pass is 4096 FSST-8 or 2048 OnPair-16 codes).
+ *   strings_per_tile  1..256 (FSST-8) or 1..1024 (OnPair-16); automatic = the
+ *                     most strings whose codes, at the column's mean codes
+ *                     per string plus a margin for their spread, fit one pass
+ *                     (a pass is 8192 FSST-8 or 4096 OnPair-16 codes; a tile
+ *                     with more codes takes several passes, each recomputing
+ *                     the lengths).  The estimate uses n_codes / n_strings,
+ *                     so a decode of a few strings out of a much larger code
+ *                     buffer should pass the codes of its range (rebased
+ *                     offsets) or set strings_per_tile.
  *   grid              workgroups to launch; automatic = all that can be
  *                     resident on the device (they pull tiles from a counter).
  * The decoded result does not depend on the tuning. */

@@ -493,18 +493,31 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
+        // every length first, then every token entry: the lengths (and so the
+        // tile total the look-back publishes) wait only for their own loads
+        uint32_t lv[P][8];
 #pragma unroll
-        for (int c = 0; c < P; c++) {
-            uint32_t lv[8];
+        for (int c = 0; c < P; c++)
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 const uint32_t cj = (L.w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                lv[j] = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
-                if (gather_tokens) L.tok[c * 8 + j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, cj << 4, 0, 0);
+                lv[c][j] = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
             }
+        // (unconditional, also in the counting passes of long tiles: a branch
+        // here would make the waits for the lengths count the token loads)
+        (void)gather_tokens;
+#pragma unroll
+        for (int c = 0; c < P; c++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t cj = (L.w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                L.tok[c * 8 + j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, cj << 4, 0, 0);
+            }
+#pragma unroll
+        for (int c = 0; c < P; c++) {
             uint32_t cbad = 0;
             cb[c] = (uint16_t)tot;
-            tot += onpair_chunk_lengths(lv, L.valid >> (8 * c), pre8w[c], L.lenp[c], cbad);
+            tot += onpair_chunk_lengths(lv[c], L.valid >> (8 * c), pre8w[c], L.lenp[c], cbad);
             bad |= cbad << (8 * c);
         }
     }
