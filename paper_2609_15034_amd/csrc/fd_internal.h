@@ -14,7 +14,7 @@ constexpr int kOnpair16 = FD_ONPAIR16;
 constexpr int kWG = 256;            // threads per workgroup
 constexpr int kNWave = kWG / 64;    // waves per workgroup
 constexpr int kWinFsst = 16384;     // LDS staging window (bytes), FSST-8
-constexpr int kWinOnpair = 16384;   // LDS staging window (bytes), OnPair-16
+constexpr int kWinOnpair = 32768;   // LDS staging window (bytes), OnPair-16 (3 workgroups per CU by VGPRs: room for a pass)
 constexpr int kSbMax = 1024;        // strings per tile, at most (OnPair-16)
 constexpr int kSbMaxFsst = 256;     // strings per tile, at most (FSST-8)
 constexpr int kBlkShift = 6;        // tiles per look-back block: 64
