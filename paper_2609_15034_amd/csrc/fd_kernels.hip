@@ -789,6 +789,7 @@ __device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom&
 // loads of the first round overlap the assembly.
 // --------------------------------------------------------------------------
 constexpr int kHelpers = 2;
+static_assert(kBlk <= 64, "one lane of wave 0 per tile of a block");
 
 struct LookBack {
     uint64_t in_v;      // lane l: aggregate of tile l of the block (l < jt)
@@ -811,7 +812,7 @@ template <bool PREV>
 __device__ __forceinline__ void lb_reload(const DecodeParams& p, int64_t blk, int jt, LookBack& lb) {
     const unsigned lane = threadIdx.x & 63;
     if ((int)lane < jt && (lb.in_v & kFlagMask) == 0) lb.in_v = lb_load(&p.tagg[(blk << kBlkShift) + lane]);
-    if (PREV && blk >= 1 && (lb.prev_v & kFlagMask) == 0)
+    if (PREV && blk >= 1 && (int)lane < kBlk && (lb.prev_v & kFlagMask) == 0)
         lb.prev_v = lb_load(&p.tagg[((blk - 1) << kBlkShift) + lane]);
     const int64_t idx = blk - 1 - (int64_t)lane;
     if (idx >= 0 && (lb.blk_v & kFlagMask) != kFlagIncl) lb.blk_v = lb_load(&p.bstate[idx]);
@@ -827,7 +828,7 @@ __device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t,
     // values that are not needed start as found (an aggregate of 0 / an
     // inclusive prefix of 0), the others as empty
     lb.in_v = (int)lane < jt ? 0ull : kFlagAgg;
-    lb.prev_v = PREV && blk >= 1 ? 0ull : kFlagAgg;
+    lb.prev_v = PREV && blk >= 1 && (int)lane < kBlk ? 0ull : kFlagAgg;
     lb.blk_v = blk - 1 - (int64_t)lane >= 0 ? 0ull : kFlagIncl;
     lb_reload<PREV>(p, blk, jt, lb);
 }
