@@ -598,14 +598,21 @@ __device__ __forceinline__ U128 shl_bytes(U128 v, uint32_t o) {
 template <typename S>
 __device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], uint32_t lit, const uint32_t (&lenp)[4],
                                                 int& q, int q0, U128& head) {
+    // the table reads run one pair ahead of the writes (source order keeps
+    // them ahead: the compiler cannot tell the staging and the table apart)
+    uint64_t n0 = s.fsst_tab[w[0] & 0xffu], n1 = s.fsst_tab[(w[0] >> 8) & 0xffu];
 #pragma unroll
     for (int j = 0; j < 16; j += 2) {
         const uint32_t l0 = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
         const uint32_t l1 = (lenp[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xffu;
         const uint32_t b0 = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
         const uint32_t b1 = (w[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xffu;
-        uint64_t v0 = s.fsst_tab[b0];
-        uint64_t v1 = s.fsst_tab[b1];
+        uint64_t v0 = n0;
+        uint64_t v1 = n1;
+        if (j + 2 < 16) {
+            n0 = s.fsst_tab[(w[(j + 2) >> 2] >> (8 * ((j + 2) & 3))) & 0xffu];
+            n1 = s.fsst_tab[(w[(j + 3) >> 2] >> (8 * ((j + 3) & 3))) & 0xffu];
+        }
         if ((lit >> j) & 1u) v0 = b0;
         if ((lit >> (j + 1)) & 1u) v1 = b1;
         if (l0 == 0) v0 = 0;                  // codes outside the range carry no bytes
