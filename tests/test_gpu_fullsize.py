@@ -1,0 +1,99 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (automatic tiling, resident grid, asynchronous status):
+
+- the 1 GiB FSST-8 log column and the 1 GiB OnPair-16 URL column: the whole
+  output must equal the generator's source text and offsets (decoding is
+  lossless, so that is the expected result at any size), and sampled runs of
+  strings across the column are checked against the oracle one run at a time;
+- the 256-column batch (2.26 GB) as one replayed graph: every column equals its
+  source text, and sampled runs of each of a few columns match the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_15034_amd as fd
+    fd.lib()
+    yield
+
+
+def sample_runs(n_strings, rng, n_runs=40, run=50):
+    """Runs of consecutive strings: the first, the last and random ones."""
+    starts = [0, max(0, n_strings - run)] + list(rng.integers(0, max(1, n_strings - run), size=n_runs))
+    return [(int(a), int(min(n_strings, a + run))) for a in starts]
+
+
+def check_runs_against_oracle(col, out_off, out, rng, n_runs=40):
+    import oracle
+    co = col.code_off.astype(np.int64)
+    for a, b in sample_runs(col.n_strings, rng, n_runs):
+        c0, c1 = int(co[a]), int(co[b])
+        exp = oracle.decode(col.codec, col.codes[c0:c1], co[a:b + 1] - c0, col.dict_bytes, col.dict_lens)
+        assert exp.status == 0
+        rel = out_off[a:b + 1] - out_off[a]
+        assert np.array_equal(rel, exp.out_off), (col.name, a, b)
+        assert np.array_equal(out[int(out_off[a]):int(out_off[b])], exp.out_bytes), (col.name, a, b)
+
+
+@pytest.mark.parametrize("workload,seed", [("fsst_logs", 2), ("onpair_urls", 3)])
+def test_full_column(datagen_mod, oracle_mod, workload, seed):
+    import torch
+    import paper_2609_15034_amd as fd
+    col = getattr(datagen_mod, workload)(seed=seed)
+    print(f"{workload}: {col.stats}", flush=True)
+    dev = torch.device("cuda")
+    codes = torch.from_numpy(col.codes if col.codec == "fsst8" else col.codes.view(np.int16)).to(dev)
+    code_off = torch.from_numpy(col.code_off).to(dev)
+    d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
+    guard = 4096
+    buf = torch.full((col.decoded_bytes + guard,), 0xA5, dtype=torch.uint8, device=dev)
+    out = buf[:col.decoded_bytes]
+    out_off = torch.full((col.n_strings + 1,), -7, dtype=code_off.dtype, device=dev)
+    ws = fd.alloc_workspace(col.codec, codes.numel(), col.n_strings)
+    status = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    for _ in range(2):        # twice: the second run reuses the workspace as the benchmark does
+        assert fd.decode_into(d, codes, code_off, out_off, out, ws, status=status, async_=True) == fd.OK
+        torch.cuda.synchronize()
+        assert int(status.item()) == fd.OK
+    assert torch.equal(out, torch.from_numpy(col.text).to(dev))
+    assert torch.equal(out_off.to(torch.int64), torch.from_numpy(col.text_off).to(dev))
+    assert bool((buf[col.decoded_bytes:] == 0xA5).all()), "write past the output"
+    rng = np.random.default_rng(seed + 100)
+    check_runs_against_oracle(col, out_off.cpu().numpy().astype(np.int64), out.cpu().numpy(), rng)
+
+
+def test_full_batch(datagen_mod, oracle_mod):
+    import torch
+    import paper_2609_15034_amd as fd
+    cols = datagen_mod.batch_columns(seed=4)
+    dev = torch.device("cuda")
+    tups, bufs = [], []
+    for c in cols:
+        codes = torch.from_numpy(c.codes if c.codec == "fsst8" else c.codes.view(np.int16)).to(dev)
+        code_off = torch.from_numpy(c.code_off).to(dev)
+        d = fd.Dict(c.codec, torch.from_numpy(c.dict_bytes).to(dev), torch.from_numpy(c.dict_lens).to(dev))
+        buf = torch.full((c.decoded_bytes + 64,), 0xA5, dtype=torch.uint8, device=dev)
+        bufs.append(buf)
+        tups.append((d, codes, code_off, torch.full((c.n_strings + 1,), -7, dtype=code_off.dtype, device=dev),
+                     buf[:c.decoded_bytes]))
+    ws = torch.empty(fd.batch_workspace_size(tups, None), dtype=torch.uint8, device=dev)
+    status = torch.full((len(tups) + 1,), -1, dtype=torch.int32, device=dev)
+    for _ in range(3):        # autotune on the first call, then graph replays
+        assert fd.batch_decode(tups, ws, status=status, async_=True, graph=True) == fd.OK
+        torch.cuda.synchronize()
+        assert int(status[-1].item()) == fd.OK
+    assert bool((status == 0).all())
+    for c, t, buf in zip(cols, tups, bufs):
+        assert torch.equal(t[4], torch.from_numpy(c.text).to(dev)), c.name
+        assert torch.equal(t[3].to(torch.int64), torch.from_numpy(c.text_off).to(dev)), c.name
+        assert bool((buf[c.decoded_bytes:] == 0xA5).all()), c.name
+    rng = np.random.default_rng(41)
+    for k in rng.choice(len(cols), size=6, replace=False):
+        c, t = cols[int(k)], tups[int(k)]
+        check_runs_against_oracle(c, t[3].cpu().numpy().astype(np.int64), t[4].cpu().numpy(), rng, n_runs=8)
