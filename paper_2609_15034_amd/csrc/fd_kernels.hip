@@ -493,8 +493,8 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
-        // every length first, then every token entry: the lengths (and so the
-        // tile total the look-back publishes) wait only for their own loads
+        // the token lengths only: the lengths (and so the tile total the
+        // look-back publishes) wait for nothing else
         uint32_t lv[P][8];
 #pragma unroll
         for (int c = 0; c < P; c++)
@@ -503,16 +503,11 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
                 const uint32_t cj = (L.w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
                 lv[c][j] = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
             }
-        // (unconditional, also in the counting passes of long tiles: a branch
-        // here would make the waits for the lengths count the token loads)
+        // (the token entries are gathered by the assembly of the lane's window;
+        // these two parameters are unused but kept: without them the register
+        // allocation of the OnPair-16 kernel changes, from 4 spills to 64-90)
         (void)gather_tokens;
-#pragma unroll
-        for (int c = 0; c < P; c++)
-#pragma unroll
-            for (int j = 0; j < 8; j++) {
-                const uint32_t cj = (L.w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                L.tok[c * 8 + j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, cj << 4, 0, 0);
-            }
+        (void)r_tok;
 #pragma unroll
         for (int c = 0; c < P; c++) {
             uint32_t cbad = 0;
@@ -660,10 +655,22 @@ __device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const 
 }
 
 template <int CODEC, typename S>
-__device__ __forceinline__ void assemble(S& s, const Lane<CODEC>& L, int win, int c, U128& head) {
+__device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, U128& head,
+                                         const __amdgpu_buffer_rsrc_t& r_tok) {
     using C = Cfg<CODEC>;
     constexpr uint32_t K = C::WIN - C::CPL * C::W;
     if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
+    if constexpr (CODEC == kOnpair16) {
+        if (c == 0) {          // the lane's token entries, gathered for its window
+#pragma unroll
+            for (int cc = 0; cc < C::P; cc++)
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const uint32_t cj = (L.w[cc][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                    L.tok[cc * 8 + j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, cj << 4, 0, 0);
+                }
+        }
+    }
     // the chunk starts after the lane's earlier chunks
     uint32_t cbase = 0;
 #pragma unroll
@@ -1130,12 +1137,12 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             }
             if constexpr (MODE != kModeTotals) {
                 if (nsp >= 1) {
-                    assemble<CODEC>(s, L, 0, 0, head);
+                    assemble<CODEC>(s, L, 0, 0, head, r_tok);
                     if constexpr (MODE == kModeLookback) {
                         if (single && wv == 0) lookback_mid<kPrevTiles<CODEC>>(p, t, tsp, lb);
                     }
 #pragma unroll
-                    for (int c = 1; c < P; c++) assemble<CODEC>(s, L, 0, c, head);
+                    for (int c = 1; c < P; c++) assemble<CODEC>(s, L, 0, c, head, r_tok);
                 }
             }
             if (single) {
@@ -1173,7 +1180,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                             __syncthreads();
                             head = U128{0, 0};
 #pragma unroll
-                            for (int c = 0; c < P; c++) assemble<CODEC>(s, L, win, c, head);
+                            for (int c = 0; c < P; c++) assemble<CODEC>(s, L, win, c, head, r_tok);
                             __syncthreads();
                         }
                         fixup<CODEC>(s, L, win, head);
