@@ -953,6 +953,12 @@ template <int CODEC> constexpr bool kPrevTiles = CODEC == kFsst8;
 // longer and varies more: requesting earlier lets tiles start out of order).
 template <int CODEC> constexpr bool kEarlyNext = CODEC == kFsst8;
 
+// The tile counter's top bit: set by a workgroup that meets a tile of several
+// passes.  Such a tile publishes its total late, and with early requests the
+// starts of the tiles after it drift out of order (measured: a convoy), so
+// every workgroup that sees the bit in a returned id requests late from then on.
+constexpr uint32_t kLateBit = 0x80000000u;
+
 // --------------------------------------------------------------------------
 // where a launch's tiles come from: one column, or a batch of columns whose
 // tiles are numbered consecutively (column c owns ids first_tile[c] ..
@@ -1011,7 +1017,9 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     // and the look-back waits for the latest of them).
     if (tid == 0) s.nb[0] = (int64_t)atomicAdd(ctr, 1u);
     __syncthreads();
-    int64_t v = uniform64(s.nb[0]);                          // global tile id
+    const uint32_t raw0 = (uint32_t)uniform64(s.nb[0]);
+    int64_t v = (int64_t)(raw0 & ~kLateBit);                 // global tile id
+    bool late = (raw0 & kLateBit) != 0;                      // request late from now on
     __syncthreads();
     int col = 0, table_col = -1;
     const void* table_src = nullptr;      // the prepared table in LDS (batches)
@@ -1044,6 +1052,9 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             CODEC == kOnpair16 ? (const void*)p.tok_len : (const void*)p.codes, CODEC == kOnpair16 ? 65536u : 0u);
         const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
             CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes, CODEC == kOnpair16 ? 65536u * 16u : 0u);
+        // requests for the next tile: early unless a tile of several passes was seen
+        if (kEarlyNext<CODEC> && g.nsp > 1 && tid == 0 && !late) atomicOr(ctr, kLateBit);
+        const bool early = kEarlyNext<CODEC> && !late;
         // (A) the tile's code offsets into LDS, validation
         uint32_t nid = 0;               // the next tile's id (requested as the look-back completes)
         int64_t cur_reg = 0;
@@ -1095,7 +1106,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             if (counting) {
                 tile_total += tsp;
                 if (it == nsp - 1) {
-                    if (kEarlyNext<CODEC> && tid == 0) nid = atomicAdd(ctr, 1u);
+                    if (early && tid == 0) nid = atomicAdd(ctr, 1u);
                     if constexpr (MODE == kModeTotals) {
                         if (tid == 0) p.tagg[t] = tile_total;
                     } else if constexpr (MODE == kModeLookback) {
@@ -1108,11 +1119,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                     } else {
                         if (tid == 0) s.cursor = cur_reg;
                     }
-                    if (kEarlyNext<CODEC> && tid == 0) s.next_id = (int32_t)nid;
+                    if (early && tid == 0) s.next_id = (int32_t)nid;
                     __syncthreads();
                     cursor = uniform64(s.cursor);
-                    if constexpr (kEarlyNext<CODEC>) {
-                        nv = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+                    if (early) {
+                        const uint32_t raw = uniform32((uint32_t)s.next_id);
+                        nv = (int64_t)(raw & ~kLateBit);
+                        late = late || (raw & kLateBit) != 0;
                         if (nv < n_all) {
                             ncol = src.column(nv, col);
                             nt = nv - src.first(ncol);
@@ -1146,7 +1159,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 }
             }
             if (single) {
-                if (kEarlyNext<CODEC> && tid == 0) nid = atomicAdd(ctr, 1u);
+                if (early && tid == 0) nid = atomicAdd(ctr, 1u);
                 if constexpr (MODE == kModeLookback) {
                     if (wv == 0) {
                         const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tsp, lb);
@@ -1155,12 +1168,14 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 } else if constexpr (MODE == kModeExpand) {
                     if (tid == 0) s.cursor = cur_reg;
                 }
-                if (kEarlyNext<CODEC> && tid == 0) s.next_id = (int32_t)nid;
+                if (early && tid == 0) s.next_id = (int32_t)nid;
             }
             __syncthreads();
             if (single) {
-                if constexpr (kEarlyNext<CODEC>) {
-                    nv = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+                if (early) {
+                    const uint32_t raw = uniform32((uint32_t)s.next_id);
+                    nv = (int64_t)(raw & ~kLateBit);
+                    late = late || (raw & kLateBit) != 0;
                     if (nv < n_all) {
                         ncol = src.column(nv, col);
                         nt = nv - src.first(ncol);
@@ -1205,10 +1220,12 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 if (endv > p.out_cap) record_error(p.err, kRankCapacity, FD_ECAPACITY);
             }
         }
-        if constexpr (!kEarlyNext<CODEC>) {
+        if (!early) {
             if (tid == 0) s.next_id = (int32_t)nid;
             __syncthreads();
-            nv = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+            const uint32_t raw = uniform32((uint32_t)s.next_id);
+            nv = (int64_t)(raw & ~kLateBit);
+            late = late || (raw & kLateBit) != 0;
             if (nv < n_all) {
                 ncol = src.column(nv, col);
                 nt = nv - src.first(ncol);
