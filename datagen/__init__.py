@@ -286,6 +286,51 @@ def onpair_urls(seed: int = 3, target_bytes: int = 1 << 30, sample_bytes: int = 
                   off if keep_text else None, 0, _stats("onpair16", codes, coff, dl, 0, len(text)))
 
 
+def pack_codes12(codes) -> np.ndarray:
+    """Pack codes < 4096 into the 12-bit stream the 12-bit decoders read:
+    least significant bit first, two codes in three bytes (a storage format,
+    vectorised here; the checker has its own one-code-at-a-time unpacker)."""
+    c = np.asarray(codes, dtype=np.uint32)
+    n = len(c)
+    if n % 2:
+        c = np.concatenate([c, np.zeros(1, np.uint32)])
+    a, b = c[0::2], c[1::2]
+    out = np.empty((len(a), 3), np.uint8)
+    out[:, 0] = a & 0xFF
+    out[:, 1] = ((a >> 8) & 0xF) | ((b & 0xF) << 4)
+    out[:, 2] = (b >> 4) & 0xFF
+    return out.reshape(-1)[: (n * 12 + 7) // 8].copy()
+
+
+def _code12_column(name, codes16, coff, db, dl, text, off, keep_text) -> Column:
+    st = _stats("onpair16", codes16, coff, dl, 0, len(text))
+    return Column(name, "onpair12", pack_codes12(codes16), coff, db, dl, text if keep_text else None,
+                  off if keep_text else None, 0, st)
+
+
+def onpair12_urls(seed: int = 6, target_bytes: int = 1 << 30, sample_bytes: int = 4 << 20,
+                  threads: int | None = None, keep_text: bool = True) -> Column:
+    """OnPair-12: the URL / identifier strings of onpair_urls with a 4,096-token
+    dictionary (tokens of 1-16 bytes) and 12-bit packed codes."""
+    st, so = url_strings(seed, sample_bytes, nchunk=16, threads=threads, stream_base=SAMPLE_STREAM)
+    db, dl = onpair_train(st, so, max_tokens=4096, tau=2, max_len=16)
+    text, off = url_strings(seed, target_bytes, threads=threads)
+    codes, coff, _ = encode_onpair(db, dl, text, off, threads)
+    return _code12_column("onpair12_urls", codes, coff, db, dl, text, off, keep_text)
+
+
+def fsst12_logs(seed: int = 7, target_bytes: int = 1 << 30, sample_bytes: int = 1 << 20,
+                threads: int | None = None, keep_text: bool = True) -> Column:
+    """FSST-12: the log lines of fsst_logs with a 4,096-symbol table of 1-8 byte
+    symbols (all 256 single bytes included, so no escapes) and 12-bit packed
+    codes.  It decodes through the 12-bit path like OnPair-12."""
+    st, so = log_lines(seed, sample_bytes, nchunk=4, threads=threads, stream_base=SAMPLE_STREAM)
+    db, dl = onpair_train(st, so, max_tokens=4096, tau=2, max_len=8)
+    text, off = log_lines(seed, target_bytes, threads=threads)
+    codes, coff, _ = encode_onpair(db, dl, text, off, threads)
+    return _code12_column("fsst12_logs", codes, coff, db, dl, text, off, keep_text)
+
+
 def random_onpair(seed: int = 33, n_codes: int = 1 << 16, n_strings: int = 1000, n_tok: int = 65536) -> Column:
     """Random full dictionary with uniform random codes (no text kept)."""
     db, dl = random_dict(seed, n_tok, 16)
@@ -362,4 +407,4 @@ def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 128, min_bytes:
 
 def column_for(name: str, **kw) -> Column:
     return {"fsst_small": fsst_small, "fsst_logs": fsst_logs, "onpair_urls": onpair_urls,
-            "random_onpair": random_onpair}[name](**kw)
+            "random_onpair": random_onpair, "onpair12_urls": onpair12_urls, "fsst12_logs": fsst12_logs}[name](**kw)

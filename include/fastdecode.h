@@ -75,7 +75,7 @@ typedef enum fd_status {
     FD_ENOMEM = 9      /* allocation failed / request exceeds a memory budget     */
 } fd_status;
 
-typedef enum fd_codec { FD_FSST8 = 1, FD_ONPAIR16 = 2 } fd_codec;
+typedef enum fd_codec { FD_FSST8 = 1, FD_ONPAIR16 = 2, FD_ONPAIR12 = 3 } fd_codec;
 
 /* flags */
 #define FD_ASYNC 1u

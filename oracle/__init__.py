@@ -71,10 +71,53 @@ def _as_i64(code_off) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(code_off), dtype=np.int64)
 
 
+def unpack12(packed, n_codes: int) -> np.ndarray:
+    """12-bit codes from their packed byte stream (OnPair-12 / FSST-12, code
+    widths table of the Background section).  The paper widens such codes to
+    16 bits before decoding (Evaluation, pre-decode preparation) and fixes no
+    bit order; the reading here: least significant bit first, code k in bits
+    [12k, 12k + 12) of the stream, so two codes fill three bytes.  Written
+    from that definition, one code at a time."""
+    b = np.ascontiguousarray(packed, dtype=np.uint8)
+    if len(b) * 8 < n_codes * 12:
+        raise ValueError("packed stream shorter than n_codes codes")
+    out = np.zeros(n_codes, np.uint16)
+    for k in range(n_codes):
+        bit = 12 * k
+        byte, sh = bit // 8, bit % 8
+        v = int(b[byte]) | (int(b[byte + 1]) << 8) if byte + 1 < len(b) else int(b[byte])
+        out[k] = (v >> sh) & 0xFFF
+    return out
+
+
+def pack12(codes) -> np.ndarray:
+    """The inverse of unpack12 (test and generator helper): codes < 4096."""
+    c = np.asarray(codes, dtype=np.int64)
+    if len(c) and (c.min() < 0 or c.max() > 0xFFF):
+        raise ValueError("12-bit codes out of range")
+    out = np.zeros((len(c) * 12 + 7) // 8, np.uint8)
+    for k, v in enumerate(c.tolist()):
+        bit = 12 * k
+        byte, sh = bit // 8, bit % 8
+        w = v << sh
+        out[byte] |= w & 0xFF
+        out[byte + 1] |= (w >> 8) & 0xFF
+        if sh and byte + 2 < len(out):
+            out[byte + 2] |= (w >> 16) & 0xFF
+    return out
+
+
 def decode(codec: str, codes, code_off, dict_bytes, dict_lens, index_bits: int | None = None,
-           out_capacity: int | None = None) -> Result:
+           out_capacity: int | None = None, n_codes: int | None = None) -> Result:
     """Decode a whole column.  ``out_capacity=None`` sizes the output exactly
-    (an upper bound is used for the call and the result trimmed)."""
+    (an upper bound is used for the call and the result trimmed).  For
+    "onpair12" ``codes`` is the packed stream and ``n_codes`` its code count
+    (default: every whole code in it); the codes are unpacked (unpack12) and
+    decoded as OnPair-16 codes."""
+    if codec == "onpair12":
+        packed = np.ascontiguousarray(codes, dtype=np.uint8)
+        n = (len(packed) * 8) // 12 if n_codes is None else int(n_codes)
+        return decode("onpair16", unpack12(packed, n), code_off, dict_bytes, dict_lens, index_bits, out_capacity)
     codes = np.ascontiguousarray(codes, dtype=np.uint8 if codec == "fsst8" else np.uint16)
     code_off_arr = np.asarray(code_off)
     if index_bits is None:

@@ -26,7 +26,16 @@ LIB_PATH = os.path.join(HERE, "libfastdecode.so")
 
 FSST8 = 1
 ONPAIR16 = 2
-CODECS = {"fsst8": FSST8, "onpair16": ONPAIR16}
+ONPAIR12 = 3          # 12-bit packed codes (OnPair-12, and FSST-12 with tokens of at most 8 bytes)
+CODECS = {"fsst8": FSST8, "onpair16": ONPAIR16, "onpair12": ONPAIR12}
+
+
+def codes_in(codec, codes) -> int:
+    """The number of codes in a code tensor: its elements, or for 12-bit
+    packed streams (uint8, least significant bit first, two codes in three
+    bytes) the whole codes its bytes hold."""
+    c = CODECS[codec] if isinstance(codec, str) else int(codec)
+    return codes.numel() * 8 // 12 if c == ONPAIR12 else codes.numel()
 ASYNC = 1
 GRAPH = 2
 
@@ -260,7 +269,7 @@ def decode_into(d: Dict, codes, code_off, out_off, out_bytes, workspace, status=
                 tuning=None, stream=None, n_codes=None) -> int:
     """fd_decode_ex with preallocated outputs; returns the fd_status (FD_OK when
     enqueued with async_=True)."""
-    return lib().fd_decode_ex(d.handle, _ptr(codes), int(codes.numel() if n_codes is None else n_codes),
+    return lib().fd_decode_ex(d.handle, _ptr(codes), int(codes_in(d.codec, codes) if n_codes is None else n_codes),
                               _ptr(code_off), _index_bits(code_off), code_off.numel() - 1, _ptr(out_off),
                               _ptr(out_bytes), out_bytes.numel() if out_bytes is not None else 0, _ptr(workspace),
                               workspace.numel(), _ptr(status), ASYNC if async_ else 0, _tuning(tuning),
@@ -272,7 +281,7 @@ def decode(d: Dict, codes, code_off, tuning=None, stream=None):
     first pass with zero capacity to obtain the offsets and the exact size."""
     torch = _torch()
     dev = codes.device
-    ws = alloc_workspace(d.codec, codes.numel(), code_off.numel() - 1, tuning, device=dev)
+    ws = alloc_workspace(d.codec, codes_in(d.codec, codes), code_off.numel() - 1, tuning, device=dev)
     out_off = torch.empty(code_off.numel(), dtype=code_off.dtype, device=dev)
     empty = torch.empty(0, dtype=torch.uint8, device=dev)
     st = decode_into(d, codes, code_off, out_off, empty, ws, tuning=tuning, stream=stream)
@@ -294,7 +303,8 @@ def make_columns(cols):
     tuples of device tensors (out_bytes may be None for capacity 0)."""
     arr = (Column * max(len(cols), 1))()
     for i, (d, codes, code_off, out_off, out_bytes) in enumerate(cols):
-        arr[i] = Column(d.handle.value, codes.data_ptr(), codes.numel(), code_off.data_ptr(), _index_bits(code_off),
+        arr[i] = Column(d.handle.value, codes.data_ptr(), codes_in(d.codec, codes), code_off.data_ptr(),
+                        _index_bits(code_off),
                         code_off.numel() - 1, out_off.data_ptr(), out_bytes.data_ptr() if out_bytes is not None else 0,
                         out_bytes.numel() if out_bytes is not None else 0)
     return arr

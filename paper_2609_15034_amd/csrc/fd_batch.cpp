@@ -28,7 +28,7 @@ namespace {
 
 constexpr size_t kBHdr = 256;          // group tile counters (8 bytes each) and the status word
 constexpr size_t kBOffStatus = 128;
-constexpr int kMaxGroups = 4;          // (codec, offset width) pairs
+constexpr int kMaxGroups = 6;          // (codec, offset width) pairs
 constexpr int32_t kMaxCols = 65536;
 
 // Candidate tile sizes of the autotuner: fractions (percent) of the automatic
@@ -54,13 +54,15 @@ struct BatchPlan {
     size_t off_errs = 0, off_table = 0, table_bytes = 0, bytes = 0;
 };
 
-int group_of(int codec, int index_bits) { return (codec == FD_FSST8 ? 0 : 2) + (index_bits == 64 ? 1 : 0); }
+int group_of(int codec, int index_bits) {
+    return (codec == FD_FSST8 ? 0 : codec == FD_ONPAIR16 ? 2 : 4) + (index_bits == 64 ? 1 : 0);
+}
 
 // Host-visible checks of one column (those of the single-column entry points).
 bool column_ok(const fd_column& c) {
     if (!c.dict) return false;
     const fd_codec codec = c.dict->codec;
-    if (codec != FD_FSST8 && codec != FD_ONPAIR16) return false;
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
     if (c.index_bits != 32 && c.index_bits != 64) return false;
     if (c.n_strings < 0 || c.n_codes < 0 || c.out_capacity < 0) return false;
     if (c.n_strings > (int64_t)1 << 40 || c.n_codes > (int64_t)1 << 40) return false;

@@ -100,7 +100,7 @@ struct Plan {
 
 bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl) {
     if (n_codes < 0 || n_strings < 0) return false;
-    if (codec != FD_FSST8 && codec != FD_ONPAIR16) return false;
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
     const int64_t sb_max = codec == FD_FSST8 ? kSbMaxFsst : kSbMax;
     int64_t sb = tu ? tu->strings_per_tile : 0;
     if (sb < 0 || sb > sb_max) return false;
@@ -161,6 +161,7 @@ fd_status run_decode(const Args& a) {
         if (a.n_dict < 0) return FD_EINVAL;
         if (a.codec == FD_FSST8 && a.n_dict > 255) return FD_EINVAL;
         if (a.codec == FD_ONPAIR16 && a.n_dict > 65536) return FD_EINVAL;
+        if (a.codec == FD_ONPAIR12) return FD_EINVAL;   // 12-bit codes decode with a prepared dictionary only
         if (a.n_dict > 0 && (!a.dict_lens || !a.dict_bytes)) return FD_EINVAL;
     }
     Plan pl;
@@ -279,7 +280,7 @@ fd_status fd_workspace_size(fd_codec codec, int64_t n_codes, int64_t n_strings, 
 fd_status fd_decoded_bound(fd_codec codec, int64_t n_codes, int64_t* bytes) {
     if (!bytes || n_codes < 0) return FD_EINVAL;
     if (codec == FD_FSST8) *bytes = n_codes * 8;
-    else if (codec == FD_ONPAIR16) *bytes = n_codes * 16;
+    else if (codec == FD_ONPAIR16 || codec == FD_ONPAIR12) *bytes = n_codes * 16;
     else return FD_EINVAL;
     return FD_OK;
 }
@@ -339,8 +340,9 @@ fd_status fd_dict_create(fd_codec codec, const uint8_t* dict_bytes, const uint8_
                          void* hip_stream, fd_dict** out) {
     if (!out) return FD_EINVAL;
     *out = nullptr;
-    if (codec != FD_FSST8 && codec != FD_ONPAIR16) return FD_EINVAL;
-    if (n_tokens < 0 || (codec == FD_FSST8 && n_tokens > 255) || (codec == FD_ONPAIR16 && n_tokens > 65536))
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return FD_EINVAL;
+    if (n_tokens < 0 || (codec == FD_FSST8 && n_tokens > 255) || (codec == FD_ONPAIR16 && n_tokens > 65536) ||
+        (codec == FD_ONPAIR12 && n_tokens > 4096))
         return FD_EINVAL;
     if (n_tokens > 0 && (!dict_bytes || !dict_lens)) return FD_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;

@@ -10,6 +10,7 @@ namespace fd {
 
 constexpr int kFsst8 = FD_FSST8;
 constexpr int kOnpair16 = FD_ONPAIR16;
+constexpr int kOnpair12 = FD_ONPAIR12;
 
 constexpr int kWG = 256;            // threads per workgroup
 constexpr int kNWave = kWG / 64;    // waves per workgroup

@@ -189,6 +189,24 @@ template <> struct Cfg<kOnpair16> {
     static constexpr int SB = kSbMax;
     static constexpr int WIN = kWinOnpair;
 };
+// OnPair-12 (and FSST-12: the same decode with tokens of at most 8 bytes):
+// 12-bit codes packed least significant bit first, two codes in three bytes.
+// A chunk is 8 codes = 12 bytes, unpacked at load into the OnPair-16 register
+// layout; everything after the load is the OnPair-16 path.
+template <> struct Cfg<kOnpair12> {
+    static constexpr int CB = 0;      // (not whole bytes: see PACKED)
+    static constexpr int CPC = 8;
+    static constexpr int P = 2;
+    static constexpr int CPL = 16;
+    static constexpr int W = 16;
+    static constexpr int SB = kSbMax;
+    static constexpr int WIN = kWinOnpair;
+};
+template <int CODEC> constexpr bool kPacked12 = CODEC == kOnpair12;
+template <int CODEC> constexpr bool kIsOnpair = CODEC == kOnpair16 || CODEC == kOnpair12;
+
+// bytes of a 12-bit packed stream of n codes
+__host__ __device__ __forceinline__ int64_t packed12_bytes(int64_t n) { return (n * 12 + 7) / 8; }
 
 template <int CODEC> struct SmemT {
     static constexpr int P = Cfg<CODEC>::P, CPC = Cfg<CODEC>::CPC, SB = Cfg<CODEC>::SB;
@@ -230,10 +248,17 @@ __device__ __forceinline__ Geom make_geom(const DecodeParams& p, int64_t t, int6
     g.a = min(max(c_first, (int64_t)0), p.n_codes);
     g.b = min(max(c_last, g.a), p.n_codes);
     const uintptr_t lo = (uintptr_t)p.codes;
-    g.base = (lo + (uintptr_t)g.a * C::CB) & ~(uintptr_t)15;
-    g.nchunk = (g.b > g.a) ? (int64_t)((lo + (uintptr_t)g.b * C::CB - g.base + 15) >> 4) : 0;
+    if constexpr (kPacked12<CODEC>) {
+        // chunks are groups of 8 codes (12 bytes) from the start of the stream
+        g.pos0 = g.a & ~(int64_t)7;
+        g.base = lo + (uintptr_t)(g.pos0 / 8) * 12u;
+        g.nchunk = (g.b > g.a) ? (g.b - g.pos0 + 7) / 8 : 0;
+    } else {
+        g.base = (lo + (uintptr_t)g.a * C::CB) & ~(uintptr_t)15;
+        g.nchunk = (g.b > g.a) ? (int64_t)((lo + (uintptr_t)g.b * C::CB - g.base + 15) >> 4) : 0;
+        g.pos0 = ((int64_t)g.base - (int64_t)lo) / C::CB;
+    }
     g.nsp = (int)((g.nchunk + (int64_t)kWG * C::P - 1) / ((int64_t)kWG * C::P));
-    g.pos0 = ((int64_t)g.base - (int64_t)lo) / C::CB;
     return g;
 }
 
@@ -280,8 +305,44 @@ __device__ __forceinline__ Geom geom_from_regs(S& s, const DecodeParams& p, int6
 template <int CODEC>
 __device__ __forceinline__ void codes_load(const DecodeParams& p, const Geom& g, int sp, uint32_t w[][4]) {
     using C = Cfg<CODEC>;
-    const uintptr_t lo = (uintptr_t)p.codes, hi = lo + (uintptr_t)p.n_codes * C::CB;
     const int64_t k0 = (int64_t)sp * kWG * C::P + (int64_t)threadIdx.x * C::P;
+    if constexpr (kPacked12<CODEC>) {
+        // 12 bytes per chunk; three dword loads when the chunk is whole and
+        // dword-aligned, bytes otherwise (only inside the stream)
+        const uintptr_t lo = (uintptr_t)p.codes, hi = lo + (uintptr_t)packed12_bytes(p.n_codes);
+#pragma unroll
+        for (int c = 0; c < C::P; c++) {
+            const int64_t k = k0 + c;
+            const uintptr_t ca = g.base + (uintptr_t)k * 12u;
+            uint32_t x = 0, y = 0, z = 0;
+            if (k < g.nchunk) {
+                if (ca + 12 <= hi && (ca & 3u) == 0) {
+                    x = __builtin_nontemporal_load((const uint32_t*)ca);
+                    y = __builtin_nontemporal_load((const uint32_t*)(ca + 4));
+                    z = __builtin_nontemporal_load((const uint32_t*)(ca + 8));
+                } else {
+                    uint32_t d[3] = {0, 0, 0};
+#pragma unroll
+                    for (int j = 0; j < 12; j++) {
+                        const uintptr_t a = ca + j;
+                        if (a >= lo && a < hi) d[j >> 2] |= (uint32_t)(*(const uint8_t*)a) << (8 * (j & 3));
+                    }
+                    x = d[0]; y = d[1]; z = d[2];
+                }
+            }
+            // 8 codes of 12 bits, least significant first, into 16-bit halves
+            const uint32_t c0 = x & 0xfffu, c1 = (x >> 12) & 0xfffu;
+            const uint32_t c2 = __builtin_amdgcn_alignbit(y, x, 24) & 0xfffu, c3 = (y >> 4) & 0xfffu;
+            const uint32_t c4 = (y >> 16) & 0xfffu, c5 = __builtin_amdgcn_alignbit(z, y, 28) & 0xfffu;
+            const uint32_t c6 = (z >> 8) & 0xfffu, c7 = z >> 20;
+            w[c][0] = c0 | (c1 << 16);
+            w[c][1] = c2 | (c3 << 16);
+            w[c][2] = c4 | (c5 << 16);
+            w[c][3] = c6 | (c7 << 16);
+        }
+        return;
+    }
+    const uintptr_t lo = (uintptr_t)p.codes, hi = lo + (uintptr_t)p.n_codes * C::CB;
 #pragma unroll
     for (int c = 0; c < C::P; c++) {
         const int64_t k = k0 + c;
@@ -311,7 +372,7 @@ template <int CODEC> struct Lane {
     uint32_t tot;          // decoded bytes of the lane
     uint32_t lane_pre;     // exclusive prefix of the lane inside the super-pass
     uint32_t lenp[P][Cfg<CODEC>::CPC / 4];   // per-code lengths, packed bytes
-    u32x4 tok[CODEC == kOnpair16 ? Cfg<CODEC>::CPL : 1];   // OnPair-16 token entries
+    u32x4 tok[kIsOnpair<CODEC> ? Cfg<CODEC>::CPL : 1];   // OnPair token entries
 };
 
 // Load the FSST-8 table into LDS (once per workgroup).  Lengths 0 / above 8
@@ -660,7 +721,7 @@ __device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, U
     using C = Cfg<CODEC>;
     constexpr uint32_t K = C::WIN - C::CPL * C::W;
     if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
-    if constexpr (CODEC == kOnpair16) {
+    if constexpr (kIsOnpair<CODEC>) {
         if (c == 0) {          // the lane's token entries, gathered for its window
 #pragma unroll
             for (int cc = 0; cc < C::P; cc++)
@@ -755,13 +816,12 @@ __device__ __forceinline__ void drain(S& s, const DecodeParams& p, int64_t O, in
 template <int CODEC, typename IDX, typename S>
 __device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom& g, int sp, int64_t O) {
     using C = Cfg<CODEC>;
-    constexpr int P = C::P, CPC = C::CPC, CB = C::CB, SPC = kWG * C::P;
-    const uintptr_t codes_lo = (uintptr_t)p.codes;
+    constexpr int P = C::P, CPC = C::CPC, SPC = kWG * C::P;
     const int64_t k_lo = (int64_t)sp * SPC, k_hi = k_lo + SPC;
     for (int j = threadIdx.x; j < g.ns; j += kWG) {
         const int64_t st = min(max(s.coff[j], g.a), g.b);
         if (st < g.b) {
-            const int64_t k = (int64_t)((codes_lo + (uintptr_t)st * CB - g.base) >> 4);
+            const int64_t k = (int64_t)((uint64_t)(st - g.pos0) / CPC);
             if (k >= k_lo && k < k_hi) {
                 const int kk = (int)(k - k_lo);
                 const int jj = (int)(st - (g.pos0 + k * CPC));
@@ -775,7 +835,7 @@ __device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom&
             const int64_t en = min(max(s.coff[j + 1], g.a), g.b);
             if (en > st) {
                 const int64_t last = en - 1;
-                const int64_t k = (int64_t)((codes_lo + (uintptr_t)last * CB - g.base) >> 4);
+                const int64_t k = (int64_t)((uint64_t)(last - g.pos0) / CPC);
                 if (k >= k_lo && k < k_hi) {
                     const int kk = (int)(k - k_lo);
                     const int jj = (int)(last - (g.pos0 + k * CPC));
@@ -1049,9 +1109,9 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         }
         // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
         const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
-            CODEC == kOnpair16 ? (const void*)p.tok_len : (const void*)p.codes, CODEC == kOnpair16 ? 65536u : 0u);
+            kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
         const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
-            CODEC == kOnpair16 ? (const void*)p.tok16 : (const void*)p.codes, CODEC == kOnpair16 ? 65536u * 16u : 0u);
+            kIsOnpair<CODEC> ? (const void*)p.tok16 : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u * 16u : 0u);
         // requests for the next tile: early unless a tile of several passes was seen
         if (kEarlyNext<CODEC> && g.nsp > 1 && tid == 0 && !late) atomicOr(ctr, kLateBit);
         const bool early = kEarlyNext<CODEC> && !late;
@@ -1417,7 +1477,9 @@ static int occupancy_of() {
     X(kFsst8, int32_t, kModeLookback) X(kFsst8, int64_t, kModeLookback) X(kOnpair16, int32_t, kModeLookback) \
     X(kOnpair16, int64_t, kModeLookback) X(kFsst8, int32_t, kModeTotals) X(kFsst8, int64_t, kModeTotals)     \
     X(kOnpair16, int32_t, kModeTotals) X(kOnpair16, int64_t, kModeTotals) X(kFsst8, int32_t, kModeExpand)    \
-    X(kFsst8, int64_t, kModeExpand) X(kOnpair16, int32_t, kModeExpand) X(kOnpair16, int64_t, kModeExpand)
+    X(kFsst8, int64_t, kModeExpand) X(kOnpair16, int32_t, kModeExpand) X(kOnpair16, int64_t, kModeExpand)    \
+    X(kOnpair12, int32_t, kModeLookback) X(kOnpair12, int64_t, kModeLookback) X(kOnpair12, int32_t, kModeTotals) \
+    X(kOnpair12, int64_t, kModeTotals) X(kOnpair12, int32_t, kModeExpand) X(kOnpair12, int64_t, kModeExpand)
 
 int decode_occupancy(int codec, int index_bits, int mode) {
 #define OCC(C, I, M) \
@@ -1444,6 +1506,8 @@ static int batch_occupancy_of() {
 
 int batch_occupancy(int codec, int index_bits) {
     if (codec == kFsst8) return index_bits == 64 ? batch_occupancy_of<kFsst8, int64_t>() : batch_occupancy_of<kFsst8, int32_t>();
+    if (codec == kOnpair12)
+        return index_bits == 64 ? batch_occupancy_of<kOnpair12, int64_t>() : batch_occupancy_of<kOnpair12, int32_t>();
     return index_bits == 64 ? batch_occupancy_of<kOnpair16, int64_t>() : batch_occupancy_of<kOnpair16, int32_t>();
 }
 
@@ -1453,6 +1517,10 @@ hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* co
         hipLaunchKernelGGL((k_decode_batch<kFsst8, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
     else if (codec == kFsst8)
         hipLaunchKernelGGL((k_decode_batch<kFsst8, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
+    else if (codec == kOnpair12 && index_bits == 32)
+        hipLaunchKernelGGL((k_decode_batch<kOnpair12, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
+    else if (codec == kOnpair12)
+        hipLaunchKernelGGL((k_decode_batch<kOnpair12, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
     else if (index_bits == 32)
         hipLaunchKernelGGL((k_decode_batch<kOnpair16, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
     else
@@ -1475,8 +1543,12 @@ hipError_t launch_batch_status(const unsigned long long* errs, int32_t n_cols, i
     return hipGetLastError();
 }
 
-int chunks_per_lane(int codec) { return codec == kFsst8 ? Cfg<kFsst8>::P : Cfg<kOnpair16>::P; }
-int codes_per_chunk(int codec) { return codec == kFsst8 ? Cfg<kFsst8>::CPC : Cfg<kOnpair16>::CPC; }
+int chunks_per_lane(int codec) {
+    return codec == kFsst8 ? Cfg<kFsst8>::P : codec == kOnpair12 ? Cfg<kOnpair12>::P : Cfg<kOnpair16>::P;
+}
+int codes_per_chunk(int codec) {
+    return codec == kFsst8 ? Cfg<kFsst8>::CPC : codec == kOnpair12 ? Cfg<kOnpair12>::CPC : Cfg<kOnpair16>::CPC;
+}
 
 hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n,
                         hipStream_t st) {

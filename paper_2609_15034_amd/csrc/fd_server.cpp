@@ -57,9 +57,11 @@ struct Slot {
 };
 
 int64_t request_bytes(const fd_column& c) {
-    const int64_t cb = (c.dict && c.dict->codec == FD_ONPAIR16) ? 2 : 1;
+    const fd_codec codec = c.dict ? c.dict->codec : FD_FSST8;
+    const int64_t code_bytes = codec == FD_ONPAIR16 ? 2 * c.n_codes : codec == FD_ONPAIR12 ? (c.n_codes * 12 + 7) / 8
+                                                                                           : c.n_codes;
     const int64_t ob = c.index_bits == 64 ? 8 : 4;
-    return c.n_codes * cb + 2 * (c.n_strings + 1) * ob + c.out_capacity;
+    return code_bytes + 2 * (c.n_strings + 1) * ob + c.out_capacity;
 }
 
 }  // namespace

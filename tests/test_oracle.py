@@ -302,6 +302,38 @@ def test_golden_onpair16(oracle_mod, case):
         assert bytes(r.out_bytes) == case["bytes"]
 
 
+@pytest.mark.parametrize("case", parse_golden("code12_cases.txt"), ids=lambda c: c["line"][:40])
+def test_golden_code12(oracle_mod, case):
+    packed = np.frombuffer(bytes.fromhex("".join(case["codes"])), np.uint8)
+    db, dl = pack(case["tokens"])
+    r = oracle_mod.decode("onpair12", packed, np.array(case["code_off"], np.int64), db, dl)
+    assert r.status == case["status"]
+    if case["out_off"] is not None:
+        assert list(r.out_off) == case["out_off"]
+        assert bytes(r.out_bytes) == case["bytes"]
+
+
+def test_unpack12_by_hand(oracle_mod):
+    """Bit order of the 12-bit stream, values worked out by hand."""
+    assert oracle_mod.unpack12(np.array([0x23, 0xC1, 0xAB], np.uint8), 2).tolist() == [0x123, 0xABC]
+    assert oracle_mod.unpack12(np.array([0xFF, 0x0F, 0x00, 0x01, 0x0F], np.uint8), 3).tolist() == [0xFFF, 0x000, 0xF01]
+    # every 12-bit value at both phases (even and odd code positions)
+    v = np.arange(4096)
+    for shift in (0, 1):
+        codes = np.concatenate([np.zeros(shift, np.int64), v])
+        assert np.array_equal(oracle_mod.unpack12(oracle_mod.pack12(codes), len(codes))[shift:], v)
+
+
+def test_roundtrip_code12(oracle_mod, datagen_mod):
+    """OnPair-12 and FSST-12 columns decode back to their source text."""
+    for col in (datagen_mod.onpair12_urls(target_bytes=1 << 19), datagen_mod.fsst12_logs(target_bytes=1 << 19)):
+        r = oracle_mod.decode("onpair12", col.codes, col.code_off, col.dict_bytes, col.dict_lens,
+                              n_codes=col.stats["n_codes"])
+        assert r.status == 0
+        assert np.array_equal(r.out_bytes, col.text) and np.array_equal(r.out_off, col.text_off)
+        assert len(col.dict_lens) <= 4096
+
+
 # --------------------------------------------------------------------------- #
 # errors and precedence
 # --------------------------------------------------------------------------- #
