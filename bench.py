@@ -43,6 +43,10 @@ METRIC = "decoded GB/s per GPU (fraction of HBM peak), bit-exact; p50/p99 latenc
 WORKLOADS = {
     "fsst_logs": dict(codec="fsst8", desc="FSST-8 log lines, 1 GiB decoded, int64 offsets"),
     "onpair_urls": dict(codec="onpair16", desc="OnPair-16 URL/identifier strings, 1 GiB decoded, int64 offsets"),
+    "onpair12_urls": dict(codec="onpair12", desc="OnPair-12 (12-bit packed codes, 4,096 tokens) URL/identifier "
+                                                 "strings, 1 GiB decoded, int64 offsets"),
+    "fsst12_logs": dict(codec="onpair12", desc="FSST-12 (12-bit packed codes, 4,096 symbols of 1-8 bytes, no "
+                                               "escapes) log lines, 1 GiB decoded, int64 offsets"),
     "fsst_small": dict(codec="fsst8", desc="FSST-8 printable strings, 10,000 strings, int32 offsets"),
     "batch256": dict(codec="mixed", desc="256 columns, decoded sizes log-uniform 4 KB-64 MB, FSST-8 / OnPair-16 "
                                         "50/50, a dictionary per column, one replayed HIP graph"),
@@ -73,6 +77,10 @@ def make_column(name: str, seed: int | None):
         return datagen.onpair_urls(seed=seed or 3)
     if name == "fsst_small":
         return datagen.fsst_small(seed=seed or 1)
+    if name == "onpair12_urls":
+        return datagen.onpair12_urls(seed=seed or 6)
+    if name == "fsst12_logs":
+        return datagen.fsst12_logs(seed=seed or 7)
     raise ValueError(name)
 
 
@@ -81,9 +89,9 @@ def algorithmic_bytes(col) -> int:
     codes of the decoded range, read the code offsets, write the Arrow offsets,
     read the dictionary once."""
     n_used = int(col.code_off[-1] - col.code_off[0])
-    code_bytes = 1 if col.codec == "fsst8" else 2
+    code_bytes = {"fsst8": n_used, "onpair16": 2 * n_used, "onpair12": (12 * n_used + 7) // 8}[col.codec]
     w_off = col.code_off.dtype.itemsize
-    return (col.decoded_bytes + n_used * code_bytes + 2 * (col.n_strings + 1) * w_off
+    return (col.decoded_bytes + code_bytes + 2 * (col.n_strings + 1) * w_off
             + int(col.dict_bytes.size + col.dict_lens.size))
 
 
@@ -121,7 +129,7 @@ def read_traffic(workload: str, src_hash: str):
 def _upload_column(col, dev):
     import numpy as np
     import torch
-    codes_np = col.codes if col.codec == "fsst8" else col.codes.view(np.int16)
+    codes_np = col.codes.view(np.int16) if col.codec == "onpair16" else col.codes
     return torch.from_numpy(codes_np).to(dev), torch.from_numpy(col.code_off).to(dev)
 
 
@@ -154,7 +162,7 @@ def single_rate(workload: str, steps: int = 10, seed: int | None = None) -> floa
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
     out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
-    ws = fd.alloc_workspace(col.codec, codes.numel(), col.n_strings)
+    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     mean_s, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True),
                              steps, 2)
@@ -419,7 +427,7 @@ def main():
     log(f"[bench] generated {args.workload}: {col.stats} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda")
-    codes_np = col.codes if col.codec == "fsst8" else col.codes.view(np.int16)
+    codes_np = col.codes.view(np.int16) if col.codec == "onpair16" else col.codes
     codes = torch.from_numpy(codes_np).to(dev)
     code_off = torch.from_numpy(col.code_off).to(dev)
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
@@ -427,7 +435,7 @@ def main():
     out = torch.empty(D, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
     tuning = {"mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid, "reserved": 0}
-    ws = fd.alloc_workspace(col.codec, codes.numel(), col.n_strings, tuning)
+    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tuning)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
@@ -485,7 +493,7 @@ def main():
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
         t_cpu, nb, ns = oracle.time_decode(col.codec, col.codes, col.code_off, col.dict_bytes, col.dict_lens,
-                                           threads=threads, repeats=3)
+                                           threads=threads, repeats=3, n_codes=int(col.stats["n_codes"]))
         cpu = {"value": round(nb / t_cpu / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
                "sample": f"whole column ({nb} decoded bytes, {ns} strings), best of 3, {threads} threads on "
                          f"contiguous string-range shards"}
@@ -527,6 +535,11 @@ def main():
             res["onpair_urls_GBps"] = round(rates["onpair16"], 2)
         except Exception as e:
             res["onpair_urls_GBps"] = {"error": f"{type(e).__name__}: {e}"}
+        for wl in ("onpair12_urls", "fsst12_logs"):     # 12-bit packed codes
+            try:
+                res[wl + "_GBps"] = round(single_rate(wl), 2)
+            except Exception as e:
+                res[wl + "_GBps"] = {"error": f"{type(e).__name__}: {e}"}
         for key, fn in (("batch", lambda: run_batch(10, 2, None, check=not args.no_check, cpu=False,
                                                     single_rates=rates if len(rates) == 2 else None)),
                         ("serve", lambda: run_serve(None, n_requests=2000, check=not args.no_check))):

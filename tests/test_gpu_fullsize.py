@@ -1,7 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times (automatic tiling, resident grid, asynchronous status):
 
-- the 1 GiB FSST-8 log column and the 1 GiB OnPair-16 URL column: the whole
+- the 1 GiB FSST-8 log column, the 1 GiB OnPair-16 URL column and their 12-bit
+  packed counterparts (OnPair-12 URLs, FSST-12 logs): the whole
   output must equal the generator's source text and offsets (decoding is
   lossless, so that is the expected result at any size), and sampled runs of
   strings across the column are checked against the oracle one run at a time;
@@ -32,30 +33,34 @@ def sample_runs(n_strings, rng, n_runs=40, run=50):
 def check_runs_against_oracle(col, out_off, out, rng, n_runs=40):
     import oracle
     co = col.code_off.astype(np.int64)
+    codec, codes = col.codec, col.codes
+    if codec == "onpair12":          # runs of a packed stream: the oracle's unpacked codes
+        codec, codes = "onpair16", oracle.unpack12_np(col.codes, int(col.stats["n_codes"]))
     for a, b in sample_runs(col.n_strings, rng, n_runs):
         c0, c1 = int(co[a]), int(co[b])
-        exp = oracle.decode(col.codec, col.codes[c0:c1], co[a:b + 1] - c0, col.dict_bytes, col.dict_lens)
+        exp = oracle.decode(codec, codes[c0:c1], co[a:b + 1] - c0, col.dict_bytes, col.dict_lens)
         assert exp.status == 0
         rel = out_off[a:b + 1] - out_off[a]
         assert np.array_equal(rel, exp.out_off), (col.name, a, b)
         assert np.array_equal(out[int(out_off[a]):int(out_off[b])], exp.out_bytes), (col.name, a, b)
 
 
-@pytest.mark.parametrize("workload,seed", [("fsst_logs", 2), ("onpair_urls", 3)])
+@pytest.mark.parametrize("workload,seed", [("fsst_logs", 2), ("onpair_urls", 3), ("onpair12_urls", 6),
+                                           ("fsst12_logs", 7)])
 def test_full_column(datagen_mod, oracle_mod, workload, seed):
     import torch
     import paper_2609_15034_amd as fd
     col = getattr(datagen_mod, workload)(seed=seed)
     print(f"{workload}: {col.stats}", flush=True)
     dev = torch.device("cuda")
-    codes = torch.from_numpy(col.codes if col.codec == "fsst8" else col.codes.view(np.int16)).to(dev)
+    codes = torch.from_numpy(col.codes.view(np.int16) if col.codec == "onpair16" else col.codes).to(dev)
     code_off = torch.from_numpy(col.code_off).to(dev)
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
     guard = 4096
     buf = torch.full((col.decoded_bytes + guard,), 0xA5, dtype=torch.uint8, device=dev)
     out = buf[:col.decoded_bytes]
     out_off = torch.full((col.n_strings + 1,), -7, dtype=code_off.dtype, device=dev)
-    ws = fd.alloc_workspace(col.codec, codes.numel(), col.n_strings)
+    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings)
     status = torch.full((1,), -1, dtype=torch.int32, device=dev)
     for _ in range(2):        # twice: the second run reuses the workspace as the benchmark does
         assert fd.decode_into(d, codes, code_off, out_off, out, ws, status=status, async_=True) == fd.OK

@@ -324,6 +324,15 @@ def test_unpack12_by_hand(oracle_mod):
         assert np.array_equal(oracle_mod.unpack12(oracle_mod.pack12(codes), len(codes))[shift:], v)
 
 
+def test_unpack12_whole_column_form(oracle_mod):
+    """The vectorised unpacker the oracle uses on whole columns agrees with the
+    one-code-at-a-time definition."""
+    rng = np.random.default_rng(12)
+    for n in (0, 1, 2, 3, 1000, 1001):
+        packed = rng.integers(0, 256, (n * 12 + 7) // 8).astype(np.uint8)
+        assert np.array_equal(oracle_mod.unpack12_np(packed, n), oracle_mod.unpack12(packed, n))
+
+
 def test_roundtrip_code12(oracle_mod, datagen_mod):
     """OnPair-12 and FSST-12 columns decode back to their source text."""
     for col in (datagen_mod.onpair12_urls(target_bytes=1 << 19), datagen_mod.fsst12_logs(target_bytes=1 << 19)):
