@@ -11,6 +11,19 @@
  *   - OnPair-16: uint16 codes, a dictionary of at most 65,536 tokens of
  *                1..16 bytes, no escapes (same section; the paper's OnPair-16
  *                codec).
+ *   - OnPair-12: 12-bit codes packed two to three bytes, a dictionary of at
+ *                most 4,096 tokens of 1..16 bytes, no escapes (the 12-bit
+ *                code width of the same section).  Code k is bits
+ *                [12k, 12k + 12) of the byte stream, least significant bit
+ *                first: codes x, y are the bytes x & 0xff,
+ *                (x >> 8) | (y & 0xf) << 4, y >> 4.  The stream may start at
+ *                any byte address; n_codes counts codes (the stream holds
+ *                ceil(12 * n_codes / 8) bytes).  FSST-12 (4,096 symbols of
+ *                1..8 bytes with every single byte present, so no escapes)
+ *                decodes through this codec.  It needs a prepared dictionary
+ *                (fd_dict_create, then fd_decode / fd_decode_ex / a batch);
+ *                the raw-dictionary entry points fsst_decode and
+ *                onpair_decode are FSST-8 and OnPair-16 only.
  *
  * Decoding looks every code's token up and concatenates the tokens in code
  * order (same section).  String i of a column is the code range
@@ -140,8 +153,9 @@ fd_status onpair_decode(const uint16_t *codes, int64_t n_codes, const void *code
 /* An immutable device-resident dictionary, prepared once: for OnPair-16 the
  * tokens are repacked into fixed 16-byte entries so that a token's address
  * follows from its code (the fixed-stride dictionary of the introduction and of
- * the design section's decode stages) plus a 65,536-entry length table; for
- * FSST-8 the packed symbols are copied.  dict_bytes / dict_lens are device
+ * the design section's decode stages) plus a 65,536-entry length table; an
+ * OnPair-12 dictionary (at most 4,096 tokens) is repacked the same way; for
+ * FSST-8 the packed symbols are copied and the decode table is built.  dict_bytes / dict_lens are device
  * pointers (read during the call only).  Validation runs on the device: the
  * call waits for hip_stream and returns FD_EBADDICT for a length of 0 or above
  * the codec maximum.  The handle owns library-allocated device memory on the
@@ -155,7 +169,8 @@ fd_codec fd_dict_codec(const fd_dict *dict);
 int32_t fd_dict_size(const fd_dict *dict);
 
 /* Decode one column with a prepared dictionary (codec taken from the handle).
- * codes is uint8 (FSST-8) or uint16 (OnPair-16); other arguments as
+ * codes is uint8 (FSST-8), uint16 (OnPair-16) or the packed 12-bit byte
+ * stream (OnPair-12, n_codes = codes in it); other arguments as
  * fsst_decode / onpair_decode. */
 fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets, int index_bits,
                     int64_t n_strings, void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
@@ -173,10 +188,10 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                        expansion), reading the code stream twice (the
  *                        "sidecar regenerated at decode time" variant the
  *                        paper measures in its design overview).
- *   strings_per_tile  1..256 (FSST-8) or 1..1024 (OnPair-16); automatic = the
+ *   strings_per_tile  1..256 (FSST-8) or 1..1024 (OnPair); automatic = the
  *                     most strings whose codes, at the column's mean codes
  *                     per string plus a margin for their spread, fit one pass
- *                     (a pass is 8192 FSST-8 or 4096 OnPair-16 codes; a tile
+ *                     (a pass is 8192 FSST-8 or 4096 OnPair codes; a tile
  *                     with more codes takes several passes, each recomputing
  *                     the lengths).  The estimate uses n_codes / n_strings,
  *                     so a decode of a few strings out of a much larger code
