@@ -18,13 +18,18 @@ Prints one JSON line:
   cpu_baseline the CPU oracle on this host's cores over the same column
   bit_exact    GPU output == the generated source text (bytes and offsets)
 
-  python bench.py [--workload fsst_logs|onpair_urls|fsst_small|batch256|serve] [--steps K] [--warmup W]
+  python bench.py [--workload fsst_logs|onpair_urls|onpair12_urls|fsst12_logs|fsst_small|batch256|serve]
+                  [--steps K] [--warmup W] [--sidecar]
 
-The default run (fsst_logs) also reports, in "batch" and "serve", short
-runs of the batched workload (256 columns in one replayed HIP graph, against
-the same columns decoded one call each) and of the served workload
-(Poisson arrivals into the continuous-batching server, p50/p99 latency);
---no-extra skips them.
+--sidecar times the decode with output positions read from a stored sidecar
+(built once before timing) instead of the look-back.
+
+The default run (fsst_logs) also reports the other 1 GiB columns' rates, the
+sidecar decode against the look-back on the FSST-8 and OnPair-16 columns
+("sidecar"), and, in "batch" and "serve", short runs of the batched workload
+(256 columns in one replayed HIP graph, against the same columns decoded one
+call each) and of the served workload (Poisson arrivals into the
+continuous-batching server, p50/p99 latency); --no-extra skips them.
 """
 from __future__ import annotations
 
@@ -167,6 +172,34 @@ def single_rate(workload: str, steps: int = 10, seed: int | None = None) -> floa
     mean_s, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True),
                              steps, 2)
     return col.decoded_bytes / mean_s / 1e9
+
+
+def sidecar_rates(workload: str, steps: int = 20, seed: int | None = None) -> dict:
+    """One 1 GiB column decoded with its output positions taken from a stored
+    sidecar (built once before timing, as the paper stores it with the
+    column) and with the positions regenerated by the look-back, timed back to
+    back; the sidecar decode's output is checked against the source text."""
+    import torch
+    import paper_2609_15034_amd as fd
+    col = make_column(workload, seed)
+    dev = torch.device("cuda")
+    codes, code_off = _upload_column(col, dev)
+    d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
+    out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
+    out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
+    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    sc = fd.sidecar_build(d, codes, code_off)
+    t_sc, _ = _events_time(lambda: fd.decode_sidecar_into(d, codes, code_off, sc, out_off, out, ws, status=st,
+                                                          async_=True), steps, 2)
+    ok = int(st.item()) == fd.OK and torch.equal(out, torch.from_numpy(col.text).to(dev)) and \
+        torch.equal(out_off.to(torch.int64), torch.from_numpy(col.text_off).to(dev))
+    t_lb, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True),
+                           steps, 2)
+    D = col.decoded_bytes
+    return {"sidecar_GBps": round(D / t_sc / 1e9, 2), "lookback_GBps": round(D / t_lb / 1e9, 2),
+            "regeneration_cost": round(t_lb / t_sc - 1.0, 3), "sidecar_bytes": int(sc.numel() * 8),
+            "bit_exact": bool(ok)}
 
 
 def run_batch(steps: int, warmup: int, seed: int | None, n_cols: int = 256, max_bytes: int = 64 << 20,
@@ -380,6 +413,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the output check")
     ap.add_argument("--no-extra", action="store_true", help="default run: skip the batched and served legs")
+    ap.add_argument("--sidecar", action="store_true",
+                    help="decode with output positions from a stored sidecar (built once, before timing)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
@@ -437,10 +472,19 @@ def main():
     tuning = {"mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid, "reserved": 0}
     ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tuning)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
+    sidecar = None
+    if args.sidecar:                  # stored output positions, built once before timing
+        if args.mode != 0:
+            raise SystemExit("--sidecar decodes take mode 0 tuning")
+        sidecar = fd.sidecar_build(d, codes, code_off, tuning)
     torch.cuda.synchronize()
 
     def step():
-        st = fd.decode_into(d, codes, code_off, out_off, out, ws, status=status, async_=True, tuning=tuning)
+        if sidecar is not None:
+            st = fd.decode_sidecar_into(d, codes, code_off, sidecar, out_off, out, ws, status=status, async_=True,
+                                        tuning=tuning)
+        else:
+            st = fd.decode_into(d, codes, code_off, out_off, out, ws, status=status, async_=True, tuning=tuning)
         if st != fd.OK:
             raise fd.DecodeError(st)
 
@@ -475,15 +519,17 @@ def main():
         bit_exact = bool(ok_b and ok_o)
         log(f"[bench] output vs source text: bytes {ok_b}, offsets {ok_o}")
 
-    B_alg = algorithmic_bytes(col)
+    B_alg = algorithmic_bytes(col) + (8 * sidecar.numel() if sidecar is not None else 0)
     value = D / mean_s / 1e9
     achieved = B_alg / mean_s / 1e9
     src_hash = kernel_source_hash()
-    tr = read_traffic(args.workload, src_hash)
+    tr = read_traffic(args.workload, src_hash) if sidecar is None else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": (int(tr["hbm_bytes_per_launch"]) if tr else None),
-            "algorithmic_bytes": int(B_alg), "kernel": "k_decode (single pass) + k_reset",
+            "algorithmic_bytes": int(B_alg),
+            "kernel": ("k_decode (expand, stored positions) + k_reset" if sidecar is not None
+                       else "k_decode (single pass) + k_reset"),
             "duration_us": round(mean_s * 1e6, 2)}
 
     copy_gbps = copy_calibration(1 << 30, reps=3)
@@ -517,7 +563,8 @@ def main():
                    "n_strings": col.n_strings, "index_bits": 8 * col.code_off.dtype.itemsize,
                    "bytes_per_code": round(col.stats.get("bytes_per_code", 0.0), 3),
                    "escape_share": round(col.stats.get("escape_share", 0.0), 4),
-                   "mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid},
+                   "mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid,
+                   "positions": "stored sidecar" if sidecar is not None else "look-back"},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBPS, 4),
         "step_us": {"min": round(float(per.min()) * 1e6, 2), "p50": round(float(np.median(per)) * 1e6, 2),
                     "p99": round(float(np.percentile(per, 99)) * 1e6, 2)},
@@ -540,6 +587,12 @@ def main():
                 res[wl + "_GBps"] = round(single_rate(wl), 2)
             except Exception as e:
                 res[wl + "_GBps"] = {"error": f"{type(e).__name__}: {e}"}
+        res["sidecar"] = {}
+        for wl in ("fsst_logs", "onpair_urls"):          # stored positions against regenerated ones
+            try:
+                res["sidecar"][wl] = sidecar_rates(wl)
+            except Exception as e:
+                res["sidecar"][wl] = {"error": f"{type(e).__name__}: {e}"}
         for key, fn in (("batch", lambda: run_batch(10, 2, None, check=not args.no_check, cpu=False,
                                                     single_rates=rates if len(rates) == 2 else None)),
                         ("serve", lambda: run_serve(None, n_requests=2000, check=not args.no_check))):

@@ -52,7 +52,8 @@
  *   - Errors in the data are found on the device: FD_EBADDICT, FD_EOFFSETS,
  *     FD_EBADCODE, FD_EESCAPE, FD_EOVERFLOW, FD_ECAPACITY.  When several
  *     apply, the one reported is the first of: EBADDICT, EOFFSETS, the data
- *     error at the lowest code position, EOVERFLOW, ECAPACITY.
+ *     error at the lowest code position, ESIDECAR (fd_decode_sidecar),
+ *     EOVERFLOW, ECAPACITY.
  *     Without FD_ASYNC the call waits for the stream and returns the status.
  *     With FD_ASYNC the call returns FD_OK once enqueued and the final status
  *     is written to *status (a device int32) when the work completes.
@@ -85,7 +86,8 @@ typedef enum fd_status {
     FD_EBADDICT = 6,   /* token length 0 or above the codec maximum               */
     FD_EOFFSETS = 7,   /* code_offsets decreasing, negative or past n_codes       */
     FD_EHIP = 8,       /* a HIP runtime call failed                               */
-    FD_ENOMEM = 9      /* allocation failed / request exceeds a memory budget     */
+    FD_ENOMEM = 9,     /* allocation failed / request exceeds a memory budget     */
+    FD_ESIDECAR = 10   /* fd_decode_sidecar: stored positions differ from the codes */
 } fd_status;
 
 typedef enum fd_codec { FD_FSST8 = 1, FD_ONPAIR16 = 2, FD_ONPAIR12 = 3 } fd_codec;
@@ -216,6 +218,58 @@ fd_status fd_decode_ex(const fd_dict *dict, const void *codes, int64_t n_codes, 
                        int index_bits, int64_t n_strings, void *out_offsets, uint8_t *out_bytes, int64_t out_capacity,
                        void *workspace, size_t workspace_bytes, int32_t *status, unsigned flags,
                        const fd_tuning *tuning, void *hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Persisted output positions (sidecar)                                       */
+/* ------------------------------------------------------------------------- */
+
+/* The paper stores, with each compressed column, the output position of every
+ * fixed-size group of codes (its "sidecar", introduction and the design
+ * section's paragraph on output placement), so that decoding needs no prefix
+ * scan across groups; regenerating it at decode time costs 20-35% there.
+ * Here a group is a tile of strings_per_tile consecutive strings, so the
+ * sidecar of a column under a tiling is an int64 array of n_tiles + 1
+ * entries (n_tiles = ceil(n_strings / strings_per_tile), 1 when n_strings is
+ * 0):
+ *     sidecar[k] = out_offsets[min(k * strings_per_tile, n_strings)],
+ * the decoded position of tile k's first string, and sidecar[n_tiles] the
+ * decoded total.  An encoder that has the source strings can fill it from
+ * their offsets; fd_sidecar_build computes it on the device from the codes.
+ * It is 8 bytes per tile (about 0.1% of the codes of the 1 GiB log column).
+ *
+ * fd_sidecar_layout: the tiling of a column (tuning as for fd_decode_ex; its
+ * mode must be 0) and the number of sidecar entries.  The sidecar is valid
+ * only with that strings_per_tile: store it beside the sidecar and pass it to
+ * the decode in tuning->strings_per_tile. */
+fd_status fd_sidecar_layout(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning *tuning,
+                            int32_t *strings_per_tile, int64_t *n_entries);
+
+/* Compute the sidecar of a column on the device (a totals-only pass over the
+ * codes and a scan of the tile totals), into the caller's device array
+ * sidecar[n_entries] (8-byte aligned; n_entries from fd_sidecar_layout with
+ * the same tuning, else FD_EINVAL).  The workspace is fd_workspace_size_ex's.
+ * Statuses: FD_OK, or the errors in the data that a decode would report
+ * before EOVERFLOW (EBADDICT, EOFFSETS, EBADCODE, EESCAPE), in the same
+ * precedence; then the entries are unspecified.  No output is written. */
+fd_status fd_sidecar_build(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets,
+                           int index_bits, int64_t n_strings, int64_t *sidecar, int64_t n_entries, void *workspace,
+                           size_t workspace_bytes, int32_t *status, unsigned flags, const fd_tuning *tuning,
+                           void *hip_stream);
+
+/* fd_decode_ex with the output positions taken from a sidecar (device,
+ * n_entries int64, read only) instead of a scan: every tile starts at once.
+ * tuning->strings_per_tile must be the sidecar's (0 = the automatic choice,
+ * as in fd_sidecar_layout) and tuning->mode 0.  Each tile checks its entry
+ * against the next (sidecar[k] + tile k's decoded total = sidecar[k + 1], and
+ * sidecar[0] = 0); a tile that fails writes no byte, and the call reports
+ * FD_ESIDECAR, which ranks after the data errors and before EOVERFLOW and
+ * ECAPACITY.  Bytes are never written outside out_bytes[0, out_capacity),
+ * whatever the sidecar holds. */
+fd_status fd_decode_sidecar(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets,
+                            int index_bits, int64_t n_strings, const int64_t *sidecar, int64_t n_entries,
+                            void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
+                            size_t workspace_bytes, int32_t *status, unsigned flags, const fd_tuning *tuning,
+                            void *hip_stream);
 
 /* ------------------------------------------------------------------------- */
 /* Batched decode                                                              */

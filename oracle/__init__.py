@@ -8,7 +8,7 @@ imports nothing from the library.
 
 Status numbering (a convention of the decode interface, restated here):
 0 OK, 1 EINVAL, 2 EBADCODE, 3 EESCAPE, 4 ECAPACITY, 5 EOVERFLOW, 6 EBADDICT,
-7 EOFFSETS.
+7 EOFFSETS, 10 ESIDECAR.
 """
 from __future__ import annotations
 
@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS = range(8)
+ESIDECAR = 10
 
 
 def build(force: bool = True) -> str:
@@ -164,6 +165,46 @@ def decode(codec: str, codes, code_off, dict_bytes, dict_lens, index_bits: int |
     if not np.all(out[cap:] == 0xA5):
         raise AssertionError("oracle wrote past out_capacity")
     return Result(int(st), out_off, out[: min(t, cap)], t, int(err.value))
+
+
+def sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, strings_per_tile: int,
+            n_codes: int | None = None):
+    """The sidecar of a column: the output position stored for every batch of
+    the column so that a decoder can start every batch at once (introduction;
+    design section, placement of the output).  Reading: a batch is a tile of
+    ``strings_per_tile`` consecutive strings, so entry k is the decoded
+    position of string k * strings_per_tile, i.e. the sum of the decoded
+    lengths of the strings before it, for k < n_tiles = max(1, ceil(n_strings
+    / strings_per_tile)), and the last entry is the decoded total.  Returns
+    (status, int64 entries); the entries are None when the data has an error."""
+    r = decode(codec, codes, code_off, dict_bytes, dict_lens, index_bits=64, n_codes=n_codes)
+    if r.status != OK:
+        return r.status, None
+    n = len(code_off) - 1
+    sb = int(strings_per_tile)
+    if sb < 1:
+        raise ValueError("strings_per_tile must be positive")
+    n_tiles = max(1, -(-n // sb))
+    firsts = [min(k * sb, n) for k in range(n_tiles)] + [n]
+    return OK, r.out_off[firsts].astype(np.int64)
+
+
+def decode_with_sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, stored, strings_per_tile: int,
+                        index_bits: int | None = None, out_capacity: int | None = None,
+                        n_codes: int | None = None) -> Result:
+    """Decode with stored output positions: the plain decode's result, except
+    that stored positions other than the column's own sidecar give ESIDECAR,
+    which ranks after the errors in the data and before EOVERFLOW and
+    ECAPACITY (on ESIDECAR nothing of the output is defined)."""
+    st, own = sidecar(codec, codes, code_off, dict_bytes, dict_lens, strings_per_tile, n_codes)
+    if st == OK:
+        given = np.asarray(stored, dtype=np.int64)
+        if len(given) != len(own):
+            raise ValueError("a sidecar of another tiling")
+        if not np.array_equal(given, own):
+            n = len(code_off) - 1
+            return Result(ESIDECAR, np.zeros(n + 1, np.int64), np.zeros(0, np.uint8), int(own[-1]), -1)
+    return decode(codec, codes, code_off, dict_bytes, dict_lens, index_bits, out_capacity, n_codes)
 
 
 def decode_onpair16_copy16(codes, code_off, dict_bytes, dict_lens):

@@ -39,9 +39,9 @@ def codes_in(codec, codes) -> int:
 ASYNC = 1
 GRAPH = 2
 
-OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS, EHIP, ENOMEM = range(10)
+OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS, EHIP, ENOMEM, ESIDECAR = range(11)
 STATUS_NAMES = ["FD_OK", "FD_EINVAL", "FD_EBADCODE", "FD_EESCAPE", "FD_ECAPACITY", "FD_EOVERFLOW", "FD_EBADDICT",
-                "FD_EOFFSETS", "FD_EHIP", "FD_ENOMEM"]
+                "FD_EOFFSETS", "FD_EHIP", "FD_ENOMEM", "FD_ESIDECAR"]
 
 
 class LibraryNotBuilt(RuntimeError):
@@ -118,6 +118,14 @@ def lib():
     L.fd_decode.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, P]
     L.fd_decode_ex.restype = ctypes.c_int
     L.fd_decode_ex.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, ctypes.POINTER(Tuning), P]
+    L.fd_sidecar_layout.restype = ctypes.c_int
+    L.fd_sidecar_layout.argtypes = [ctypes.c_int, I64, I64, ctypes.POINTER(Tuning), ctypes.POINTER(I32),
+                                    ctypes.POINTER(I64)]
+    L.fd_sidecar_build.restype = ctypes.c_int
+    L.fd_sidecar_build.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, I64, P, S, P, U, ctypes.POINTER(Tuning), P]
+    L.fd_decode_sidecar.restype = ctypes.c_int
+    L.fd_decode_sidecar.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, I64, P, P, I64, P, S, P, U,
+                                    ctypes.POINTER(Tuning), P]
     L.fd_batch_workspace_size.restype = ctypes.c_int
     L.fd_batch_workspace_size.argtypes = [ctypes.POINTER(Column), I32, ctypes.POINTER(Tuning), ctypes.POINTER(S)]
     L.batch_decode.restype = ctypes.c_int
@@ -293,6 +301,53 @@ def decode(d: Dict, codes, code_off, tuning=None, stream=None):
     if st != OK:
         raise DecodeError(st)
     return out_off, out
+
+
+# --------------------------------------------------------------------------- #
+# persisted output positions (sidecar)
+# --------------------------------------------------------------------------- #
+def sidecar_layout(codec, n_codes: int, n_strings: int, tuning=None):
+    """fd_sidecar_layout: (strings_per_tile, n_entries) of a column's sidecar."""
+    sb, n = ctypes.c_int32(0), ctypes.c_int64(0)
+    tu = Tuning(**tuning) if isinstance(tuning, dict) else tuning
+    st = lib().fd_sidecar_layout(_codec_id(codec), int(n_codes), int(n_strings),
+                                 ctypes.byref(tu) if tu is not None else None, ctypes.byref(sb), ctypes.byref(n))
+    if st:
+        raise DecodeError(st, "fd_sidecar_layout")
+    return int(sb.value), int(n.value)
+
+
+def sidecar_build_into(d: Dict, codes, code_off, sidecar, workspace, status=None, async_=False, tuning=None,
+                       stream=None, n_codes=None) -> int:
+    """fd_sidecar_build into a preallocated int64 device tensor; returns the fd_status."""
+    return lib().fd_sidecar_build(d.handle, _ptr(codes), int(codes_in(d.codec, codes) if n_codes is None else n_codes),
+                                  _ptr(code_off), _index_bits(code_off), code_off.numel() - 1, _ptr(sidecar),
+                                  sidecar.numel(), _ptr(workspace), workspace.numel(), _ptr(status),
+                                  ASYNC if async_ else 0, _tuning(tuning), _stream_handle(stream))
+
+
+def sidecar_build(d: Dict, codes, code_off, tuning=None, stream=None):
+    """The sidecar of a column as a new int64 device tensor (raises on error)."""
+    torch = _torch()
+    n = codes_in(d.codec, codes)
+    _, n_entries = sidecar_layout(d.codec, n, code_off.numel() - 1, tuning)
+    sc = torch.empty(n_entries, dtype=torch.int64, device=codes.device)
+    ws = alloc_workspace(d.codec, n, code_off.numel() - 1, tuning, device=codes.device)
+    st = sidecar_build_into(d, codes, code_off, sc, ws, tuning=tuning, stream=stream)
+    if st != OK:
+        raise DecodeError(st, "fd_sidecar_build")
+    return sc
+
+
+def decode_sidecar_into(d: Dict, codes, code_off, sidecar, out_off, out_bytes, workspace, status=None, async_=False,
+                        tuning=None, stream=None, n_codes=None) -> int:
+    """fd_decode_sidecar with preallocated outputs; returns the fd_status."""
+    return lib().fd_decode_sidecar(d.handle, _ptr(codes),
+                                   int(codes_in(d.codec, codes) if n_codes is None else n_codes), _ptr(code_off),
+                                   _index_bits(code_off), code_off.numel() - 1, _ptr(sidecar), sidecar.numel(),
+                                   _ptr(out_off), _ptr(out_bytes), out_bytes.numel() if out_bytes is not None else 0,
+                                   _ptr(workspace), workspace.numel(), _ptr(status), ASYNC if async_ else 0,
+                                   _tuning(tuning), _stream_handle(stream))
 
 
 # --------------------------------------------------------------------------- #

@@ -109,7 +109,8 @@ bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tunin
     pl->n_tiles = n_strings == 0 ? 1 : (n_strings + sb - 1) / sb;
     pl->n_blocks = (pl->n_tiles + kBlk - 1) / kBlk;
     pl->off_tiles = kHdr;
-    pl->off_blocks = pl->off_tiles + (size_t)pl->n_tiles * 8;
+    // n_tiles + 1 tile words: the three-phase scan leaves the decoded total in the last
+    pl->off_blocks = pl->off_tiles + (size_t)(pl->n_tiles + 1) * 8;
     pl->off_dict = align_up(pl->off_blocks + (size_t)pl->n_blocks * 8, 256);
     pl->bytes = pl->off_dict + (codec == FD_ONPAIR16 ? align_up(kTok16Bytes + kTokLenBytes, 256) : 0);
     return true;
@@ -138,14 +139,22 @@ struct Args {
     unsigned flags;
     const fd_tuning* tuning;
     hipStream_t stream;
+    // persisted output positions: 0 none, 1 build them (no output), 2 decode with them
+    int sidecar_op;
+    int64_t* sidecar;
+    int64_t sidecar_n;
 };
+
+constexpr int kSidecarBuild = 1;
+constexpr int kSidecarDecode = 2;
 
 fd_status run_decode(const Args& a) {
     // ---------------- host-side validation ----------------
     if (a.index_bits != 32 && a.index_bits != 64) return FD_EINVAL;
     if (a.n_strings < 0 || a.n_codes < 0 || a.out_cap < 0) return FD_EINVAL;
     if (a.n_strings > (int64_t)1 << 40 || a.n_codes > (int64_t)1 << 40) return FD_EINVAL;
-    if (!a.code_off || !a.out_off || !a.ws) return FD_EINVAL;
+    const bool build = a.sidecar_op == kSidecarBuild;        // no decoded output
+    if (!a.code_off || (!build && !a.out_off) || !a.ws) return FD_EINVAL;
     if (a.n_codes > 0 && !a.codes) return FD_EINVAL;
     if (a.out_cap > 0 && !a.out) return FD_EINVAL;
     if ((a.flags & FD_ASYNC) && !a.status) return FD_EINVAL;
@@ -156,6 +165,7 @@ fd_status run_decode(const Args& a) {
     if ((uintptr_t)a.ws & 255) return FD_EINVAL;
     const int mode_sel = a.tuning ? a.tuning->mode : 0;
     if (mode_sel != 0 && mode_sel != 1) return FD_EINVAL;
+    if (a.sidecar_op && (mode_sel != 0 || !a.dict || !a.sidecar || ((uintptr_t)a.sidecar & 7))) return FD_EINVAL;
     if (a.tuning && a.tuning->grid < 0) return FD_EINVAL;
     if (!a.dict) {
         if (a.n_dict < 0) return FD_EINVAL;
@@ -167,6 +177,7 @@ fd_status run_decode(const Args& a) {
     Plan pl;
     if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl)) return FD_EINVAL;
     if (a.ws_bytes < pl.bytes) return FD_EINVAL;
+    if (a.sidecar_op && a.sidecar_n != pl.n_tiles + 1) return FD_EINVAL;   // another tiling's sidecar
 
     uint8_t* ws = (uint8_t*)a.ws;
     DecodeParams p;
@@ -188,8 +199,18 @@ fd_status run_decode(const Args& a) {
     p.status2 = (int32_t*)(ws + kOffStatus);
 
     hipStream_t st = a.stream;
-    // tile aggregates and block states are contiguous: one zeroing covers both
-    if (launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + pl.n_blocks, st) != hipSuccess) return hip_fail();
+    if (a.sidecar_op == kSidecarBuild) {
+        // the totals pass writes entries [0, n_tiles); the scan then needs a zero in the last
+        p.tagg = (unsigned long long*)a.sidecar;
+        if (launch_reset(p.err, p.counters, p.tagg + pl.n_tiles, 1, st) != hipSuccess) return hip_fail();
+    } else if (a.sidecar_op == kSidecarDecode) {
+        p.tagg = (unsigned long long*)a.sidecar;     // read only (entries t and t + 1 per tile)
+        if (launch_reset(p.err, p.counters, nullptr, 0, st) != hipSuccess) return hip_fail();
+    } else {
+        // tile words and block states are contiguous: one zeroing covers both
+        if (launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + 1 + pl.n_blocks, st) != hipSuccess)
+            return hip_fail();
+    }
 
     if (a.codec == FD_FSST8) {
         if (a.dict) {
@@ -219,7 +240,17 @@ fd_status run_decode(const Args& a) {
 
     const int codec = (int)a.codec;
     int grid_req = a.tuning ? a.tuning->grid : 0;
-    if (mode_sel == 0) {
+    if (a.sidecar_op == kSidecarBuild) {
+        int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
+        if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
+        if (launch_decode(codec, a.index_bits, kModeTotals, p, g1, st) != hipSuccess) return hip_fail();
+        if (launch_scan_totals(p.tagg, pl.n_tiles + 1, p.err, a.status, p.status2, st) != hipSuccess)
+            return hip_fail();
+    } else if (a.sidecar_op == kSidecarDecode) {
+        int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
+        if ((int64_t)g2 > pl.n_tiles) g2 = (int)pl.n_tiles;
+        if (launch_decode(codec, a.index_bits, kModeExpand, p, g2, st) != hipSuccess) return hip_fail();
+    } else if (mode_sel == 0) {
         int grid = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeLookback);
         if ((int64_t)grid > pl.n_tiles) grid = (int)pl.n_tiles;
         if (launch_decode(codec, a.index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();
@@ -227,7 +258,8 @@ fd_status run_decode(const Args& a) {
         int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
         if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
         if (launch_decode(codec, a.index_bits, kModeTotals, p, g1, st) != hipSuccess) return hip_fail();
-        if (launch_scan_totals(p.tagg, pl.n_tiles, st) != hipSuccess) return hip_fail();
+        if (launch_scan_totals(p.tagg, pl.n_tiles + 1, nullptr, nullptr, nullptr, st) != hipSuccess)
+            return hip_fail();
         // the expand phase takes tiles from the counter again
         if (launch_reset(nullptr, p.counters, nullptr, 0, st) != hipSuccess) return hip_fail();
         int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
@@ -258,6 +290,7 @@ const char* fd_status_str(int status) {
         case FD_EOFFSETS: return "FD_EOFFSETS";
         case FD_EHIP: return "FD_EHIP";
         case FD_ENOMEM: return "FD_ENOMEM";
+        case FD_ESIDECAR: return "FD_ESIDECAR";
         default: return "FD_UNKNOWN";
     }
 }
@@ -326,6 +359,51 @@ fd_status fd_decode_ex(const fd_dict* dict, const void* codes, int64_t n_codes, 
     a.n_strings = n_strings; a.out_off = out_offsets; a.out = out_bytes; a.out_cap = out_capacity;
     a.ws = workspace; a.ws_bytes = workspace_bytes; a.status = status; a.flags = flags; a.tuning = tuning;
     a.stream = (hipStream_t)hip_stream;
+    return run_decode(a);
+}
+
+fd_status fd_sidecar_layout(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tuning,
+                            int32_t* strings_per_tile, int64_t* n_entries) {
+    if (!strings_per_tile || !n_entries) return FD_EINVAL;
+    if (tuning && tuning->mode != 0) return FD_EINVAL;
+    Plan pl;
+    if (!plan_for(codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
+    *strings_per_tile = (int32_t)pl.sb;
+    *n_entries = pl.n_tiles + 1;
+    return FD_OK;
+}
+
+fd_status fd_sidecar_build(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets,
+                           int index_bits, int64_t n_strings, int64_t* sidecar, int64_t n_entries, void* workspace,
+                           size_t workspace_bytes, int32_t* status, unsigned flags, const fd_tuning* tuning,
+                           void* hip_stream) {
+    if (!dict) return FD_EINVAL;
+    Args a;
+    memset(&a, 0, sizeof(a));
+    a.codec = dict->codec;
+    a.dict = dict;
+    a.codes = codes; a.n_codes = n_codes; a.code_off = code_offsets; a.index_bits = index_bits;
+    a.n_strings = n_strings; a.ws = workspace; a.ws_bytes = workspace_bytes; a.status = status; a.flags = flags;
+    a.tuning = tuning; a.stream = (hipStream_t)hip_stream;
+    a.sidecar_op = kSidecarBuild; a.sidecar = sidecar; a.sidecar_n = n_entries;
+    return run_decode(a);
+}
+
+fd_status fd_decode_sidecar(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets,
+                            int index_bits, int64_t n_strings, const int64_t* sidecar, int64_t n_entries,
+                            void* out_offsets, uint8_t* out_bytes, int64_t out_capacity, void* workspace,
+                            size_t workspace_bytes, int32_t* status, unsigned flags, const fd_tuning* tuning,
+                            void* hip_stream) {
+    if (!dict) return FD_EINVAL;
+    Args a;
+    memset(&a, 0, sizeof(a));
+    a.codec = dict->codec;
+    a.dict = dict;
+    a.codes = codes; a.n_codes = n_codes; a.code_off = code_offsets; a.index_bits = index_bits;
+    a.n_strings = n_strings; a.out_off = out_offsets; a.out = out_bytes; a.out_cap = out_capacity;
+    a.ws = workspace; a.ws_bytes = workspace_bytes; a.status = status; a.flags = flags; a.tuning = tuning;
+    a.stream = (hipStream_t)hip_stream;
+    a.sidecar_op = kSidecarDecode; a.sidecar = (int64_t*)sidecar; a.sidecar_n = n_entries;
     return run_decode(a);
 }
 

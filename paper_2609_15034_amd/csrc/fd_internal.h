@@ -24,7 +24,7 @@ constexpr int kBlk = 1 << kBlkShift;
 // decode modes
 constexpr int kModeLookback = 0;    // single pass, decoupled look-back for tile cursors
 constexpr int kModeTotals = 1;      // three-phase: tile totals only
-constexpr int kModeExpand = 2;      // three-phase: expand with precomputed tile cursors
+constexpr int kModeExpand = 2;      // three-phase / sidecar: expand with stored tile cursors (checked)
 
 // tile state words (look-back): 2 flag bits + 62 value bits
 constexpr uint64_t kFlagAgg = 1ull << 62;
@@ -38,6 +38,7 @@ constexpr uint64_t kRankInternal = 0;             // look-back wait limit exceed
 constexpr uint64_t kRankDict = 0;
 constexpr uint64_t kRankOffsets = 1;
 constexpr uint64_t kRankData = 2;                 // + code position
+constexpr uint64_t kRankSidecar = (1ull << 58) - 1;   // stored cursors that do not match the codes
 constexpr uint64_t kRankOverflow = 1ull << 58;
 constexpr uint64_t kRankCapacity = (1ull << 58) + 1;
 
@@ -65,7 +66,8 @@ struct DecodeParams {
     // workspace
     unsigned long long* err;
     unsigned* counters;            // [0] tile counter, [1] finished workgroups
-    unsigned long long* tagg;      // per tile: aggregate (look-back) / total / cursor (three phases)
+    unsigned long long* tagg;      // per tile: aggregate (look-back) / total / cursor (three phases, sidecar:
+                                   // n_tiles + 1 int64 entries, the last the decoded total)
     unsigned long long* bstate;    // per block of kBlk tiles: look-back state
     int32_t* status;               // caller's device status (may be null)
     int32_t* status2;              // workspace status slot
@@ -75,7 +77,10 @@ int decode_occupancy(int codec, int index_bits, int mode);
 hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams& p, int grid, hipStream_t st);
 hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n,
                         hipStream_t st);
-hipError_t launch_scan_totals(unsigned long long* v, int64_t n, hipStream_t st);
+// Exclusive scan of v[0, n) in place; with err non-null it then publishes the
+// status of the errors recorded so far to *status / *status2.
+hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned long long* err, int32_t* status,
+                              int32_t* status2, hipStream_t st);
 int batch_occupancy(int codec, int index_bits);
 hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
                                int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st);

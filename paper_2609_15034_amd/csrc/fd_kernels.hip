@@ -86,6 +86,21 @@ __device__ __forceinline__ void record_error(unsigned long long* err, uint64_t r
     atomicMin(err, (unsigned long long)((rank << 4) | (uint64_t)status));
 }
 
+// Expand mode: tile t's stored cursor, checked against the next tile's
+// (stored cursor + the tile's decoded total = the next stored cursor, and
+// tile 0 starts at 0).  A mismatch records ESIDECAR and gives -1: the tile
+// then writes nothing.  A sidecar that passes every tile's check is the
+// exclusive prefix of the decoded tile totals, entry for entry.  Entries are
+// kept below 2^62 even when every tile's check passes on a shifted sidecar,
+// so output positions derived from them cannot wrap.
+__device__ __forceinline__ int64_t checked_cursor(const DecodeParams& p, int64_t t, int64_t cur, int64_t nxt,
+                                                  uint64_t total) {
+    const bool ok = cur >= 0 && (t != 0 || cur == 0) && nxt >= cur && nxt <= (int64_t)kValueMask &&
+                    (uint64_t)(nxt - cur) == total;
+    if (!ok) record_error(p.err, kRankSidecar, FD_ESIDECAR);
+    return ok ? cur : -1;
+}
+
 __device__ __forceinline__ uint64_t data_error_key(int64_t pos, int status) {
     return ((uint64_t)(pos + (int64_t)kRankData) << 4) | (uint64_t)status;
 }
@@ -1117,14 +1132,17 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         const bool early = kEarlyNext<CODEC> && !late;
         // (A) the tile's code offsets into LDS, validation
         uint32_t nid = 0;               // the next tile's id (requested as the look-back completes)
-        int64_t cur_reg = 0;
+        int64_t cur_reg = 0, nxt_reg = 0;
 #pragma unroll
         for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
             const int j = (int)tid + kWG * r;
             if (j <= g.ns) s.coff[j] = (int64_t)cr.v[r];
         }
         if constexpr (MODE == kModeExpand) {
-            if (tid == 0) cur_reg = (int64_t)p.tagg[t];
+            if (tid == 0) {
+                cur_reg = (int64_t)p.tagg[t];
+                nxt_reg = (int64_t)p.tagg[t + 1];
+            }
         }
         __syncthreads();
         {
@@ -1177,7 +1195,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                             if (tid == 0) s.cursor = (int64_t)ex;
                         }
                     } else {
-                        if (tid == 0) s.cursor = cur_reg;
+                        if (tid == 0) s.cursor = checked_cursor(p, t, cur_reg, nxt_reg, tile_total);
                     }
                     if (early && tid == 0) s.next_id = (int32_t)nid;
                     __syncthreads();
@@ -1226,7 +1244,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                         if (tid == 0) s.cursor = (int64_t)ex;
                     }
                 } else if constexpr (MODE == kModeExpand) {
-                    if (tid == 0) s.cursor = cur_reg;
+                    if (tid == 0) s.cursor = checked_cursor(p, t, cur_reg, nxt_reg, tsp);
                 }
                 if (early && tid == 0) s.next_id = (int32_t)nid;
             }
@@ -1247,7 +1265,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             }
             if constexpr (MODE != kModeTotals) {
                 if (single) cursor = uniform64(s.cursor);
-                if (nsp >= 1) {
+                if (nsp >= 1 && (MODE != kModeExpand || cursor >= 0)) {
                     const int64_t O = cursor + (int64_t)sp_base;
                     const int nwin = (int)uniform32(s.nwin);
                     for (int win = 0; win < nwin; win++) {
@@ -1269,7 +1287,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             sp_base += tsp;
         }
 
-        if constexpr (MODE != kModeTotals) {
+        if (MODE == kModeLookback || (MODE == kModeExpand && cursor >= 0)) {
             const int64_t endv = cursor + (int64_t)tile_total;
             for (int j = tid; j < g.ns; j += kWG) {
                 if (min(max(s.coff[j], g.a), g.b) >= g.b) ((IDX*)p.out_off)[g.i0 + j] = (IDX)endv;
@@ -1383,8 +1401,12 @@ __global__ void k_reset(unsigned long long* err, unsigned* counters, unsigned lo
     for (int64_t k = i; k < n; k += (int64_t)gridDim.x * blockDim.x) z[k] = 0;
 }
 
-// Single-workgroup exclusive scan of tile totals into tile cursors (in place).
-__global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* v, int64_t n) {
+// Single-workgroup exclusive scan of tile totals into tile cursors (in place);
+// with err non-null, the status of the errors recorded so far is published
+// after it (the sidecar build, whose totals pass publishes none).
+__global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* v, int64_t n,
+                                                      const unsigned long long* err, int32_t* status,
+                                                      int32_t* status2) {
     __shared__ uint64_t s_w[16];
     __shared__ uint64_t s_carry;
     const unsigned tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -1409,6 +1431,12 @@ __global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* v, int
         __syncthreads();
         if (tid == 0) s_carry += tot;
         __syncthreads();
+    }
+    if (err && tid == 0) {
+        const unsigned long long e = *err;
+        const int st = (e == ~0ull) ? FD_OK : (int)(e & 15ull);
+        if (status) *status = st;
+        if (status2) *status2 = st;
     }
 }
 
@@ -1559,8 +1587,9 @@ hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned lo
     return hipGetLastError();
 }
 
-hipError_t launch_scan_totals(unsigned long long* v, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, v, n);
+hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned long long* err, int32_t* status,
+                              int32_t* status2, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, v, n, err, status, status2);
     return hipGetLastError();
 }
 

@@ -114,3 +114,24 @@ def test_batch_argument_errors_enqueue_nothing(fdlib):
     assert L.fd_batch_workspace_size(arr, 1, None, ctypes.byref(sz)) == fdlib.EINVAL
     assert L.fd_batch_workspace_size(arr, 0, None, ctypes.byref(sz)) == 0 and sz.value >= 256
     assert L.fd_batch_workspace_size(arr, -1, None, ctypes.byref(sz)) == fdlib.EINVAL
+
+
+def test_sidecar_host_checks(fdlib):
+    """fd_sidecar_layout follows the tiling; the sidecar entry points reject a
+    missing dictionary, a sidecar of another tiling and three-phase tuning
+    before touching the device."""
+    fd = fdlib
+    tu = {"mode": 0, "strings_per_tile": 3, "grid": 0, "reserved": 0}
+    assert fd.sidecar_layout("fsst8", 1000, 10, tu) == (3, 5)
+    assert fd.sidecar_layout("onpair12", 1000, 0, tu) == (3, 2)
+    sb, n = fd.sidecar_layout("onpair16", 10 ** 6, 10 ** 4)
+    assert 1 <= sb <= 1024 and n == -(-10 ** 4 // sb) + 1
+    with pytest.raises(fd.DecodeError):
+        fd.sidecar_layout("fsst8", 1000, 10, {"mode": 1, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+    L = fd.lib()
+    P = ctypes.c_void_p
+    fake, ws = P(1 << 20), P(1 << 21)
+    assert L.fd_sidecar_build(None, fake, 10, fake, 64, 1, fake, 2, ws, 1 << 20, None, 0, None, None) == fd.EINVAL
+    assert L.fd_decode_sidecar(None, fake, 10, fake, 64, 1, fake, 2, fake, fake, 10, ws, 1 << 20, None, 0, None,
+                               None) == fd.EINVAL
+    assert fd.status_str(fd.ESIDECAR) == "FD_ESIDECAR"

@@ -344,6 +344,100 @@ def test_roundtrip_code12(oracle_mod, datagen_mod):
 
 
 # --------------------------------------------------------------------------- #
+# the sidecar (stored output positions per tile of strings)
+# --------------------------------------------------------------------------- #
+
+
+def tile_firsts(n_strings, sb):
+    """The first string of every tile, then n_strings (the sidecar's entries)."""
+    n_tiles = max(1, -(-n_strings // sb))
+    return [min(k * sb, n_strings) for k in range(n_tiles)] + [n_strings]
+
+
+def test_sidecar_by_hand(oracle_mod):
+    """Positions derived by hand.  FSST-8 table {0: "ab", 1: "c"}; strings
+    "abc" (codes 0 1), "x" (escape + literal), "ab" (0), "" and "cc" (1 1):
+    decoded lengths 3, 1, 2, 0, 2.  OnPair-16 tokens {"a", "bcd", "ef"};
+    strings of codes [1 2], [0], [2 2 1]: lengths 5, 1, 7."""
+    O = oracle_mod
+    db, dl = pack([b"ab", b"c"])
+    codes = np.array([0, 1, 255, ord("x"), 0, 1, 1], np.uint8)
+    off = np.array([0, 2, 4, 5, 5, 7], np.int64)
+    for sb, exp in ((1, [0, 3, 4, 6, 6, 8]), (2, [0, 4, 6, 8]), (3, [0, 6, 8]), (5, [0, 8]), (9, [0, 8])):
+        st, sc = O.sidecar("fsst8", codes, off, db, dl, sb)
+        assert st == O.OK and list(sc) == exp, sb
+    db, dl = pack([b"a", b"bcd", b"ef"])
+    st, sc = O.sidecar("onpair16", np.array([1, 2, 0, 2, 2, 1], np.uint16), np.array([0, 2, 3, 6], np.int64),
+                       db, dl, 2)
+    assert st == O.OK and list(sc) == [0, 6, 13]
+    # no strings: one empty tile
+    st, sc = O.sidecar("fsst8", np.zeros(0, np.uint8), np.array([0], np.int64), db[:1], dl[:1], 4)
+    assert st == O.OK and list(sc) == [0, 0]
+
+
+@pytest.mark.parametrize("sb", [1, 3, 64, 1000, 100000])
+def test_sidecar_is_the_source_offsets(oracle_mod, datagen_mod, sb):
+    """Decoding is lossless, so the stored positions are the source strings'
+    own offsets sampled at every tile's first string (the generator's offsets,
+    not a decode)."""
+    cols = [(datagen_mod.fsst_small(), "fsst8", None),
+            (datagen_mod.onpair_urls(target_bytes=1 << 20, sample_bytes=1 << 20), "onpair16", None)]
+    c12 = datagen_mod.onpair12_urls(target_bytes=1 << 19)
+    cols.append((c12, "onpair12", c12.stats["n_codes"]))
+    for c, codec, n_codes in cols:
+        st, sc = oracle_mod.sidecar(codec, c.codes, c.code_off, c.dict_bytes, c.dict_lens, sb, n_codes=n_codes)
+        assert st == 0
+        assert np.array_equal(sc, np.asarray(c.text_off, np.int64)[tile_firsts(c.n_strings, sb)]), codec
+
+
+def test_sidecar_escape_closed_form(oracle_mod, datagen_mod):
+    """With escapes, against the run-parity characterisation's offsets."""
+    rng = np.random.default_rng(5)
+    syms = [bytes(rng.integers(97, 123, int(k)).astype(np.uint8)) for k in rng.integers(1, 9, 200)]
+    db, dl = pack(syms)
+    n = 300
+    lens = rng.integers(0, 12, n)
+    code_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    pool = np.array(list(range(200)) + [255] * 60, np.uint8)
+    codes = pool[rng.integers(0, len(pool), int(code_off[-1]))]
+    for i in range(n):                         # no string ends in an unpaired escape
+        a, e = int(code_off[i]), int(code_off[i + 1])
+        if e > a and codes[e - 1] == 255:
+            codes[e - 1] = 7
+    st, offs, _ = closed_form_fsst8(codes.tobytes(), [int(x) for x in code_off], syms)
+    if st != 0:
+        pytest.skip("the random stream ended a string in an escape run")
+    for sb in (1, 7, 64):
+        st2, sc = oracle_mod.sidecar("fsst8", codes, code_off, db, dl, sb)
+        assert st2 == 0 and list(sc) == [offs[k] for k in tile_firsts(n, sb)]
+
+
+def test_decode_with_sidecar_precedence(oracle_mod):
+    """A matching sidecar gives the plain decode; any other gives ESIDECAR,
+    after the errors in the data and before EOVERFLOW / ECAPACITY."""
+    O = oracle_mod
+    db, dl = pack([b"ab", b"c"])
+    codes = np.array([0, 1, 255, ord("x"), 0, 1, 1], np.uint8)
+    off = np.array([0, 2, 4, 5, 5, 7], np.int64)
+    good = np.array([0, 4, 6, 8], np.int64)
+    r = O.decode_with_sidecar("fsst8", codes, off, db, dl, good, 2)
+    assert r.status == O.OK and bytes(r.out_bytes) == b"abcxabcc" and list(r.out_off) == [0, 3, 4, 6, 6, 8]
+    for bad in ([0, 4, 6, 9], [1, 4, 6, 8], [0, 5, 6, 8], [0, -4, 6, 8], [0, 4, 6, 1 << 62]):
+        assert O.decode_with_sidecar("fsst8", codes, off, db, dl, np.array(bad, np.int64), 2).status == O.ESIDECAR
+    # a wrong sidecar and too little room: ESIDECAR; the right one: ECAPACITY
+    assert O.decode_with_sidecar("fsst8", codes, off, db, dl, np.array([0, 4, 7, 8]), 2,
+                                 out_capacity=3).status == O.ESIDECAR
+    assert O.decode_with_sidecar("fsst8", codes, off, db, dl, good, 2, out_capacity=3).status == O.ECAPACITY
+    # an error in the data wins over a wrong sidecar
+    bad_codes = codes.copy()
+    bad_codes[5] = 9
+    assert O.decode_with_sidecar("fsst8", bad_codes, off, db, dl, good, 2).status == O.EBADCODE
+    assert O.sidecar("fsst8", bad_codes, off, db, dl, 2)[0] == O.EBADCODE
+    with pytest.raises(ValueError):              # a sidecar of another tiling
+        O.decode_with_sidecar("fsst8", codes, off, db, dl, good, 3)
+
+
+# --------------------------------------------------------------------------- #
 # errors and precedence
 # --------------------------------------------------------------------------- #
 
