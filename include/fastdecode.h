@@ -272,6 +272,42 @@ fd_status fd_decode_sidecar(const fd_dict *dict, const void *codes, int64_t n_co
                             void *hip_stream);
 
 /* ------------------------------------------------------------------------- */
+/* Selective decode (take)                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Dictionary codecs keep every string independently decodable, so a query can
+ * decode just the values it needs (the random access the paper's introduction
+ * and related-work section give as these codecs' motivation).
+ *
+ * fd_decode_take decodes the strings rows[0 .. n_rows) of a column, in that
+ * order, into a new Arrow string array: out_offsets[0 .. n_rows] (index_bits
+ * wide, like code_offsets) and out_bytes.  rows is a DEVICE int64 array (8-byte
+ * aligned); rows may repeat and come in any order.  Only the selected
+ * strings' codes and code offsets are read: errors in other strings are not
+ * seen.  The selected strings' codes are first compacted into the workspace
+ * (12-bit codes widened to 16 bits), then decoded by the same kernels as a
+ * whole column, so the result equals fd_decode_ex of the column made of the
+ * selected strings.
+ *   max_codes   an upper bound on the selected strings' total code count,
+ *               which sizes the workspace (n_codes when no row repeats);
+ *               a selection with more codes reports FD_ENOMEM.  index_bits 32
+ *               needs max_codes <= INT32_MAX.
+ *   tuning      as fd_decode_ex (mode must be 0); the automatic tile size
+ *               assumes the rows have the column's mean codes per string.
+ * Statuses: a row outside [0, n_strings) or a selected string whose code
+ * offsets are not ordered inside [0, n_codes] is FD_EOFFSETS; then FD_ENOMEM;
+ * then the decode's statuses, the data errors ranked by position in the
+ * selection.  n_rows = 0 writes out_offsets[0] = 0. */
+fd_status fd_take_workspace_size(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n_rows,
+                                 int64_t max_codes, const fd_tuning *tuning, size_t *bytes);
+
+fd_status fd_decode_take(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets,
+                         int index_bits, int64_t n_strings, const int64_t *rows, int64_t n_rows, int64_t max_codes,
+                         void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
+                         size_t workspace_bytes, int32_t *status, unsigned flags, const fd_tuning *tuning,
+                         void *hip_stream);
+
+/* ------------------------------------------------------------------------- */
 /* Batched decode                                                              */
 /* ------------------------------------------------------------------------- */
 

@@ -8,7 +8,7 @@ imports nothing from the library.
 
 Status numbering (a convention of the decode interface, restated here):
 0 OK, 1 EINVAL, 2 EBADCODE, 3 EESCAPE, 4 ECAPACITY, 5 EOVERFLOW, 6 EBADDICT,
-7 EOFFSETS, 10 ESIDECAR.
+7 EOFFSETS, 9 ENOMEM, 10 ESIDECAR.
 """
 from __future__ import annotations
 
@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS = range(8)
-ESIDECAR = 10
+ENOMEM, ESIDECAR = 9, 10
 
 
 def build(force: bool = True) -> str:
@@ -205,6 +205,42 @@ def decode_with_sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, stor
             n = len(code_off) - 1
             return Result(ESIDECAR, np.zeros(n + 1, np.int64), np.zeros(0, np.uint8), int(own[-1]), -1)
     return decode(codec, codes, code_off, dict_bytes, dict_lens, index_bits, out_capacity, n_codes)
+
+
+def take(codec: str, codes, code_off, dict_bytes, dict_lens, rows, max_codes: int | None = None,
+         index_bits: int | None = None, out_capacity: int | None = None, n_codes: int | None = None) -> Result:
+    """Selective decode: string i of the result is string rows[i] of the
+    column (dictionary codecs keep strings independently decodable: the
+    random access of the introduction and related work).  The selected
+    strings' codes, each string's whole, form a column of their own, which is
+    decoded.  A row outside the column, or a selected string whose code
+    offsets are not ordered inside [0, n_codes], is EOFFSETS; more than
+    ``max_codes`` selected codes is ENOMEM; then the decode's statuses."""
+    if codec == "onpair12":
+        packed = np.ascontiguousarray(codes, dtype=np.uint8)
+        n = (len(packed) * 8) // 12 if n_codes is None else int(n_codes)
+        codes, codec = unpack12_np(packed, n), "onpair16"
+    codes = np.ascontiguousarray(codes, dtype=np.uint8 if codec == "fsst8" else np.uint16)
+    code_off_arr = np.asarray(code_off)
+    co = _as_i64(code_off_arr)
+    n_strings = len(co) - 1
+    rows = np.asarray(rows, dtype=np.int64)
+    sel_off = np.zeros(len(rows) + 1, np.int64)
+    bad = Result(EOFFSETS, sel_off, np.zeros(0, np.uint8), 0, -1)
+    if len(rows) and (rows.min() < 0 or rows.max() >= n_strings):
+        return bad
+    a, b = co[rows], co[rows + 1]
+    if len(rows) and ((a < 0).any() or (b < a).any() or (b > len(codes)).any()):
+        return bad
+    lens = b - a
+    sel_off[1:] = np.cumsum(lens)
+    total = int(sel_off[-1])
+    if max_codes is not None and total > max_codes:
+        return Result(ENOMEM, sel_off, np.zeros(0, np.uint8), 0, -1)
+    # code j of the selection is code a[i] + (j - sel_off[i]) of the column, i its string
+    idx = np.repeat(a - sel_off[:-1], lens) + np.arange(total, dtype=np.int64)
+    return decode(codec, codes[idx], sel_off.astype(code_off_arr.dtype), dict_bytes, dict_lens, index_bits,
+                  out_capacity)
 
 
 def decode_onpair16_copy16(codes, code_off, dict_bytes, dict_lens):

@@ -126,6 +126,11 @@ def lib():
     L.fd_decode_sidecar.restype = ctypes.c_int
     L.fd_decode_sidecar.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, I64, P, P, I64, P, S, P, U,
                                     ctypes.POINTER(Tuning), P]
+    L.fd_take_workspace_size.restype = ctypes.c_int
+    L.fd_take_workspace_size.argtypes = [ctypes.c_int, I64, I64, I64, I64, ctypes.POINTER(Tuning), ctypes.POINTER(S)]
+    L.fd_decode_take.restype = ctypes.c_int
+    L.fd_decode_take.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, I64, I64, P, P, I64, P, S, P, U,
+                                 ctypes.POINTER(Tuning), P]
     L.fd_batch_workspace_size.restype = ctypes.c_int
     L.fd_batch_workspace_size.argtypes = [ctypes.POINTER(Column), I32, ctypes.POINTER(Tuning), ctypes.POINTER(S)]
     L.batch_decode.restype = ctypes.c_int
@@ -348,6 +353,52 @@ def decode_sidecar_into(d: Dict, codes, code_off, sidecar, out_off, out_bytes, w
                                    _ptr(out_off), _ptr(out_bytes), out_bytes.numel() if out_bytes is not None else 0,
                                    _ptr(workspace), workspace.numel(), _ptr(status), ASYNC if async_ else 0,
                                    _tuning(tuning), _stream_handle(stream))
+
+
+# --------------------------------------------------------------------------- #
+# selective decode (take)
+# --------------------------------------------------------------------------- #
+def take_workspace_size(codec, n_codes: int, n_strings: int, n_rows: int, max_codes: int, tuning=None) -> int:
+    out = ctypes.c_size_t(0)
+    tu = Tuning(**tuning) if isinstance(tuning, dict) else tuning
+    st = lib().fd_take_workspace_size(_codec_id(codec), int(n_codes), int(n_strings), int(n_rows), int(max_codes),
+                                      ctypes.byref(tu) if tu is not None else None, ctypes.byref(out))
+    if st:
+        raise DecodeError(st, "fd_take_workspace_size")
+    return int(out.value)
+
+
+def decode_take_into(d: Dict, codes, code_off, rows, max_codes: int, out_off, out_bytes, workspace, status=None,
+                     async_=False, tuning=None, stream=None, n_codes=None) -> int:
+    """fd_decode_take with preallocated outputs (rows: int64 device tensor);
+    returns the fd_status."""
+    return lib().fd_decode_take(d.handle, _ptr(codes), int(codes_in(d.codec, codes) if n_codes is None else n_codes),
+                                _ptr(code_off), _index_bits(code_off), code_off.numel() - 1, _ptr(rows),
+                                rows.numel(), int(max_codes), _ptr(out_off), _ptr(out_bytes),
+                                out_bytes.numel() if out_bytes is not None else 0, _ptr(workspace),
+                                workspace.numel(), _ptr(status), ASYNC if async_ else 0, _tuning(tuning),
+                                _stream_handle(stream))
+
+
+def decode_take(d: Dict, codes, code_off, rows, tuning=None, stream=None, n_codes=None):
+    """The strings `rows` of a column as new tensors (out_offsets, out_bytes);
+    rows must not repeat (the workspace holds at most the column's codes).
+    Runs a first pass with zero capacity for the exact size."""
+    torch = _torch()
+    dev = codes.device
+    n = codes_in(d.codec, codes) if n_codes is None else int(n_codes)
+    ws = torch.empty(take_workspace_size(d.codec, n, code_off.numel() - 1, rows.numel(), n, tuning),
+                     dtype=torch.uint8, device=dev)
+    out_off = torch.empty(rows.numel() + 1, dtype=code_off.dtype, device=dev)
+    empty = torch.empty(0, dtype=torch.uint8, device=dev)
+    st = decode_take_into(d, codes, code_off, rows, n, out_off, empty, ws, tuning=tuning, stream=stream, n_codes=n)
+    if st not in (OK, ECAPACITY):
+        raise DecodeError(st, "fd_decode_take")
+    out = torch.empty(int(out_off[-1].item()), dtype=torch.uint8, device=dev)
+    st = decode_take_into(d, codes, code_off, rows, n, out_off, out, ws, tuning=tuning, stream=stream, n_codes=n)
+    if st != OK:
+        raise DecodeError(st, "fd_decode_take")
+    return out_off, out
 
 
 # --------------------------------------------------------------------------- #

@@ -118,6 +118,36 @@ bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tunin
 
 fd_status hip_fail() { return FD_EHIP; }
 
+// Selective decode: the workspace holds the decode plan of the compacted
+// column (its tile words and block states after the header), the per-1,024-row
+// code counts, the compacted code offsets and the compacted codes.
+struct TakePlan {
+    Plan dec;              // tiling of the compacted column (n_rows strings)
+    fd_codec codec2;       // codec of the compacted codes (12-bit codes are widened to 16)
+    int64_t nblk;
+    size_t off_bsum, off_noff, off_codes, bytes;
+};
+
+bool take_plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n_rows, int64_t max_codes,
+                   const fd_tuning* tu, TakePlan* tp) {
+    if (n_codes < 0 || n_strings < 0 || n_rows < 0 || max_codes < 0) return false;
+    if (n_rows > (int64_t)1 << 40 || max_codes > (int64_t)1 << 40) return false;
+    if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
+    if (tu && tu->mode != 0) return false;
+    tp->codec2 = codec == FD_ONPAIR12 ? FD_ONPAIR16 : codec;
+    // tile size from the column's mean codes per string (the rows are a sample of it)
+    const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+    const int64_t est = (int64_t)(mean * (double)n_rows) + 1;
+    if (!plan_for(tp->codec2, est, n_rows, tu, &tp->dec)) return false;
+    tp->nblk = n_rows > 0 ? (n_rows + 1023) / 1024 : 1;
+    tp->off_bsum = tp->dec.off_dict;                                   // no dictionary repack here
+    tp->off_noff = align_up(tp->off_bsum + (size_t)(tp->nblk + 1) * 8, 256);
+    tp->off_codes = align_up(tp->off_noff + (size_t)(n_rows + 1) * 8, 256);
+    const size_t w = tp->codec2 == FD_FSST8 ? 1 : 2;
+    tp->bytes = align_up(tp->off_codes + (size_t)max_codes * w + 64, 256);
+    return true;
+}
+
 struct Args {
     fd_codec codec;
     const void* codes;
@@ -405,6 +435,92 @@ fd_status fd_decode_sidecar(const fd_dict* dict, const void* codes, int64_t n_co
     a.stream = (hipStream_t)hip_stream;
     a.sidecar_op = kSidecarDecode; a.sidecar = (int64_t*)sidecar; a.sidecar_n = n_entries;
     return run_decode(a);
+}
+
+fd_status fd_take_workspace_size(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n_rows, int64_t max_codes,
+                                 const fd_tuning* tuning, size_t* bytes) {
+    if (!bytes) return FD_EINVAL;
+    TakePlan tp;
+    if (!take_plan_for(codec, n_codes, n_strings, n_rows, max_codes, tuning, &tp)) return FD_EINVAL;
+    *bytes = tp.bytes;
+    return FD_OK;
+}
+
+fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets,
+                         int index_bits, int64_t n_strings, const int64_t* rows, int64_t n_rows, int64_t max_codes,
+                         void* out_offsets, uint8_t* out_bytes, int64_t out_capacity, void* workspace,
+                         size_t workspace_bytes, int32_t* status, unsigned flags, const fd_tuning* tuning,
+                         void* hip_stream) {
+    // ---------------- host-side validation ----------------
+    if (!dict || !code_offsets || !out_offsets || !workspace) return FD_EINVAL;
+    if (index_bits != 32 && index_bits != 64) return FD_EINVAL;
+    if (n_strings < 0 || n_codes < 0 || out_capacity < 0 || n_rows < 0 || max_codes < 0) return FD_EINVAL;
+    if (n_strings > (int64_t)1 << 40 || n_codes > (int64_t)1 << 40) return FD_EINVAL;
+    if (n_codes > 0 && !codes) return FD_EINVAL;
+    if (n_rows > 0 && (!rows || ((uintptr_t)rows & 7))) return FD_EINVAL;
+    if (out_capacity > 0 && !out_bytes) return FD_EINVAL;
+    if ((flags & FD_ASYNC) && !status) return FD_EINVAL;
+    if (flags & ~(unsigned)FD_ASYNC) return FD_EINVAL;
+    if (dict->codec == FD_ONPAIR16 && codes && ((uintptr_t)codes & 1)) return FD_EINVAL;
+    const size_t ia = index_bits / 8;
+    if (((uintptr_t)code_offsets & (ia - 1)) || ((uintptr_t)out_offsets & (ia - 1))) return FD_EINVAL;
+    if (index_bits == 32 && (n_codes > INT32_MAX || max_codes > INT32_MAX)) return FD_EINVAL;
+    if ((uintptr_t)workspace & 255) return FD_EINVAL;
+    if (tuning && tuning->grid < 0) return FD_EINVAL;
+    TakePlan tp;
+    if (!take_plan_for(dict->codec, n_codes, n_strings, n_rows, max_codes, tuning, &tp)) return FD_EINVAL;
+    if (workspace_bytes < tp.bytes) return FD_EINVAL;
+
+    uint8_t* ws = (uint8_t*)workspace;
+    hipStream_t st = (hipStream_t)hip_stream;
+    unsigned long long* err = (unsigned long long*)(ws + kOffErr);
+    unsigned* counters = (unsigned*)(ws + kOffCounters);
+    unsigned long long* tagg = (unsigned long long*)(ws + tp.dec.off_tiles);
+    if (launch_reset(err, counters, tagg, tp.dec.n_tiles + 1 + tp.dec.n_blocks, st) != hipSuccess) return hip_fail();
+    // compaction: the selected strings' codes, whole, one after another
+    uint8_t* ccodes = ws + tp.off_codes;
+    void* coff = ws + tp.off_noff;
+    if (launch_take_compact((int)dict->codec, index_bits, rows, n_rows, code_offsets, n_strings, n_codes,
+                            (const uint8_t*)codes, (unsigned long long*)(ws + tp.off_bsum), max_codes, coff, ccodes,
+                            err, st) != hipSuccess)
+        return hip_fail();
+    // the compacted column through the decode kernels
+    DecodeParams p;
+    memset(&p, 0, sizeof(p));
+    p.codes = ccodes;
+    p.n_codes = max_codes;
+    p.code_off = coff;
+    p.n_strings = n_rows;
+    p.out_off = out_offsets;
+    p.out = out_bytes;
+    p.out_cap = out_capacity;
+    p.n_tiles = tp.dec.n_tiles;
+    p.sb = (int32_t)tp.dec.sb;
+    p.err = err;
+    p.counters = counters;
+    p.tagg = tagg;
+    p.bstate = (unsigned long long*)(ws + tp.dec.off_blocks);
+    p.status = status;
+    p.status2 = (int32_t*)(ws + kOffStatus);
+    if (dict->codec == FD_FSST8) {
+        p.dict_bytes = dict->bytes;
+        p.dict_lens = dict->lens;
+        p.n_sym = dict->n;
+        p.fsst_tab = dict->fsst_tab;
+        p.fsst_len = dict->fsst_len;
+    } else {
+        p.tok16 = dict->tok16;
+        p.tok_len = dict->tok_len;
+    }
+    const int codec2 = (int)tp.codec2;
+    int grid = (tuning && tuning->grid) ? tuning->grid : resident_grid(codec2, index_bits, kModeLookback);
+    if ((int64_t)grid > tp.dec.n_tiles) grid = (int)tp.dec.n_tiles;
+    if (launch_decode(codec2, index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();
+    if (flags & FD_ASYNC) return FD_OK;
+    if (hipStreamSynchronize(st) != hipSuccess) return hip_fail();
+    int32_t hs = 0;
+    if (hipMemcpy(&hs, p.status2, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail();
+    return (fd_status)hs;
 }
 
 fd_status fd_decode(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets, int index_bits,

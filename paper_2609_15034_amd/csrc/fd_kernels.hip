@@ -1486,6 +1486,149 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
 }
 
 // --------------------------------------------------------------------------
+// selective decode: the strings a row list names, compacted into one code
+// stream (strings are independently decodable, so each keeps its codes
+// whole), which the decode kernels then expand as a column of their own
+// --------------------------------------------------------------------------
+constexpr int kTakeRows = 1024;     // rows per workgroup of the compaction kernels (256 threads x 4)
+
+// The code range of row i of the list, or an empty one (recording EOFFSETS
+// when err is given) for a row outside the column or with code offsets that
+// are not ordered and inside the code stream.
+template <typename IDX>
+__device__ __forceinline__ void take_row(const int64_t* rows, int64_t i, const IDX* code_off, int64_t n_strings,
+                                         int64_t n_codes, unsigned long long* err, int64_t& a, int64_t& len) {
+    a = 0;
+    len = 0;
+    const int64_t r = rows[i];
+    if (r < 0 || r >= n_strings) {
+        if (err) record_error(err, kRankOffsets, FD_EOFFSETS);
+        return;
+    }
+    const int64_t x = (int64_t)code_off[r], y = (int64_t)code_off[r + 1];
+    if (x < 0 || y < x || y > n_codes) {
+        if (err) record_error(err, kRankOffsets, FD_EOFFSETS);
+        return;
+    }
+    a = x;
+    len = y - x;
+}
+
+// Pass 1: the code count of every block of kTakeRows rows (bsum[blk]), and a
+// zero after the last for the scan that follows.
+template <typename IDX>
+__global__ void __launch_bounds__(256) k_take_sizes(const int64_t* rows, int64_t n_rows, const IDX* code_off,
+                                                    int64_t n_strings, int64_t n_codes, unsigned long long* bsum,
+                                                    unsigned long long* err) {
+    __shared__ uint64_t s_w[kNWave];
+    const unsigned tid = threadIdx.x, w = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTakeRows;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kTakeRows / 256; k++) {
+        const int64_t i = base + tid + 256 * k;
+        if (i < n_rows) {
+            int64_t a, len;
+            take_row(rows, i, code_off, n_strings, n_codes, err, a, len);
+            sum += (uint64_t)len;
+        }
+    }
+    sum = wave_sum_u64(sum);
+    if (lane_id() == 0) s_w[w] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        bsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (blockIdx.x == 0) bsum[gridDim.x] = 0;
+    }
+}
+
+// Pass 3 (after the exclusive scan of the block counts): each workgroup
+// writes its rows' offsets in the compacted stream and copies their codes,
+// widening 12-bit codes to 16 bits.  Positions at or past max_codes are not
+// written; the offsets are clamped to it and ENOMEM is recorded, so the
+// decode that follows stays inside the compacted buffer.
+template <int CIN, typename IDX>
+__global__ void __launch_bounds__(256) k_take_gather(const int64_t* rows, int64_t n_rows, const IDX* code_off,
+                                                     int64_t n_strings, int64_t n_codes, const uint8_t* codes,
+                                                     const unsigned long long* bsum, int64_t max_codes,
+                                                     IDX* new_off, uint8_t* dst, unsigned long long* err) {
+    __shared__ int64_t s_start[kTakeRows + 1];   // the block's rows: start in the block's output, then its end
+    __shared__ int64_t s_src[kTakeRows];         // ... and their first code in the column
+    __shared__ uint64_t s_w[kNWave];
+    constexpr int R = kTakeRows / 256;
+    const unsigned tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTakeRows;
+    int64_t a[R], len[R];
+    uint64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < R; k++) {                 // thread t holds rows base + R t .. + R - 1
+        const int64_t i = base + (int64_t)R * tid + k;
+        a[k] = 0;
+        len[k] = 0;
+        if (i < n_rows) take_row(rows, i, code_off, n_strings, n_codes, nullptr, a[k], len[k]);
+        tsum += (uint64_t)len[k];
+    }
+    uint64_t incl = tsum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(incl, d, 64);
+        if (lane >= (unsigned)d) incl += y;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    uint64_t loc = incl - tsum;
+    for (unsigned k = 0; k < w; k++) loc += s_w[k];
+    const uint64_t blk0 = bsum[blockIdx.x];
+    const uint64_t cap = (uint64_t)max_codes;
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const int j = R * (int)tid + k;
+        const int64_t i = base + j;
+        s_start[j] = (int64_t)loc;
+        s_src[j] = a[k];
+        if (i < n_rows) new_off[i] = (IDX)min(blk0 + loc, cap);
+        loc += (uint64_t)len[k];
+    }
+    const uint64_t blk_tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    if (tid == 0) {
+        s_start[kTakeRows] = (int64_t)blk_tot;
+        if (blockIdx.x == gridDim.x - 1) {
+            const uint64_t total = blk0 + blk_tot;
+            new_off[n_rows] = (IDX)min(total, cap);
+            if (total > cap) record_error(err, kRankOffsets, FD_ENOMEM);
+        }
+    }
+    __syncthreads();
+    const int64_t lim = (int64_t)min(blk_tot, blk0 < cap ? cap - blk0 : (uint64_t)0);
+    const int nr = (int)min((int64_t)kTakeRows, n_rows - base);
+    for (int64_t q = (int64_t)tid * 4; q < lim; q += 256 * 4) {
+        int lo = 0, hi = nr - 1;                  // the last row starting at or before q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        int j = lo;
+        for (int e = 0; e < 4; e++) {
+            const int64_t pq = q + e;
+            if (pq >= lim) break;
+            while (s_start[j + 1] <= pq) j++;     // past rows that end before pq (empty ones included)
+            const int64_t src = s_src[j] + (pq - s_start[j]);
+            const int64_t o = (int64_t)blk0 + pq;
+            if constexpr (CIN == kFsst8) {
+                dst[o] = codes[src];
+            } else if constexpr (CIN == kOnpair16) {
+                ((uint16_t*)dst)[o] = ((const uint16_t*)codes)[src];
+            } else {                              // code src: bits [12 src, 12 src + 12), least significant first
+                const int64_t bo = src + (src >> 1);
+                const uint32_t v = (uint32_t)codes[bo] | ((uint32_t)codes[bo + 1] << 8);
+                ((uint16_t*)dst)[o] = (uint16_t)((v >> ((src & 1) * 4)) & 0xfffu);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // host-side launch helpers
 // --------------------------------------------------------------------------
 template <int CODEC, typename IDX, int MODE>
@@ -1591,6 +1734,27 @@ hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned l
                               int32_t* status2, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, v, n, err, status, status2);
     return hipGetLastError();
+}
+
+hipError_t launch_take_compact(int codec, int index_bits, const int64_t* rows, int64_t n_rows,
+                               const void* code_off, int64_t n_strings, int64_t n_codes, const uint8_t* codes,
+                               unsigned long long* bsum, int64_t max_codes, void* new_off, uint8_t* dst,
+                               unsigned long long* err, hipStream_t st) {
+    const int64_t nblk = n_rows > 0 ? (n_rows + kTakeRows - 1) / kTakeRows : 1;
+    if (nblk > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+#define TAKE(C, I)                                                                                             \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8)) {                                                     \
+        hipLaunchKernelGGL((k_take_sizes<I>), dim3((unsigned)nblk), dim3(256), 0, st, rows, n_rows,              \
+                           (const I*)code_off, n_strings, n_codes, bsum, err);                                   \
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, bsum, nblk + 1, nullptr, nullptr, nullptr); \
+        hipLaunchKernelGGL((k_take_gather<C, I>), dim3((unsigned)nblk), dim3(256), 0, st, rows, n_rows,          \
+                           (const I*)code_off, n_strings, n_codes, codes, bsum, max_codes, (I*)new_off, dst, err); \
+        return hipGetLastError();                                                                                \
+    }
+    TAKE(kFsst8, int32_t) TAKE(kFsst8, int64_t) TAKE(kOnpair16, int32_t) TAKE(kOnpair16, int64_t)
+    TAKE(kOnpair12, int32_t) TAKE(kOnpair12, int64_t)
+#undef TAKE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int32_t n_tok, uint4* tok16,

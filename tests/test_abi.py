@@ -135,3 +135,24 @@ def test_sidecar_host_checks(fdlib):
     assert L.fd_decode_sidecar(None, fake, 10, fake, 64, 1, fake, 2, fake, fake, 10, ws, 1 << 20, None, 0, None,
                                None) == fd.EINVAL
     assert fd.status_str(fd.ESIDECAR) == "FD_ESIDECAR"
+
+
+def test_take_host_checks(fdlib):
+    """fd_take_workspace_size grows with the code budget and rejects
+    three-phase tuning; fd_decode_take rejects a missing dictionary."""
+    fd = fdlib
+    a = fd.take_workspace_size("fsst8", 10 ** 6, 10 ** 4, 100, 0)
+    b = fd.take_workspace_size("fsst8", 10 ** 6, 10 ** 4, 100, 10 ** 5)
+    c = fd.take_workspace_size("onpair12", 10 ** 6, 10 ** 4, 100, 10 ** 5)
+    assert b - a >= 10 ** 5 - 256 and c - b >= 10 ** 5 - 256    # 256-byte rounding; OnPair-12 codes widen to 16 bits
+    assert fd.take_workspace_size("onpair16", 0, 0, 0, 0) > 0
+    for bad in ((10 ** 6, 10 ** 4, -1, 0), (10 ** 6, 10 ** 4, 1, -1)):
+        with pytest.raises(fd.DecodeError):
+            fd.take_workspace_size("fsst8", *bad)
+    with pytest.raises(fd.DecodeError):
+        fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 1, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+    L = fd.lib()
+    P = ctypes.c_void_p
+    fake, ws = P(1 << 20), P(1 << 21)
+    assert L.fd_decode_take(None, fake, 10, fake, 64, 1, fake, 1, 10, fake, fake, 10, ws, 1 << 20, None, 0, None,
+                            None) == fd.EINVAL

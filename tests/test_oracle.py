@@ -438,6 +438,80 @@ def test_decode_with_sidecar_precedence(oracle_mod):
 
 
 # --------------------------------------------------------------------------- #
+# selective decode (take)
+# --------------------------------------------------------------------------- #
+
+
+def source_take(text, text_off, rows):
+    """The selected source strings (the generator's text, no decode)."""
+    parts = [bytes(text[int(text_off[r]):int(text_off[r + 1])]) for r in rows]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    return off, b"".join(parts)
+
+
+def test_take_by_hand(oracle_mod):
+    """Hand-derived: FSST-8 table {0: "ab", 1: "c"}; strings "abc", "x"
+    (escape + literal), "ab", "" and "cc"."""
+    O = oracle_mod
+    db, dl = pack([b"ab", b"c"])
+    codes = np.array([0, 1, 255, ord("x"), 0, 1, 1], np.uint8)
+    off = np.array([0, 2, 4, 5, 5, 7], np.int64)
+    for rows, exp_off, exp in (([4, 0], [0, 2, 5], b"ccabc"), ([1, 1, 3], [0, 1, 2, 2], b"xx"), ([], [0], b""),
+                               ([3], [0, 0], b""), ([2, 1, 0], [0, 2, 3, 6], b"abxabc")):
+        r = O.take("fsst8", codes, off, db, dl, rows)
+        assert r.status == O.OK and list(r.out_off) == exp_off and bytes(r.out_bytes) == exp, rows
+
+
+@pytest.mark.parametrize("order", ["sorted", "random", "repeats", "all", "reversed"])
+def test_take_is_the_source_strings(oracle_mod, datagen_mod, order):
+    """Against the generator's own strings, for three codecs."""
+    rng = np.random.default_rng(len(order))
+    cols = [(datagen_mod.fsst_small(), None),
+            (datagen_mod.onpair_urls(target_bytes=1 << 20, sample_bytes=1 << 20), None)]
+    c12 = datagen_mod.onpair12_urls(target_bytes=1 << 19)
+    cols.append((c12, c12.stats["n_codes"]))
+    for c, n_codes in cols:
+        n = c.n_strings
+        if order == "sorted":
+            rows = np.sort(rng.choice(n, n // 10, replace=False))
+        elif order == "random":
+            rows = rng.choice(n, n // 10, replace=False)
+        elif order == "repeats":
+            rows = rng.integers(0, n, n // 5)
+        elif order == "all":
+            rows = np.arange(n)
+        else:
+            rows = np.arange(n)[::-1]
+        r = oracle_mod.take(c.codec, c.codes, c.code_off, c.dict_bytes, c.dict_lens, rows, n_codes=n_codes)
+        exp_off, exp = source_take(c.text, c.text_off, rows)
+        assert r.status == 0 and np.array_equal(r.out_off, exp_off) and bytes(r.out_bytes) == exp, c.codec
+
+
+def test_take_errors(oracle_mod):
+    O = oracle_mod
+    db, dl = pack([b"ab", b"c"])
+    codes = np.array([0, 1, 255, ord("x"), 0, 9, 1], np.uint8)      # string 3 ("9") has a bad code
+    off = np.array([0, 2, 4, 5, 6, 7], np.int64)
+    assert O.take("fsst8", codes, off, db, dl, [0, 5]).status == O.EOFFSETS
+    assert O.take("fsst8", codes, off, db, dl, [-1]).status == O.EOFFSETS
+    assert O.take("fsst8", codes, off, db, dl, [0, 1]).status == O.OK          # the bad string is not selected
+    assert O.take("fsst8", codes, off, db, dl, [0, 3]).status == O.EBADCODE
+    # a budget of codes: 2 + 2 codes selected
+    assert O.take("fsst8", codes, off, db, dl, [0, 1], max_codes=3).status == O.ENOMEM
+    assert O.take("fsst8", codes, off, db, dl, [0, 1], max_codes=4).status == O.OK
+    # EOFFSETS before ENOMEM before data errors
+    assert O.take("fsst8", codes, off, db, dl, [3, 7], max_codes=0).status == O.EOFFSETS
+    assert O.take("fsst8", codes, off, db, dl, [3], max_codes=0).status == O.ENOMEM
+    # offsets of a selected string out of order; those of others are not read
+    off2 = np.array([0, 2, 1, 5, 6, 7], np.int64)
+    assert O.take("fsst8", codes, off2, db, dl, [1]).status == O.EOFFSETS
+    assert O.take("fsst8", codes, off2, db, dl, [3, 4]).status == O.EBADCODE
+    # capacity
+    r = O.take("fsst8", codes, off, db, dl, [0, 2], out_capacity=2)
+    assert r.status == O.ECAPACITY and list(r.out_off) == [0, 3, 5]
+
+
+# --------------------------------------------------------------------------- #
 # errors and precedence
 # --------------------------------------------------------------------------- #
 
