@@ -26,7 +26,8 @@ Prints one JSON line:
 
 The default run (fsst_logs) also reports the other 1 GiB columns' rates, the
 sidecar decode against the look-back on the FSST-8 and OnPair-16 columns
-("sidecar"), and, in "batch" and "serve", short runs of the batched workload
+("sidecar"), selective decode of row subsets of those columns ("take"), and,
+in "batch" and "serve", short runs of the batched workload
 (256 columns in one replayed HIP graph, against the same columns decoded one
 call each) and of the served workload (Poisson arrivals into the
 continuous-batching server, p50/p99 latency); --no-extra skips them.
@@ -200,6 +201,53 @@ def sidecar_rates(workload: str, steps: int = 20, seed: int | None = None) -> di
     return {"sidecar_GBps": round(D / t_sc / 1e9, 2), "lookback_GBps": round(D / t_lb / 1e9, 2),
             "regeneration_cost": round(t_lb / t_sc - 1.0, 3), "sidecar_bytes": int(sc.numel() * 8),
             "bit_exact": bool(ok)}
+
+
+def take_rates(workload: str, steps: int = 10, seed: int | None = None,
+               shares=(0.001, 0.01, 0.1, 0.5, 1.0)) -> dict:
+    """Selective decode of one 1 GiB column: random subsets of the rows (a
+    share of them, in row order as a filter gives them, and one share in
+    random order as a take gives them), each decoded with fd_decode_take and
+    checked against the source strings; against the whole-column decode."""
+    import numpy as np
+    import torch
+    import paper_2609_15034_amd as fd
+    col = make_column(workload, seed)
+    dev = torch.device("cuda")
+    codes, code_off = _upload_column(col, dev)
+    d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
+    n_codes = fd.codes_in(col.codec, codes)
+    co = np.asarray(col.code_off, np.int64)
+    to = np.asarray(col.text_off, np.int64)
+    text = torch.from_numpy(col.text).to(dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(fd.take_workspace_size(col.codec, n_codes, col.n_strings, col.n_strings, n_codes),
+                     dtype=torch.uint8, device=dev)
+    rng = np.random.default_rng(17)
+    out_all = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
+    res = {}
+    for share, order in [(x, "row order") for x in shares] + [(0.1, "random order")]:
+        k = max(1, int(round(share * col.n_strings)))
+        rows = np.sort(rng.choice(col.n_strings, k, replace=False)) if share < 1.0 else np.arange(col.n_strings)
+        if order == "random order":
+            rng.shuffle(rows)
+        D = int((to[rows + 1] - to[rows]).sum())
+        rows_t = torch.from_numpy(rows.astype(np.int64)).to(dev)
+        out = out_all[:D]
+        out_off = torch.empty(k + 1, dtype=code_off.dtype, device=dev)
+        fn = lambda: fd.decode_take_into(d, codes, code_off, rows_t, n_codes, out_off, out, ws, status=st,
+                                         async_=True)
+        t, _ = _events_time(fn, steps, 2)
+        # the source strings, gathered on the device for the check
+        lens = torch.from_numpy(to[rows + 1] - to[rows]).to(dev)
+        idx = torch.repeat_interleave(torch.from_numpy(to[rows]).to(dev) -
+                                      torch.cumsum(lens, 0) + lens, lens) + torch.arange(D, device=dev)
+        ok = int(st.item()) == fd.OK and torch.equal(out, text[idx])
+        res[f"{share:g} {order}"] = {"rows": k, "decoded_bytes": D, "us": round(t * 1e6, 1),
+                                     "GBps": round(D / t / 1e9, 2), "Mrows_per_s": round(k / t / 1e6, 1),
+                                     "bit_exact": bool(ok)}
+        del idx, lens
+    return res
 
 
 def run_batch(steps: int, warmup: int, seed: int | None, n_cols: int = 256, max_bytes: int = 64 << 20,
@@ -587,6 +635,12 @@ def main():
                 res[wl + "_GBps"] = round(single_rate(wl), 2)
             except Exception as e:
                 res[wl + "_GBps"] = {"error": f"{type(e).__name__}: {e}"}
+        res["take"] = {}
+        for wl in ("fsst_logs", "onpair_urls"):          # selective decode at several selectivities
+            try:
+                res["take"][wl] = take_rates(wl)
+            except Exception as e:
+                res["take"][wl] = {"error": f"{type(e).__name__}: {e}"}
         res["sidecar"] = {}
         for wl in ("fsst_logs", "onpair_urls"):          # stored positions against regenerated ones
             try:

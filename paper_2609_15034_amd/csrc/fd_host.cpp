@@ -125,7 +125,7 @@ struct TakePlan {
     Plan dec;              // tiling of the compacted column (n_rows strings)
     fd_codec codec2;       // codec of the compacted codes (12-bit codes are widened to 16)
     int64_t nblk;
-    size_t off_bsum, off_noff, off_codes, bytes;
+    size_t off_bsum, off_noff, off_src, off_codes, bytes;
 };
 
 bool take_plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n_rows, int64_t max_codes,
@@ -142,7 +142,8 @@ bool take_plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n
     tp->nblk = n_rows > 0 ? (n_rows + 1023) / 1024 : 1;
     tp->off_bsum = tp->dec.off_dict;                                   // no dictionary repack here
     tp->off_noff = align_up(tp->off_bsum + (size_t)(tp->nblk + 1) * 8, 256);
-    tp->off_codes = align_up(tp->off_noff + (size_t)(n_rows + 1) * 8, 256);
+    tp->off_src = align_up(tp->off_noff + (size_t)(n_rows + 1) * 8, 256);
+    tp->off_codes = align_up(tp->off_src + (size_t)n_rows * 8, 256);
     const size_t w = tp->codec2 == FD_FSST8 ? 1 : 2;
     tp->bytes = align_up(tp->off_codes + (size_t)max_codes * w + 64, 256);
     return true;
@@ -480,9 +481,13 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     // compaction: the selected strings' codes, whole, one after another
     uint8_t* ccodes = ws + tp.off_codes;
     void* coff = ws + tp.off_noff;
+    // copy workgroups of about 4,096 codes at the column's mean codes per string
+    const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+    int rows_per_wg = 16;
+    while (rows_per_wg < 1024 && (double)(2 * rows_per_wg) * mean <= 4096.0) rows_per_wg *= 2;
     if (launch_take_compact((int)dict->codec, index_bits, rows, n_rows, code_offsets, n_strings, n_codes,
-                            (const uint8_t*)codes, (unsigned long long*)(ws + tp.off_bsum), max_codes, coff, ccodes,
-                            err, st) != hipSuccess)
+                            (const uint8_t*)codes, (unsigned long long*)(ws + tp.off_bsum), max_codes, coff,
+                            (int64_t*)(ws + tp.off_src), ccodes, rows_per_wg, err, st) != hipSuccess)
         return hip_fail();
     // the compacted column through the decode kernels
     DecodeParams p;

@@ -84,12 +84,13 @@ hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned l
 // Selective decode: compact the codes of the rows rows[0, n_rows) of a column
 // into dst (uint8 for FSST-8, uint16 for OnPair-16 and widened OnPair-12) with
 // their offsets new_off[0, n_rows] (index_bits wide), using bsum (one word
-// per 1,024 rows, plus one) as scratch.  Bad rows or offsets record EOFFSETS;
-// more than max_codes codes record ENOMEM (the stream is then cut there).
+// per 1,024 rows, plus one) and src (n_rows words) as scratch; a copy
+// workgroup handles rows_per_wg (1..1,024) rows.  Bad rows or offsets record EOFFSETS; more than max_codes
+// codes record ENOMEM (the stream is then cut there).
 hipError_t launch_take_compact(int codec, int index_bits, const int64_t* rows, int64_t n_rows,
                                const void* code_off, int64_t n_strings, int64_t n_codes, const uint8_t* codes,
-                               unsigned long long* bsum, int64_t max_codes, void* new_off, uint8_t* dst,
-                               unsigned long long* err, hipStream_t st);
+                               unsigned long long* bsum, int64_t max_codes, void* new_off, int64_t* src, uint8_t* dst,
+                               int rows_per_wg, unsigned long long* err, hipStream_t st);
 int batch_occupancy(int codec, int index_bits);
 hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
                                int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st);

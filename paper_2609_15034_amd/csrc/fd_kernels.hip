@@ -1542,18 +1542,14 @@ __global__ void __launch_bounds__(256) k_take_sizes(const int64_t* rows, int64_t
     }
 }
 
-// Pass 3 (after the exclusive scan of the block counts): each workgroup
-// writes its rows' offsets in the compacted stream and copies their codes,
-// widening 12-bit codes to 16 bits.  Positions at or past max_codes are not
-// written; the offsets are clamped to it and ENOMEM is recorded, so the
-// decode that follows stays inside the compacted buffer.
-template <int CIN, typename IDX>
-__global__ void __launch_bounds__(256) k_take_gather(const int64_t* rows, int64_t n_rows, const IDX* code_off,
-                                                     int64_t n_strings, int64_t n_codes, const uint8_t* codes,
-                                                     const unsigned long long* bsum, int64_t max_codes,
-                                                     IDX* new_off, uint8_t* dst, unsigned long long* err) {
-    __shared__ int64_t s_start[kTakeRows + 1];   // the block's rows: start in the block's output, then its end
-    __shared__ int64_t s_src[kTakeRows];         // ... and their first code in the column
+// Pass 3 (after the exclusive scan of the block counts): each row's offset in
+// the compacted stream (new_off, clamped to max_codes, recording ENOMEM past
+// it) and its first code in the column (src).
+template <typename IDX>
+__global__ void __launch_bounds__(256) k_take_offsets(const int64_t* rows, int64_t n_rows, const IDX* code_off,
+                                                      int64_t n_strings, int64_t n_codes,
+                                                      const unsigned long long* bsum, int64_t max_codes,
+                                                      IDX* new_off, int64_t* src, unsigned long long* err) {
     __shared__ uint64_t s_w[kNWave];
     constexpr int R = kTakeRows / 256;
     const unsigned tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
@@ -1576,53 +1572,66 @@ __global__ void __launch_bounds__(256) k_take_gather(const int64_t* rows, int64_
     }
     if (lane == 63) s_w[w] = incl;
     __syncthreads();
-    uint64_t loc = incl - tsum;
+    uint64_t loc = bsum[blockIdx.x] + incl - tsum;
     for (unsigned k = 0; k < w; k++) loc += s_w[k];
-    const uint64_t blk0 = bsum[blockIdx.x];
     const uint64_t cap = (uint64_t)max_codes;
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        const int j = R * (int)tid + k;
-        const int64_t i = base + j;
-        s_start[j] = (int64_t)loc;
-        s_src[j] = a[k];
-        if (i < n_rows) new_off[i] = (IDX)min(blk0 + loc, cap);
+        const int64_t i = base + (int64_t)R * tid + k;
+        if (i < n_rows) {
+            new_off[i] = (IDX)min(loc, cap);
+            src[i] = a[k];
+        }
         loc += (uint64_t)len[k];
     }
-    const uint64_t blk_tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-    if (tid == 0) {
-        s_start[kTakeRows] = (int64_t)blk_tot;
-        if (blockIdx.x == gridDim.x - 1) {
-            const uint64_t total = blk0 + blk_tot;
-            new_off[n_rows] = (IDX)min(total, cap);
-            if (total > cap) record_error(err, kRankOffsets, FD_ENOMEM);
-        }
+    if (tid == 0 && blockIdx.x == gridDim.x - 1) {
+        const uint64_t total = bsum[blockIdx.x] + s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        new_off[n_rows] = (IDX)min(total, cap);
+        if (total > cap) record_error(err, kRankOffsets, FD_ENOMEM);
+    }
+}
+
+// Pass 4: copy the selected codes, widening 12-bit codes to 16 bits.  A
+// workgroup copies the codes of rows_per_wg consecutive rows (chosen so that
+// it holds a few thousand codes at the column's mean codes per string); their
+// offsets are staged in LDS and each thread finds the row holding its group of
+// 4 consecutive codes by a binary search there.
+template <int CIN, typename IDX>
+__global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_wg, const uint8_t* codes,
+                                                   const IDX* new_off, const int64_t* src, uint8_t* dst) {
+    __shared__ int64_t s_off[kTakeRows + 1];
+    __shared__ int64_t s_src[kTakeRows];
+    const unsigned tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * rows_per_wg;
+    const int nr = (int)min((int64_t)rows_per_wg, n_rows - base);
+    for (int j = tid; j <= nr; j += 256) {
+        s_off[j] = (int64_t)new_off[base + j];
+        if (j < nr) s_src[j] = src[base + j];
     }
     __syncthreads();
-    const int64_t lim = (int64_t)min(blk_tot, blk0 < cap ? cap - blk0 : (uint64_t)0);
-    const int nr = (int)min((int64_t)kTakeRows, n_rows - base);
+    const int64_t o0 = s_off[0], lim = s_off[nr] - o0;
     for (int64_t q = (int64_t)tid * 4; q < lim; q += 256 * 4) {
         int lo = 0, hi = nr - 1;                  // the last row starting at or before q
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (s_start[mid] <= q) lo = mid;
+            if (s_off[mid] - o0 <= q) lo = mid;
             else hi = mid - 1;
         }
         int j = lo;
         for (int e = 0; e < 4; e++) {
             const int64_t pq = q + e;
             if (pq >= lim) break;
-            while (s_start[j + 1] <= pq) j++;     // past rows that end before pq (empty ones included)
-            const int64_t src = s_src[j] + (pq - s_start[j]);
-            const int64_t o = (int64_t)blk0 + pq;
+            while (s_off[j + 1] - o0 <= pq) j++;  // past rows that end before pq (empty ones included)
+            const int64_t sc = s_src[j] + (pq - (s_off[j] - o0));
+            const int64_t o = o0 + pq;
             if constexpr (CIN == kFsst8) {
-                dst[o] = codes[src];
+                dst[o] = codes[sc];
             } else if constexpr (CIN == kOnpair16) {
-                ((uint16_t*)dst)[o] = ((const uint16_t*)codes)[src];
-            } else {                              // code src: bits [12 src, 12 src + 12), least significant first
-                const int64_t bo = src + (src >> 1);
+                ((uint16_t*)dst)[o] = ((const uint16_t*)codes)[sc];
+            } else {                              // code sc: bits [12 sc, 12 sc + 12), least significant first
+                const int64_t bo = sc + (sc >> 1);
                 const uint32_t v = (uint32_t)codes[bo] | ((uint32_t)codes[bo + 1] << 8);
-                ((uint16_t*)dst)[o] = (uint16_t)((v >> ((src & 1) * 4)) & 0xfffu);
+                ((uint16_t*)dst)[o] = (uint16_t)((v >> ((sc & 1) * 4)) & 0xfffu);
             }
         }
     }
@@ -1738,18 +1747,23 @@ hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned l
 
 hipError_t launch_take_compact(int codec, int index_bits, const int64_t* rows, int64_t n_rows,
                                const void* code_off, int64_t n_strings, int64_t n_codes, const uint8_t* codes,
-                               unsigned long long* bsum, int64_t max_codes, void* new_off, uint8_t* dst,
-                               unsigned long long* err, hipStream_t st) {
+                               unsigned long long* bsum, int64_t max_codes, void* new_off, int64_t* src, uint8_t* dst,
+                               int rows_per_wg, unsigned long long* err, hipStream_t st) {
     const int64_t nblk = n_rows > 0 ? (n_rows + kTakeRows - 1) / kTakeRows : 1;
-    if (nblk > (int64_t)INT32_MAX) return hipErrorInvalidValue;
-#define TAKE(C, I)                                                                                             \
-    if (codec == C && index_bits == (int)(sizeof(I) * 8)) {                                                     \
-        hipLaunchKernelGGL((k_take_sizes<I>), dim3((unsigned)nblk), dim3(256), 0, st, rows, n_rows,              \
-                           (const I*)code_off, n_strings, n_codes, bsum, err);                                   \
-        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, bsum, nblk + 1, nullptr, nullptr, nullptr); \
-        hipLaunchKernelGGL((k_take_gather<C, I>), dim3((unsigned)nblk), dim3(256), 0, st, rows, n_rows,          \
-                           (const I*)code_off, n_strings, n_codes, codes, bsum, max_codes, (I*)new_off, dst, err); \
-        return hipGetLastError();                                                                                \
+    if (nblk > (int64_t)INT32_MAX || rows_per_wg < 1 || rows_per_wg > kTakeRows) return hipErrorInvalidValue;
+    const int64_t ncopy = (n_rows + rows_per_wg - 1) / rows_per_wg;
+    if (ncopy > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+#define TAKE(C, I)                                                                                              \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8)) {                                                      \
+        hipLaunchKernelGGL((k_take_sizes<I>), dim3((unsigned)nblk), dim3(256), 0, st, rows, n_rows,               \
+                           (const I*)code_off, n_strings, n_codes, bsum, err);                                    \
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, bsum, nblk + 1, nullptr, nullptr, nullptr);  \
+        hipLaunchKernelGGL((k_take_offsets<I>), dim3((unsigned)nblk), dim3(256), 0, st, rows, n_rows,             \
+                           (const I*)code_off, n_strings, n_codes, bsum, max_codes, (I*)new_off, src, err);       \
+        if (n_rows > 0)                                                                                           \
+            hipLaunchKernelGGL((k_take_copy<C, I>), dim3((unsigned)ncopy), dim3(256), 0, st, n_rows, rows_per_wg, \
+                               codes, (const I*)new_off, src, dst);                                               \
+        return hipGetLastError();                                                                                 \
     }
     TAKE(kFsst8, int32_t) TAKE(kFsst8, int64_t) TAKE(kOnpair16, int32_t) TAKE(kOnpair16, int64_t)
     TAKE(kOnpair12, int32_t) TAKE(kOnpair12, int64_t)
