@@ -635,25 +635,23 @@ def main():
                 res[wl + "_GBps"] = round(single_rate(wl), 2)
             except Exception as e:
                 res[wl + "_GBps"] = {"error": f"{type(e).__name__}: {e}"}
-        res["take"] = {}
-        for wl in ("fsst_logs", "onpair_urls"):          # selective decode at several selectivities
-            try:
-                res["take"][wl] = take_rates(wl)
-            except Exception as e:
-                res["take"][wl] = {"error": f"{type(e).__name__}: {e}"}
-        res["sidecar"] = {}
-        for wl in ("fsst_logs", "onpair_urls"):          # stored positions against regenerated ones
-            try:
-                res["sidecar"][wl] = sidecar_rates(wl)
-            except Exception as e:
-                res["sidecar"][wl] = {"error": f"{type(e).__name__}: {e}"}
+        # the batched and served legs first, on a fresh allocator (the legs after them hold large buffers)
         for key, fn in (("batch", lambda: run_batch(10, 2, None, check=not args.no_check, cpu=False,
                                                     single_rates=rates if len(rates) == 2 else None)),
                         ("serve", lambda: run_serve(None, n_requests=2000, check=not args.no_check))):
+            torch.cuda.empty_cache()
             try:
                 res[key] = fn()
             except Exception as e:       # report, never lose the main line
                 res[key] = {"error": f"{type(e).__name__}: {e}"}
+        for key, fn in (("sidecar", sidecar_rates), ("take", take_rates)):
+            res[key] = {}
+            for wl in ("fsst_logs", "onpair_urls"):
+                torch.cuda.empty_cache()
+                try:
+                    res[key][wl] = fn(wl)
+                except Exception as e:
+                    res[key][wl] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(res), flush=True)
 
 
