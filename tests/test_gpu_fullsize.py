@@ -7,7 +7,9 @@ benchmark times (automatic tiling, resident grid, asynchronous status):
   lossless, so that is the expected result at any size), and sampled runs of
   strings across the column are checked against the oracle one run at a time;
 - the 256-column batch (2.26 GB) as one replayed graph: every column equals its
-  source text, and sampled runs of each of a few columns match the oracle."""
+  source text, and sampled runs of each of a few columns match the oracle;
+- the 1 GiB FSST-8 and OnPair-16 columns through the stored-sidecar decode and
+  a 10% selection in random order, against the source offsets and text."""
 import numpy as np
 import pytest
 
@@ -102,3 +104,52 @@ def test_full_batch(datagen_mod, oracle_mod):
     for k in rng.choice(len(cols), size=6, replace=False):
         c, t = cols[int(k)], tups[int(k)]
         check_runs_against_oracle(c, t[3].cpu().numpy().astype(np.int64), t[4].cpu().numpy(), rng, n_runs=8)
+
+
+@pytest.mark.parametrize("workload,seed", [("fsst_logs", 2), ("onpair_urls", 3)])
+def test_full_column_sidecar_and_take(datagen_mod, workload, seed):
+    """The 1 GiB columns through the stored-sidecar decode and a 10% selection
+    in random order, as the benchmark runs them: the sidecar equals the source
+    offsets at every tile's first string, both outputs equal the source text."""
+    import torch
+    import paper_2609_15034_amd as fd
+    col = getattr(datagen_mod, workload)(seed=seed)
+    dev = torch.device("cuda")
+    codes = torch.from_numpy(col.codes.view(np.int16) if col.codec == "onpair16" else col.codes).to(dev)
+    code_off = torch.from_numpy(col.code_off).to(dev)
+    d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
+    text = torch.from_numpy(col.text).to(dev)
+    to = np.asarray(col.text_off, np.int64)
+    # sidecar: built on the device, checked against the source offsets, then decoded with
+    sb, n_entries = fd.sidecar_layout(col.codec, codes.numel(), col.n_strings)
+    sc = fd.sidecar_build(d, codes, code_off)
+    firsts = [min(k * sb, col.n_strings) for k in range(n_entries - 1)] + [col.n_strings]
+    assert np.array_equal(sc.cpu().numpy(), to[firsts])
+    out = torch.full((col.decoded_bytes + 64,), 0xA5, dtype=torch.uint8, device=dev)
+    out_off = torch.full((col.n_strings + 1,), -7, dtype=code_off.dtype, device=dev)
+    ws = fd.alloc_workspace(col.codec, codes.numel(), col.n_strings)
+    st = fd.decode_sidecar_into(d, codes, code_off, sc, out_off, out[:col.decoded_bytes], ws)
+    assert st == fd.OK
+    assert torch.equal(out[:col.decoded_bytes], text)
+    assert torch.equal(out_off.to(torch.int64), torch.from_numpy(to).to(dev))
+    assert bool((out[col.decoded_bytes:] == 0xA5).all())
+    del out, out_off, ws, sc
+    # take: 10% of the rows in random order
+    rng = np.random.default_rng(seed + 200)
+    rows = rng.choice(col.n_strings, col.n_strings // 10, replace=False)
+    lens = to[rows + 1] - to[rows]
+    D = int(lens.sum())
+    ws = torch.empty(fd.take_workspace_size(col.codec, codes.numel(), col.n_strings, len(rows), codes.numel()),
+                     dtype=torch.uint8, device=dev)
+    out = torch.full((D + 64,), 0xA5, dtype=torch.uint8, device=dev)
+    out_off = torch.full((len(rows) + 1,), -7, dtype=code_off.dtype, device=dev)
+    st = fd.decode_take_into(d, codes, code_off, torch.from_numpy(rows.astype(np.int64)).to(dev), codes.numel(),
+                             out_off, out[:D], ws)
+    assert st == fd.OK
+    exp_off = np.concatenate([[0], np.cumsum(lens)])
+    assert np.array_equal(out_off.cpu().numpy().astype(np.int64), exp_off)
+    lens_t = torch.from_numpy(lens).to(dev)
+    idx = torch.repeat_interleave(torch.from_numpy(to[rows]).to(dev) - torch.from_numpy(exp_off[:-1]).to(dev),
+                                  lens_t) + torch.arange(D, device=dev)
+    assert torch.equal(out[:D], text[idx])
+    assert bool((out[D:] == 0xA5).all())
