@@ -157,8 +157,9 @@ def _events_time(fn, steps, warmup):
     return float(per.mean()), per
 
 
-def single_rate(workload: str, steps: int = 10, seed: int | None = None) -> float:
-    """Decoded GB/s of one 1 GiB single-column decode (the c2 / c3 reference rates)."""
+def single_rate(workload: str, steps: int = 10, seed: int | None = None, mode: int = 0) -> float:
+    """Decoded GB/s of one 1 GiB single-column decode (the c2 / c3 reference
+    rates; mode 1: the three-phase path)."""
     import numpy as np
     import torch
     import paper_2609_15034_amd as fd
@@ -168,10 +169,13 @@ def single_rate(workload: str, steps: int = 10, seed: int | None = None) -> floa
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
     out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
-    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings)
+    tu = {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tu)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
-    mean_s, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True),
-                             steps, 2)
+    mean_s, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True,
+                                                    tuning=tu), steps, 2)
+    if int(st.item()) != fd.OK or not torch.equal(out, torch.from_numpy(col.text).to(dev)):
+        raise fd.DecodeError(int(st.item()), f"{workload} mode {mode}: output differs from the source")
     return col.decoded_bytes / mean_s / 1e9
 
 
@@ -630,6 +634,12 @@ def main():
             res["onpair_urls_GBps"] = round(rates["onpair16"], 2)
         except Exception as e:
             res["onpair_urls_GBps"] = {"error": f"{type(e).__name__}: {e}"}
+        res["three_phase_GBps"] = {}
+        for wl in ("fsst_logs", "onpair_urls"):          # streamed tile totals, scan, expand
+            try:
+                res["three_phase_GBps"][wl] = round(single_rate(wl, mode=1), 2)
+            except Exception as e:
+                res["three_phase_GBps"][wl] = {"error": f"{type(e).__name__}: {e}"}
         for wl in ("onpair12_urls", "fsst12_logs"):     # 12-bit packed codes
             try:
                 res[wl + "_GBps"] = round(single_rate(wl), 2)

@@ -58,6 +58,11 @@ DevInfo& dev_info(int* dev_out) {
 }
 }  // namespace
 
+int dev_cus() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return dev_info(nullptr).cus;
+}
+
 int resident_grid(int codec, int index_bits, int mode) {
     std::lock_guard<std::mutex> lk(g_mu);
     DevInfo& d = dev_info(nullptr);
@@ -94,6 +99,7 @@ struct Plan {
     int64_t n_blocks;
     size_t off_tiles;
     size_t off_blocks;
+    size_t off_scan;   // three-phase mode: block sums of the cursor scan
     size_t off_dict;   // OnPair: prepared dictionary for the one-shot entry point
     size_t bytes;
 };
@@ -111,7 +117,8 @@ bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tunin
     pl->off_tiles = kHdr;
     // n_tiles + 1 tile words: the three-phase scan leaves the decoded total in the last
     pl->off_blocks = pl->off_tiles + (size_t)(pl->n_tiles + 1) * 8;
-    pl->off_dict = align_up(pl->off_blocks + (size_t)pl->n_blocks * 8, 256);
+    pl->off_scan = pl->off_blocks + (size_t)pl->n_blocks * 8;
+    pl->off_dict = align_up(pl->off_scan + (size_t)((pl->n_tiles + 1 + 1023) / 1024 + 1) * 8, 256);
     pl->bytes = pl->off_dict + (codec == FD_ONPAIR16 ? align_up(kTok16Bytes + kTokLenBytes, 256) : 0);
     return true;
 }
@@ -286,13 +293,11 @@ fd_status run_decode(const Args& a) {
         if ((int64_t)grid > pl.n_tiles) grid = (int)pl.n_tiles;
         if (launch_decode(codec, a.index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();
     } else {
-        int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
-        if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
-        if (launch_decode(codec, a.index_bits, kModeTotals, p, g1, st) != hipSuccess) return hip_fail();
-        if (launch_scan_totals(p.tagg, pl.n_tiles + 1, nullptr, nullptr, nullptr, st) != hipSuccess)
+        // tile totals streamed, scanned into cursors, then the expand phase
+        // (which validates and checks every tile's total against its cursors)
+        if (launch_tile_totals(codec, a.index_bits, p, dev_cus(), st) != hipSuccess) return hip_fail();
+        if (launch_scan_multi(p.tagg, pl.n_tiles + 1, (unsigned long long*)(ws + pl.off_scan), st) != hipSuccess)
             return hip_fail();
-        // the expand phase takes tiles from the counter again
-        if (launch_reset(nullptr, p.counters, nullptr, 0, st) != hipSuccess) return hip_fail();
         int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
         if ((int64_t)g2 > pl.n_tiles) g2 = (int)pl.n_tiles;
         if (launch_decode(codec, a.index_bits, kModeExpand, p, g2, st) != hipSuccess) return hip_fail();

@@ -91,6 +91,11 @@ hipError_t launch_take_compact(int codec, int index_bits, const int64_t* rows, i
                                const void* code_off, int64_t n_strings, int64_t n_codes, const uint8_t* codes,
                                unsigned long long* bsum, int64_t max_codes, void* new_off, int64_t* src, uint8_t* dst,
                                int rows_per_wg, unsigned long long* err, hipStream_t st);
+// Three-phase mode: every tile's decoded total into p.tagg[0, n_tiles) (no
+// validation), on a grid of resident workgroups over `cus` compute units.
+hipError_t launch_tile_totals(int codec, int index_bits, const DecodeParams& p, int cus, hipStream_t st);
+// Exclusive scan of v[0, n) in place; bsum: ceil(n / 1024) + 1 words of scratch.
+hipError_t launch_scan_multi(unsigned long long* v, int64_t n, unsigned long long* bsum, hipStream_t st);
 int batch_occupancy(int codec, int index_bits);
 hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
                                int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st);
@@ -106,6 +111,7 @@ hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int3
 // host runtime helpers shared by the single-column and batch entry points
 int64_t codes_per_pass(fd_codec c);
 int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings);
+int dev_cus();   // compute units of the current device
 int resident_grid(int codec, int index_bits, int mode);
 int resident_grid_batch(int codec, int index_bits);
 

@@ -318,9 +318,8 @@ __device__ __forceinline__ Geom geom_from_regs(S& s, const DecodeParams& p, int6
 // 16-byte aligned) are read byte by byte, only inside the buffer.  Fully
 // unrolled, so that the compiler can count the loads in flight.
 template <int CODEC>
-__device__ __forceinline__ void codes_load(const DecodeParams& p, const Geom& g, int sp, uint32_t w[][4]) {
+__device__ __forceinline__ void codes_load_at(const DecodeParams& p, const Geom& g, int64_t k0, uint32_t w[][4]) {
     using C = Cfg<CODEC>;
-    const int64_t k0 = (int64_t)sp * kWG * C::P + (int64_t)threadIdx.x * C::P;
     if constexpr (kPacked12<CODEC>) {
         // 12 bytes per chunk; three dword loads when the chunk is whole and
         // dword-aligned, bytes otherwise (only inside the stream)
@@ -376,6 +375,12 @@ __device__ __forceinline__ void codes_load(const DecodeParams& p, const Geom& g,
             }
         }
     }
+}
+
+// The chunks of super-pass sp that lane threadIdx.x owns.
+template <int CODEC>
+__device__ __forceinline__ void codes_load(const DecodeParams& p, const Geom& g, int sp, uint32_t w[][4]) {
+    codes_load_at<CODEC>(p, g, (int64_t)sp * kWG * Cfg<CODEC>::P + (int64_t)threadIdx.x * Cfg<CODEC>::P, w);
 }
 
 // Per-lane state of one super-pass between its length scan and its emit.
@@ -1486,6 +1491,300 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
 }
 
 // --------------------------------------------------------------------------
+// three-phase mode, first phase: every tile's decoded total, streamed (no
+// validation and no assembly; the expand phase validates everything and
+// checks each tile's total against the cursors scanned from these).  One wave
+// per tile, without barriers, so that many tiles' loads are in flight: the
+// wave walks the tile's chunks 64 lanes x P at a time, loading each step's
+// chunks one step ahead (FSST-8; OnPair uses k_tile_totals_wg below).  A tile
+// starts at a string boundary, where an FSST-8 code is never a literal; inside
+// the tile the escape parity runs on across strings exactly as in the expand
+// phase's scan (in valid data no string ends inside a run of escapes of odd
+// length).
+// --------------------------------------------------------------------------
+template <int CODEC, typename IDX>
+__global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
+    using C = Cfg<CODEC>;
+    constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
+    constexpr int64_t CPI = 64 * P;               // chunks per step of a wave
+    __shared__ uint8_t s_len[256];
+    const unsigned tid = threadIdx.x, lane = tid & 63;
+    if constexpr (CODEC == kFsst8) {
+        // per code its length: 0 for the escape and for codes that are not symbols
+        for (unsigned c = tid; c < 256; c += kWG) {
+            uint32_t l;
+            if (p.fsst_len) {
+                l = p.fsst_len[c];
+                l = (l & 0x80u) ? 0u : l;
+            } else {
+                l = ((int)c < p.n_sym) ? (uint32_t)p.dict_lens[c] : 0u;
+            }
+            s_len[c] = (c == 255) ? 0 : (uint8_t)l;
+        }
+        __syncthreads();
+    }
+    const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
+        kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
+    const IDX* co = (const IDX*)p.code_off;
+    const int64_t nw = (int64_t)gridDim.x * kNWave;
+    int64_t t = (int64_t)blockIdx.x * kNWave + (tid >> 6);
+    // lane 0 holds the code offsets of the wave's next tile, loaded a tile ahead
+    IDX n0 = 0, n1 = 0;
+    auto offsets_of = [&](int64_t tt) {
+        if (lane == 0 && tt < p.n_tiles) {
+            const int64_t i0 = tt * (int64_t)p.sb;
+            const int64_t i1 = min(i0 + (int64_t)p.sb, p.n_strings);
+            n0 = co[i0];
+            n1 = co[i1];
+        }
+    };
+    offsets_of(t);
+    for (; t < p.n_tiles; t += nw) {
+        const int64_t c0 = uniform64((int64_t)n0), c1 = uniform64((int64_t)n1);
+        offsets_of(t + nw);
+        const Geom g = make_geom<CODEC>(p, t, c0, c1);
+        const int64_t steps = (g.nchunk + CPI - 1) / CPI;
+        uint32_t carry = 0;
+        uint64_t total = 0;
+        uint32_t wn[P][4];                        // the next step's chunks, loaded a step ahead
+        if (steps > 0) codes_load_at<CODEC>(p, g, (int64_t)lane * P, wn);
+        for (int64_t it = 0; it < steps; it++) {
+            const int64_t k0 = it * CPI + (int64_t)lane * P;
+            uint32_t w[P][4];
+#pragma unroll
+            for (int c = 0; c < P; c++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) w[c][q] = wn[c][q];
+            if (it + 1 < steps) codes_load_at<CODEC>(p, g, k0 + CPI, wn);
+            const int64_t q0 = g.pos0 + k0 * CPC;
+            const int64_t lo = min(max(g.a - q0, (int64_t)0), (int64_t)CPL);
+            const int64_t hi = min(max(g.b - q0, (int64_t)0), (int64_t)CPL);
+            const uint32_t mhi = hi >= 32 ? 0xffffffffu : ((1u << (uint32_t)hi) - 1u);
+            const uint32_t mlo = lo >= 32 ? 0xffffffffu : ((1u << (uint32_t)lo) - 1u);
+            const uint32_t valid = mhi & ~mlo;
+            uint32_t tot = 0;
+            if constexpr (CODEC == kFsst8) {
+                uint32_t F = 0;
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t x = w[c][q];
+                        const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
+                        const uint32_t nib = ((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu;
+                        F |= nib << (c * 16 + q * 4);
+                    }
+                F &= valid;
+                // the parity entering each lane: the trailing run of the nearest
+                // lower lane that is not all escapes, else the previous step's
+                const bool all_ff = (F == 0xffffffffu);
+                const uint32_t trail = __clz(~F);
+                const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
+                const uint64_t m = M & ((1ull << lane) - 1ull);
+                const uint32_t cin = m ? (uint32_t)((T >> (63 - __clzll(m))) & 1ull) : carry;
+                if (M) carry = (uint32_t)((T >> (63 - __clzll(M))) & 1ull);
+                uint32_t esc, lit;
+                classify_escapes(F, cin, esc, lit);
+                lit &= valid;
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int j = 0; j < CPC; j++) {
+                        const int b = c * CPC + j;
+                        const uint32_t code = (w[c][j >> 2] >> (8 * (j & 3))) & 0xffu;
+                        const uint32_t v = ((lit >> b) & 1u) ? 1u : (uint32_t)s_len[code];
+                        tot += ((valid >> b) & 1u) ? v : 0u;
+                    }
+            } else {
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int j = 0; j < CPC; j++) {
+                        const int b = c * CPC + j;
+                        const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                        const uint32_t l = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
+                        tot += ((valid >> b) & 1u) ? l : 0u;
+                    }
+            }
+            total += tot;
+        }
+        total = wave_sum_u64(total);
+        if (lane == 0) p.tagg[t] = total;
+    }
+}
+
+// The same totals with a workgroup per tile (OnPair: a tile's 16 length
+// gathers per lane spread over four waves finish sooner than on one).  Each
+// workgroup takes tiles blockIdx.x, + gridDim.x, ...
+template <int CODEC, typename IDX>
+__global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
+    using C = Cfg<CODEC>;
+    constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
+    __shared__ uint8_t s_len[256];
+    __shared__ uint32_t s_wpar[kNWave];
+    __shared__ uint64_t s_wsum[kNWave];
+    __shared__ int64_t s_nb[2];
+    const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if constexpr (CODEC == kFsst8) {
+        // per code its length: 0 for the escape and for codes that are not symbols
+        for (unsigned c = tid; c < 256; c += kWG) {
+            uint32_t l;
+            if (p.fsst_len) {
+                l = p.fsst_len[c];
+                l = (l & 0x80u) ? 0u : l;
+            } else {
+                l = ((int)c < p.n_sym) ? (uint32_t)p.dict_lens[c] : 0u;
+            }
+            s_len[c] = (c == 255) ? 0 : (uint8_t)l;
+        }
+        __syncthreads();
+    }
+    const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
+        kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
+    const IDX* co = (const IDX*)p.code_off;
+    for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+        if (tid == 0) {
+            const int64_t i0 = t * (int64_t)p.sb;
+            const int64_t i1 = min(i0 + (int64_t)p.sb, p.n_strings);
+            s_nb[0] = (int64_t)co[i0];
+            s_nb[1] = (int64_t)co[i1];
+        }
+        __syncthreads();
+        const Geom g = make_geom<CODEC>(p, t, s_nb[0], s_nb[1]);
+        uint32_t carry = 0;
+        uint64_t total = 0;
+        for (int sp = 0; sp < g.nsp; sp++) {
+            uint32_t w[P][4];
+            codes_load<CODEC>(p, g, sp, w);
+            const int64_t k0 = (int64_t)sp * kWG * P + (int64_t)tid * P;
+            const int64_t q0 = g.pos0 + k0 * CPC;
+            const int64_t lo = min(max(g.a - q0, (int64_t)0), (int64_t)CPL);
+            const int64_t hi = min(max(g.b - q0, (int64_t)0), (int64_t)CPL);
+            const uint32_t mhi = hi >= 32 ? 0xffffffffu : ((1u << (uint32_t)hi) - 1u);
+            const uint32_t mlo = lo >= 32 ? 0xffffffffu : ((1u << (uint32_t)lo) - 1u);
+            const uint32_t valid = mhi & ~mlo;
+            uint32_t tot = 0;
+            if constexpr (CODEC == kFsst8) {
+                uint32_t F = 0;
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t x = w[c][q];
+                        const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
+                        const uint32_t nib = ((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu;
+                        F |= nib << (c * 16 + q * 4);
+                    }
+                F &= valid;
+                const bool all_ff = (F == 0xffffffffu);
+                const uint32_t trail = __clz(~F);
+                const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
+                const uint64_t m = M & ((1ull << lane) - 1ull);
+                if (lane == 0) s_wpar[wv] = M ? (1u | ((uint32_t)((T >> (63 - __clzll(M))) & 1ull) << 1)) : 0u;
+                __syncthreads();
+                uint32_t cw = carry, cout = carry;
+#pragma unroll
+                for (int i = 0; i < kNWave; i++) {
+                    const uint32_t v = s_wpar[i];
+                    if ((v & 1u) && i < (int)wv) cw = v >> 1;
+                    if (v & 1u) cout = v >> 1;
+                }
+                carry = cout;
+                const uint32_t cin = m ? (uint32_t)((T >> (63 - __clzll(m))) & 1ull) : cw;
+                uint32_t esc, lit;
+                classify_escapes(F, cin, esc, lit);
+                lit &= valid;
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int j = 0; j < CPC; j++) {
+                        const int b = c * CPC + j;
+                        const uint32_t code = (w[c][j >> 2] >> (8 * (j & 3))) & 0xffu;
+                        const uint32_t v = ((lit >> b) & 1u) ? 1u : (uint32_t)s_len[code];
+                        tot += ((valid >> b) & 1u) ? v : 0u;
+                    }
+                __syncthreads();                  // s_wpar of the next super-pass
+            } else {
+#pragma unroll
+                for (int c = 0; c < P; c++)
+#pragma unroll
+                    for (int j = 0; j < CPC; j++) {
+                        const int b = c * CPC + j;
+                        const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                        const uint32_t l = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
+                        tot += ((valid >> b) & 1u) ? l : 0u;
+                    }
+            }
+            total += tot;
+        }
+        total = wave_sum_u64(total);
+        if (lane == 0) s_wsum[wv] = total;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t sum = 0;
+#pragma unroll
+            for (int i = 0; i < kNWave; i++) sum += s_wsum[i];
+            p.tagg[t] = sum;
+        }
+        __syncthreads();                          // s_nb and s_wsum of the next tile
+    }
+}
+
+// Exclusive scan of v[0, n) in place across workgroups of 1,024 entries:
+// block sums (k_block_sums), a scan of those (k_scan_totals), then each
+// block's local scan plus its base (k_block_scan).  bsum holds one word per
+// block plus one.
+constexpr int kScanBlock = 1024;
+__global__ void __launch_bounds__(256) k_block_sums(const unsigned long long* v, int64_t n, unsigned long long* bsum) {
+    __shared__ uint64_t s_w[kNWave];
+    const unsigned tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanBlock / 256; k++) {
+        const int64_t i = base + tid + 256 * k;
+        if (i < n) sum += v[i];
+    }
+    sum = wave_sum_u64(sum);
+    if (lane_id() == 0) s_w[tid >> 6] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < 256 / 64; i++) t += s_w[i];
+        bsum[blockIdx.x] = t;
+        if (blockIdx.x == 0) bsum[gridDim.x] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_block_scan(unsigned long long* v, int64_t n, const unsigned long long* bsum) {
+    __shared__ uint64_t s_w[kNWave];
+    constexpr int R = kScanBlock / 256;
+    const unsigned tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * R;   // R consecutive entries per thread
+    uint64_t x[R], tsum = 0;
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        x[k] = (base + k < n) ? v[base + k] : 0;
+        tsum += x[k];
+    }
+    uint64_t incl = tsum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(incl, d, 64);
+        if (lane >= (unsigned)d) incl += y;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    uint64_t run = bsum[blockIdx.x] + incl - tsum;
+    for (unsigned k = 0; k < w; k++) run += s_w[k];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        if (base + k < n) v[base + k] = run;
+        run += x[k];
+    }
+}
+
+// --------------------------------------------------------------------------
 // selective decode: the strings a row list names, compacted into one code
 // stream (strings are independently decodable, so each keeps its codes
 // whole), which the decode kernels then expand as a column of their own
@@ -1742,6 +2041,41 @@ hipError_t launch_reset(unsigned long long* err, unsigned* counters, unsigned lo
 hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned long long* err, int32_t* status,
                               int32_t* status2, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, v, n, err, status, status2);
+    return hipGetLastError();
+}
+
+template <int CODEC, typename IDX>
+static int totals_occupancy_of() {
+    int nb = 0;
+    const void* k = CODEC == kFsst8 ? (const void*)k_tile_totals<CODEC, IDX> : (const void*)k_tile_totals_wg<CODEC, IDX>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kWG, 0) != hipSuccess) nb = 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_tile_totals(int codec, int index_bits, const DecodeParams& p, int cus, hipStream_t st) {
+#define TT(C, I)                                                                                              \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8)) {                                                    \
+        static int occ = 0;                                                                                    \
+        if (!occ) occ = totals_occupancy_of<C, I>();                                                           \
+        const int64_t g = min(p.n_tiles, (int64_t)cus * occ);                                                  \
+        if (C == kFsst8)                                                                                       \
+            hipLaunchKernelGGL((k_tile_totals<C, I>), dim3((unsigned)max(g, (int64_t)1)), dim3(kWG), 0, st, p); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_tile_totals_wg<C, I>), dim3((unsigned)max(g, (int64_t)1)), dim3(kWG), 0, st, p); \
+        return hipGetLastError();                                                                              \
+    }
+    TT(kFsst8, int32_t) TT(kFsst8, int64_t) TT(kOnpair16, int32_t) TT(kOnpair16, int64_t)
+    TT(kOnpair12, int32_t) TT(kOnpair12, int64_t)
+#undef TT
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scan_multi(unsigned long long* v, int64_t n, unsigned long long* bsum, hipStream_t st) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb < 1 || nb > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(256), 0, st, v, n, bsum);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, bsum, nb + 1, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(256), 0, st, v, n, bsum);
     return hipGetLastError();
 }
 
