@@ -195,7 +195,9 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                     per string plus a margin for their spread, fit one pass
  *                     (a pass is 8192 FSST-8 or 4096 OnPair codes; a tile
  *                     with more codes takes several passes, each recomputing
- *                     the lengths).  The estimate uses n_codes / n_strings,
+ *                     the lengths).  The margin is wider for mode 0, where a
+ *                     tile of several passes delays every later tile, than
+ *                     for mode 1 and the sidecar entry points.  The estimate uses n_codes / n_strings,
  *                     so a decode of a few strings out of a much larger code
  *                     buffer should pass the codes of its range (rebased
  *                     offsets) or set strings_per_tile.

@@ -19,17 +19,20 @@ int64_t codes_per_pass(fd_codec c) {
     return (int64_t)kWG * chunks_per_lane(codec) * codes_per_chunk(codec);
 }
 
-// Strings per tile: the largest count whose expected code count plus four
+// Strings per tile: the largest count whose expected code count plus `sigmas`
 // standard deviations (per-string coefficient of variation taken as 0.6) fits
-// in one super-pass, so that almost every tile is decoded in one pass.
-int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings) {
+// in one super-pass.  The look-back takes 4: a tile of two passes publishes its
+// total late and every later tile waits for it.  Paths without a look-back
+// (three phases, stored positions) take 2: such a tile then costs only itself,
+// and fuller tiles pay more (FSST-8 logs: 640 against 596 GB/s).
+int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings, double sigmas) {
     const double cap = (double)codes_per_pass(codec) - 16.0;
     const double m = n_strings ? (double)n_codes / (double)n_strings : 1.0;
     const double mean = m < 1.0 ? 1.0 : m;
     int64_t sb = 1;
     for (int64_t lo = 1, hi = codec == FD_FSST8 ? kSbMaxFsst : kSbMax; lo <= hi;) {
         const int64_t mid = (lo + hi) / 2;
-        const double need = mid * mean + 4.0 * 0.6 * mean * __builtin_sqrt((double)mid);
+        const double need = mid * mean + sigmas * 0.6 * mean * __builtin_sqrt((double)mid);
         if (need <= cap) { sb = mid; lo = mid + 1; } else { hi = mid - 1; }
     }
     return sb;
@@ -104,13 +107,18 @@ struct Plan {
     size_t bytes;
 };
 
-bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl) {
+// The automatic tile margin of a decode: 2 standard deviations without a
+// look-back (three-phase mode, sidecar operations), else 4.
+double tile_sigmas(const fd_tuning* tu, bool sidecar) { return (sidecar || (tu && tu->mode == 1)) ? 2.0 : 4.0; }
+
+bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl,
+              double sigmas = 4.0) {
     if (n_codes < 0 || n_strings < 0) return false;
     if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
     const int64_t sb_max = codec == FD_FSST8 ? kSbMaxFsst : kSbMax;
     int64_t sb = tu ? tu->strings_per_tile : 0;
     if (sb < 0 || sb > sb_max) return false;
-    if (sb == 0) sb = auto_strings_per_tile(codec, n_codes, n_strings);
+    if (sb == 0) sb = auto_strings_per_tile(codec, n_codes, n_strings, sigmas);
     pl->sb = sb;
     pl->n_tiles = n_strings == 0 ? 1 : (n_strings + sb - 1) / sb;
     pl->n_blocks = (pl->n_tiles + kBlk - 1) / kBlk;
@@ -213,7 +221,8 @@ fd_status run_decode(const Args& a) {
         if (a.n_dict > 0 && (!a.dict_lens || !a.dict_bytes)) return FD_EINVAL;
     }
     Plan pl;
-    if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl)) return FD_EINVAL;
+    if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl, tile_sigmas(a.tuning, a.sidecar_op != 0)))
+        return FD_EINVAL;
     if (a.ws_bytes < pl.bytes) return FD_EINVAL;
     if (a.sidecar_op && a.sidecar_n != pl.n_tiles + 1) return FD_EINVAL;   // another tiling's sidecar
 
@@ -336,8 +345,9 @@ const char* fd_version(void) { return "fastdecode 0.1 gfx950"; }
 fd_status fd_workspace_size_ex(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tuning,
                                size_t* bytes) {
     if (!bytes) return FD_EINVAL;
+    // a margin of 4 standard deviations gives the most tiles: enough for every path
     Plan pl;
-    if (!plan_for(codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
+    if (!plan_for(codec, n_codes, n_strings, tuning, &pl, 4.0)) return FD_EINVAL;
     *bytes = pl.bytes;
     return FD_OK;
 }
@@ -403,7 +413,7 @@ fd_status fd_sidecar_layout(fd_codec codec, int64_t n_codes, int64_t n_strings, 
     if (!strings_per_tile || !n_entries) return FD_EINVAL;
     if (tuning && tuning->mode != 0) return FD_EINVAL;
     Plan pl;
-    if (!plan_for(codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
+    if (!plan_for(codec, n_codes, n_strings, tuning, &pl, tile_sigmas(tuning, true))) return FD_EINVAL;
     *strings_per_tile = (int32_t)pl.sb;
     *n_entries = pl.n_tiles + 1;
     return FD_OK;

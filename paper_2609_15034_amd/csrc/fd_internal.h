@@ -110,7 +110,9 @@ hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int3
 
 // host runtime helpers shared by the single-column and batch entry points
 int64_t codes_per_pass(fd_codec c);
-int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings);
+// Automatic strings per tile; sigmas: the margin for the spread of codes per
+// string (4 for the look-back, 2 for paths without one).
+int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings, double sigmas = 4.0);
 int dev_cus();   // compute units of the current device
 int resident_grid(int codec, int index_bits, int mode);
 int resident_grid_batch(int codec, int index_bits);
