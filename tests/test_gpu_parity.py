@@ -97,21 +97,25 @@ def _ff_column(seed, n_strings, max_run=300):
     return codes, off
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("sb", [0, 1, 2, 7])
-def test_ff_runs(sb):
+def test_ff_runs(sb, mode):
     codes, off = _ff_column(7, 2500)
     db, dl = pack([b"x", b"yz", b"0123456"])
-    assert_parity("fsst8", codes, off, db, dl, tuning={"mode": 0, "strings_per_tile": sb, "grid": 0, "reserved": 0})
+    assert_parity("fsst8", codes, off, db, dl, tuning={"mode": mode, "strings_per_tile": sb, "grid": 0, "reserved": 0})
 
 
-def test_ff_run_longer_than_a_pass():
-    """One string whose code stream is a 255 run longer than one pass (4096
-    codes) followed by a literal: parity carried across passes."""
-    for L in (4095, 4096, 4097, 9001, 20000):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ff_run_longer_than_a_pass(mode):
+    """One string whose code stream is a 255 run longer than one pass (8192
+    codes) and than the three-phase totals' per-wave step (2048 codes),
+    followed by a literal: parity carried across passes, lanes and steps."""
+    for L in (2047, 2048, 2049, 4095, 4096, 4097, 9001, 20000):
         codes = np.frombuffer(b"\x00" + b"\xff" * L + (b"\x01" if L % 2 else b"") + b"\x02", np.uint8).copy()
         off = np.array([0, len(codes)], np.int64)
         db, dl = pack([b"a", b"bc", b"def"])
-        assert_parity("fsst8", codes, off, db, dl)
+        assert_parity("fsst8", codes, off, db, dl, tuning={"mode": mode, "strings_per_tile": 0, "grid": 0,
+                                                            "reserved": 0})
 
 
 # --------------------------------------------------------------------------- #
