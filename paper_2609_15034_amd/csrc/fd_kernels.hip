@@ -1564,6 +1564,7 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
             const uint32_t valid = mhi & ~mlo;
             uint32_t tot = 0;
             if constexpr (CODEC == kFsst8) {
+                // bit j: code j is 255 (the top bits of 0xFF bytes gathered by one multiply)
                 uint32_t F = 0;
 #pragma unroll
                 for (int c = 0; c < P; c++)
@@ -1571,8 +1572,7 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                     for (int q = 0; q < 4; q++) {
                         const uint32_t x = w[c][q];
                         const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
-                        const uint32_t nib = ((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu;
-                        F |= nib << (c * 16 + q * 4);
+                        F |= (((m >> 7) * 0x00204081u) >> 21 & 0xfu) << (c * 16 + q * 4);
                     }
                 F &= valid;
                 // the parity entering each lane: the trailing run of the nearest
@@ -1586,14 +1586,19 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                 uint32_t esc, lit;
                 classify_escapes(F, cin, esc, lit);
                 lit &= valid;
+                // literals count 1 each; they and the codes outside the tile are
+                // read as 255, whose length is 0 (as an escape's), so every other
+                // code adds its table length
+                tot = (uint32_t)__builtin_popcount(lit);
+                const uint32_t fix = ~valid | lit;
 #pragma unroll
                 for (int c = 0; c < P; c++)
 #pragma unroll
-                    for (int j = 0; j < CPC; j++) {
-                        const int b = c * CPC + j;
-                        const uint32_t code = (w[c][j >> 2] >> (8 * (j & 3))) & 0xffu;
-                        const uint32_t v = ((lit >> b) & 1u) ? 1u : (uint32_t)s_len[code];
-                        tot += ((valid >> b) & 1u) ? v : 0u;
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t nib = (fix >> (c * 16 + q * 4)) & 0xfu;
+                        const uint32_t x = w[c][q] | (((nib * 0x00204081u) & 0x01010101u) * 0xffu);
+                        tot += (uint32_t)s_len[x & 0xffu] + (uint32_t)s_len[(x >> 8) & 0xffu] +
+                               (uint32_t)s_len[(x >> 16) & 0xffu] + (uint32_t)s_len[x >> 24];
                     }
             } else {
 #pragma unroll
