@@ -179,7 +179,9 @@ __device__ __forceinline__ void classify_escapes(uint32_t F, uint32_t cin, uint3
 }
 
 // expand 4 bits into bit 7 of each byte of a dword
-__device__ __forceinline__ uint32_t bits_to_byte_msb(uint32_t nib) { return (nib * 0x10204081u) & 0x80808080u; }
+// 4 bits -> bytes 0x01 / 0x00 (a 24-bit multiply places bit k at bit 8k)
+__device__ __forceinline__ uint32_t nib_to_bytes(uint32_t nib) { return ((nib & 0xfu) * 0x00204081u) & 0x01010101u; }
+__device__ __forceinline__ uint32_t bits_to_byte_msb(uint32_t nib) { return nib_to_bytes(nib) << 7; }
 
 // --------------------------------------------------------------------------
 // configuration
@@ -467,21 +469,24 @@ __device__ __forceinline__ uint32_t fsst_chunk_lengths(S& s, const uint32_t (&w)
     uint32_t ctot = 0;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        uint32_t pw = 0, lw = 0;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int j = q * 4 + r;
-            const uint32_t bj = (w[q] >> (8 * r)) & 0xffu;
-            uint32_t v = ((lit >> j) & 1u) ? 1u : (uint32_t)s.fsst_len[bj];
-            v = ((valid >> j) & 1u) ? v : 0u;
-            bad |= (v >> 7) << j;
-            v &= 0x7fu;
-            pw |= ctot << (8 * r);
-            lw |= v << (8 * r);
-            ctot += v;
+        const uint32_t vn = (valid >> (q * 4)) & 0xfu;
+        const uint32_t ln = (lit >> (q * 4)) & vn & 0xfu;
+        // literals and codes outside the tile read as 255 (length 0 in the table)
+        const uint32_t fb = nib_to_bytes((~vn & 0xfu) | ln);
+        const uint32_t x = w[q] | ((fb << 8) - fb);
+        uint32_t lw = (uint32_t)s.fsst_len[x & 0xffu] | ((uint32_t)s.fsst_len[(x >> 8) & 0xffu] << 8) |
+                      ((uint32_t)s.fsst_len[(x >> 16) & 0xffu] << 16) | ((uint32_t)s.fsst_len[x >> 24] << 24);
+        const uint32_t m = lw & 0x80808080u;      // codes that are not symbols
+        if (m) {
+            bad |= (((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu) << (q * 4);
+            lw &= 0x7f7f7f7fu;
         }
-        pre[q] = pw | bits_to_byte_msb((esc >> (q * 4)) & 0xfu);
+        lw += nib_to_bytes(ln);                   // a literal is one byte
+        // per-code prefix inside the chunk, as bytes (every partial sum stays below 128)
+        const uint32_t incl = (lw << 8) + (lw << 16) + (lw << 24);
+        pre[q] = (__builtin_amdgcn_perm(0u, ctot, 0x00000000u) + incl) | bits_to_byte_msb((esc >> (q * 4)) & 0xfu);
         lenp[q] = lw;
+        ctot = __builtin_amdgcn_sad_u8(lw, 0u, ctot);
     }
     return ctot;
 }
