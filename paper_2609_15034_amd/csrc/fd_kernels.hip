@@ -497,18 +497,15 @@ __device__ __forceinline__ uint32_t onpair_chunk_lengths(const uint32_t (&lv)[8]
     uint32_t ctot = 0;
 #pragma unroll
     for (int q = 0; q < 2; q++) {
-        uint32_t pw = 0, lw = 0;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int j = q * 4 + r;
-            const uint32_t v = ((valid >> j) & 1u) ? lv[j] : 0u;
-            bad |= (((valid >> j) & 1u) && v == 0u ? 1u : 0u) << j;
-            pw |= ctot << (8 * r);
-            lw |= v << (8 * r);
-            ctot += v;
-        }
-        pre[q] = pw;
+        const uint32_t vb = nib_to_bytes(valid >> (q * 4)) * 0xffu;   // 0xFF per code inside the tile
+        const uint32_t lw = (lv[q * 4] | (lv[q * 4 + 1] << 8) | (lv[q * 4 + 2] << 16) | (lv[q * 4 + 3] << 24)) & vb;
+        // a code inside the tile with length 0 is not a token
+        const uint32_t z = ~(((lw & 0x7f7f7f7fu) + 0x7f7f7f7fu) | lw) & vb & 0x80808080u;
+        if (z) bad |= (((z >> 7) | (z >> 14) | (z >> 21) | (z >> 28)) & 0xfu) << (q * 4);
+        // per-code prefix inside the chunk, as bytes (every partial sum stays below 256)
+        pre[q] = __builtin_amdgcn_perm(0u, ctot, 0x00000000u) + (lw << 8) + (lw << 16) + (lw << 24);
         lenp[q] = lw;
+        ctot = __builtin_amdgcn_sad_u8(lw, 0u, ctot);
     }
     return ctot;
 }
@@ -1718,11 +1715,16 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
 #pragma unroll
                 for (int c = 0; c < P; c++)
 #pragma unroll
-                    for (int j = 0; j < CPC; j++) {
-                        const int b = c * CPC + j;
-                        const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                        const uint32_t l = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
-                        tot += ((valid >> b) & 1u) ? l : 0u;
+                    for (int q = 0; q < CPC / 4; q++) {
+                        uint32_t lw = 0;          // four lengths as bytes, codes outside the tile masked
+#pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const int j = q * 4 + r;
+                            const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                            lw |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0) << (8 * r);
+                        }
+                        lw &= nib_to_bytes(valid >> (c * CPC + q * 4)) * 0xffu;
+                        tot = __builtin_amdgcn_sad_u8(lw, 0u, tot);
                     }
             }
             total += tot;
