@@ -1648,6 +1648,13 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
     }
     const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
         kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
+    // 12-bit codes: the 4,096 lengths they can name, in LDS
+    __shared__ uint8_t s_len12[kPacked12<CODEC> ? 4096 : 4];
+    if constexpr (kPacked12<CODEC>) {
+        for (unsigned i = tid; i < 4096 / 16; i += kWG)
+            ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
+        __syncthreads();
+    }
     const IDX* co = (const IDX*)p.code_off;
     for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
         if (tid == 0) {
@@ -1721,7 +1728,10 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
                         for (int r = 0; r < 4; r++) {
                             const int j = q * 4 + r;
                             const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                            lw |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0) << (8 * r);
+                            if constexpr (kPacked12<CODEC>)
+                                lw |= (uint32_t)s_len12[cj & 0xfffu] << (8 * r);
+                            else
+                                lw |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0) << (8 * r);
                         }
                         lw &= nib_to_bytes(valid >> (c * CPC + q * 4)) * 0xffu;
                         tot = __builtin_amdgcn_sad_u8(lw, 0u, tot);
