@@ -234,6 +234,7 @@ template <int CODEC> struct SmemT {
     int64_t coff[SB + 1];                 // the current tile's code offsets
     uint64_t fsst_tab[CODEC == kFsst8 ? 256 : 1];
     uint8_t fsst_len[CODEC == kFsst8 ? 256 : 4];
+    alignas(16) uint8_t len12[kPacked12<CODEC> ? 4096 : 16];   // 12-bit codes: the lengths of their 4,096 tokens
     uint32_t wsum[kNWave];
     uint32_t wlast[kNWave];               // total of each wave's last lane
     uint32_t wpar[kNWave];
@@ -457,6 +458,15 @@ __device__ void fsst_build_table(S& s, const DecodeParams& p) {
     __syncthreads();
 }
 
+// 12-bit codes name at most 4,096 tokens: their lengths are copied into LDS
+// (from the prepared dictionary's length table) once per workgroup and
+// dictionary.
+template <typename S>
+__device__ void len12_load(S& s, const DecodeParams& p) {
+    for (unsigned i = threadIdx.x; i < 4096 / 16; i += kWG) ((uint4*)s.len12)[i] = ((const uint4*)p.tok_len)[i];
+    __syncthreads();
+}
+
 // --------------------------------------------------------------------------
 // per-chunk length scans
 // --------------------------------------------------------------------------
@@ -584,7 +594,10 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 const uint32_t cj = (L.w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                lv[c][j] = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
+                if constexpr (kPacked12<CODEC>)
+                    lv[c][j] = s.len12[cj & 0xfffu];
+                else
+                    lv[c][j] = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
             }
         // (the token entries are gathered by the assembly of the lane's window;
         // these two parameters are unused but kept: without them the register
@@ -1118,6 +1131,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     }
 
     if constexpr (CODEC == kFsst8 && !SRC::kBatch) fsst_build_table(s, src.params(0));
+    if constexpr (kPacked12<CODEC> && !SRC::kBatch) len12_load(s, src.params(0));
     while (v < n_all) {
         const DecodeParams& p = src.params(col);
         if constexpr (CODEC == kFsst8 && SRC::kBatch) {
@@ -1127,6 +1141,12 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 fsst_build_table(s, p);
                 table_col = col;
                 table_src = p.fsst_tab;
+            }
+        }
+        if constexpr (kPacked12<CODEC> && SRC::kBatch) {
+            if ((const void*)p.tok_len != table_src) {    // a column of another dictionary
+                len12_load(s, p);
+                table_src = p.tok_len;
             }
         }
         // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
