@@ -704,10 +704,8 @@ __device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], ui
             n0 = s.fsst_tab[(w[(j + 2) >> 2] >> (8 * ((j + 2) & 3))) & 0xffu];
             n1 = s.fsst_tab[(w[(j + 3) >> 2] >> (8 * ((j + 3) & 3))) & 0xffu];
         }
-        if ((lit >> j) & 1u) v0 = b0;
-        if ((lit >> (j + 1)) & 1u) v1 = b1;
-        if (l0 == 0) v0 = 0;                  // codes outside the range carry no bytes
-        if (l1 == 0) v1 = 0;
+        if ((lit >> j) & 1u) v0 = b0;             // (an escape, a code that is not a symbol and a
+        if ((lit >> (j + 1)) & 1u) v1 = b1;       // code outside the tile read zero entries)
         // the pair: v0 | v1 << 8 * l0 over 128 bits, l0 in 0..8
         U128 pr;
         if (l0 >= 8) {
@@ -783,7 +781,16 @@ __device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, U
 #pragma unroll
     for (int i = 0; i < C::CPC / 4; i++) { lenp[i] = L.lenp[c][i]; asm volatile("" : "+v"(lenp[i])); }
 #pragma unroll
-    for (int i = 0; i < 4; i++) { w[i] = L.w[c][i]; asm volatile("" : "+v"(w[i])); }
+    for (int i = 0; i < 4; i++) {
+        w[i] = L.w[c][i];
+        if constexpr (CODEC == kFsst8) {
+            // codes outside the tile read as 255, whose table entry is zero (as
+            // for an escape and a code that is not a symbol): nothing to mask later
+            const uint32_t fb = nib_to_bytes(~(L.valid >> (C::CPC * c + 4 * i)));
+            w[i] |= (fb << 8) - fb;
+        }
+        asm volatile("" : "+v"(w[i]));
+    }
     if constexpr (CODEC == kFsst8) fsst_chunk_emit(s, w, lit, lenp, q, lane0, head);
     else onpair_chunk_emit(s, &L.tok[c * 8], lenp, q, lane0, head);
 }
