@@ -487,7 +487,7 @@ __device__ __forceinline__ uint32_t fsst_chunk_lengths(S& s, const uint32_t (&w)
         uint32_t lw = (uint32_t)s.fsst_len[x & 0xffu] | ((uint32_t)s.fsst_len[(x >> 8) & 0xffu] << 8) |
                       ((uint32_t)s.fsst_len[(x >> 16) & 0xffu] << 16) | ((uint32_t)s.fsst_len[x >> 24] << 24);
         const uint32_t m = lw & 0x80808080u;      // codes that are not symbols
-        if (m) {
+        if (__ballot(m != 0u)) {                  // rare: a scalar branch skips it in most waves
             bad |= (((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu) << (q * 4);
             lw &= 0x7f7f7f7fu;
         }
@@ -511,7 +511,7 @@ __device__ __forceinline__ uint32_t onpair_chunk_lengths(const uint32_t (&lv)[8]
         const uint32_t lw = (lv[q * 4] | (lv[q * 4 + 1] << 8) | (lv[q * 4 + 2] << 16) | (lv[q * 4 + 3] << 24)) & vb;
         // a code inside the tile with length 0 is not a token
         const uint32_t z = ~(((lw & 0x7f7f7f7fu) + 0x7f7f7f7fu) | lw) & vb & 0x80808080u;
-        if (z) bad |= (((z >> 7) | (z >> 14) | (z >> 21) | (z >> 28)) & 0xfu) << (q * 4);
+        if (__ballot(z != 0u)) bad |= (((z >> 7) | (z >> 14) | (z >> 21) | (z >> 28)) & 0xfu) << (q * 4);
         // per-code prefix inside the chunk, as bytes (every partial sum stays below 256)
         pre[q] = __builtin_amdgcn_perm(0u, ctot, 0x00000000u) + (lw << 8) + (lw << 16) + (lw << 24);
         lenp[q] = lw;
