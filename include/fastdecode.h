@@ -337,16 +337,18 @@ fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const f
  * submission: columns of one codec and offset width form a group, each group
  * runs as one persistent kernel in which every workgroup takes tiles of the
  * group's columns, in column order, from one counter (each column keeps its
- * own tile cursors and error word), and a last kernel collects the statuses.
+ * own error word), and a last kernel collects the statuses.  The tile cursors
+ * come from a look-back per column (mode 0) or from three phases per group
+ * (mode 1: the group's tile totals, one scan over them, then the expand pass).
  * The byte semantics per column are those of fd_decode; out_bytes and
  * out_offsets of different columns must not overlap.
  *   cols, n_cols      host array of column descriptions (0 <= n_cols <= 65536);
  *                     the description is read during the call only.
- *   tuning            NULL: tiles are sized by a built-in autotuner that
- *                     times candidate tile sizes on this batch the first time
- *                     a batch of its shape is seen and caches the winner;
- *                     else mode must be 0 and strings_per_tile / grid apply
- *                     to every column / group (0 = automatic).
+ *   tuning            NULL: a built-in autotuner times both modes at three
+ *                     tile sizes on this batch the first time a batch of its
+ *                     shape is seen and caches the winner; else mode (0 or 1)
+ *                     applies to the batch and strings_per_tile / grid to
+ *                     every column / group (0 = automatic).
  *   status            device int32[n_cols + 1] or NULL (required with
  *                     FD_ASYNC): status[c] = the status of column c,
  *                     status[n_cols] = the first non-OK status in column order.

@@ -5,9 +5,12 @@
 // as one persistent kernel over a device table of per-column parameters; its
 // tiles are numbered consecutively over its columns and taken from one
 // counter, so every workgroup works through the group's columns in order and
-// small columns cost no launch of their own.  Each column keeps its own tile
-// cursors (look-back state) and error word; a last one-workgroup kernel turns
-// the error words into per-column statuses.
+// small columns cost no launch of their own.  The tile cursors come either from
+// a decoupled look-back per column (mode 0) or from three phases per group
+// (mode 1): the group's tile totals in global tile order, one scan over them,
+// then the expand pass, each column's cursors taken relative to its first
+// tile.  Each column keeps its own error word; a last one-workgroup kernel
+// turns the error words into per-column statuses.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -44,9 +47,12 @@ struct Group {
     std::vector<int32_t> cols;   // column indices (caller order)
     int64_t total = 0;           // tiles
     int grid = 0;
+    size_t off_sum = 0;          // mode 1: tile totals, then cursors (total + 1 words)
+    size_t off_gsum = 0;         // mode 1: block sums of their scan
 };
 
 struct BatchPlan {
+    int mode = 0;                         // 0: look-back per column, 1: three phases per group
     std::vector<int64_t> sb, n_tiles;     // per column
     std::vector<size_t> off_state;        // per column: tile aggregates, then block states
     std::vector<Group> groups;
@@ -79,7 +85,9 @@ bool column_ok(const fd_column& c) {
 
 // Plan of a batch for one tile-size choice: `sb_fixed` > 0 sets every column's
 // strings per tile, else `scale` percent of the automatic value.
-bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, int grid_req, BatchPlan* pl) {
+bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, int grid_req, int mode,
+               BatchPlan* pl) {
+    pl->mode = mode;
     pl->sb.assign(n, 0);
     pl->n_tiles.assign(n, 0);
     pl->off_state.assign(n, 0);
@@ -92,7 +100,8 @@ bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, in
         int64_t sb = sb_fixed;
         if (sb > sb_max) return false;
         if (sb == 0) {
-            sb = auto_strings_per_tile(codec, col.n_codes, col.n_strings) * scale / 100;
+            // the look-back needs a wider margin against tiles of several passes
+            sb = auto_strings_per_tile(codec, col.n_codes, col.n_strings, mode == 1 ? 2.0 : 4.0) * scale / 100;
             sb = std::max<int64_t>(1, std::min(sb, sb_max));
         }
         const int64_t tiles = col.n_strings == 0 ? 1 : (col.n_strings + sb - 1) / sb;
@@ -100,7 +109,7 @@ bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, in
         pl->sb[c] = sb;
         pl->n_tiles[c] = tiles;
         pl->off_state[c] = off;
-        off += (size_t)tiles_pad * 8 + (size_t)(tiles_pad / kBlk) * 8;
+        if (mode == 0) off += (size_t)tiles_pad * 8 + (size_t)(tiles_pad / kBlk) * 8;
         Group& g = pl->groups[group_of((int)codec, col.index_bits)];
         g.codec = (int)codec;
         g.index_bits = col.index_bits;
@@ -113,6 +122,15 @@ bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, in
     for (Group& g : pl->groups)
         std::stable_sort(g.cols.begin(), g.cols.end(),
                          [&](int32_t a, int32_t b) { return (uintptr_t)cols[a].dict < (uintptr_t)cols[b].dict; });
+    if (mode == 1) {
+        for (Group& g : pl->groups) {
+            if (g.cols.empty()) continue;
+            g.off_sum = off;
+            off += (size_t)(g.total + 1) * 8;
+            g.off_gsum = off;
+            off += (size_t)((g.total + 1 + 1023) / 1024 + 1) * 8;
+        }
+    }
     pl->states_end = off;
     pl->off_errs = align_up(off, 256);
     pl->off_table = align_up(pl->off_errs + (size_t)n * 8, 256);
@@ -123,7 +141,7 @@ bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, in
     pl->bytes = align_up(pl->off_table + tb, 256);
     for (Group& g : pl->groups) {
         if (g.cols.empty()) continue;
-        int grid = grid_req ? grid_req : resident_grid_batch(g.codec, g.index_bits);
+        int grid = grid_req ? grid_req : resident_grid_batch(g.codec, g.index_bits, mode == 1 ? kModeExpand : kModeLookback);
         if ((int64_t)grid > g.total) grid = (int)g.total;
         g.grid = grid < 1 ? 1 : grid;
     }
@@ -161,9 +179,15 @@ void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* 
             p.sb = (int32_t)pl.sb[c];
             p.err = (unsigned long long*)(ws + pl.off_errs) + c;
             p.counters = nullptr;
-            p.tagg = (unsigned long long*)(ws + pl.off_state[c]);
-            const int64_t tiles_pad = (pl.n_tiles[c] + kBlk - 1) / kBlk * kBlk;
-            p.bstate = p.tagg + tiles_pad;
+            if (pl.mode == 1) {
+                // the group's scanned totals from this column's first tile on
+                p.tagg = (unsigned long long*)(ws + g.off_sum) + first;
+                p.bstate = nullptr;
+            } else {
+                p.tagg = (unsigned long long*)(ws + pl.off_state[c]);
+                const int64_t tiles_pad = (pl.n_tiles[c] + kBlk - 1) / kBlk * kBlk;
+                p.bstate = p.tagg + tiles_pad;
+            }
             dp[k++] = p;
             *ft++ = first;
             first += pl.n_tiles[c];
@@ -189,7 +213,17 @@ hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
         const Group& g = pl.groups[gi];
         if (g.cols.empty()) continue;
         unsigned* ctr = (unsigned*)(ws + 8 * gi);
-        e = launch_decode_batch(g.codec, g.index_bits, dp + k, ft, (int32_t)g.cols.size(), g.total, ctr, g.grid, st);
+        const int32_t nc = (int32_t)g.cols.size();
+        if (pl.mode == 1) {
+            unsigned long long* sum = (unsigned long long*)(ws + g.off_sum);
+            e = launch_tile_totals_batch(g.codec, g.index_bits, dp + k, ft, nc, g.total, sum, dev_cus(), st);
+            if (e != hipSuccess) return e;
+            e = launch_scan_multi(sum, g.total + 1, (unsigned long long*)(ws + g.off_gsum), st);
+            if (e != hipSuccess) return e;
+            e = launch_decode_batch(g.codec, g.index_bits, kModeExpand, dp + k, ft, nc, g.total, ctr, g.grid, st);
+        } else {
+            e = launch_decode_batch(g.codec, g.index_bits, kModeLookback, dp + k, ft, nc, g.total, ctr, g.grid, st);
+        }
         if (e != hipSuccess) return e;
         k += (int)g.cols.size();
         ft += g.cols.size() + 1;
@@ -280,17 +314,19 @@ fd_status run_once(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
     return FD_OK;
 }
 
-// Autotune: time every candidate scale on this batch, keep the fastest.
+// Autotune: time every candidate (mode, scale) on this batch, keep the fastest.
 fd_status autotune(const fd_column* cols, int32_t n, uint8_t* ws, size_t ws_bytes, hipStream_t st, int dev,
-                   int* best_scale) {
+                   int* best_mode, int* best_scale) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return FD_EHIP;
     float best = 1e30f;
+    *best_mode = 0;
     *best_scale = kScales[0];
     fd_status rc = FD_OK;
-    for (int i = 0; i < kNumScales && rc == FD_OK; i++) {
+    for (int i = 0; i < 2 * kNumScales && rc == FD_OK; i++) {
+        const int mode = i / kNumScales, scale = kScales[i % kNumScales];
         BatchPlan pl;
-        if (!make_plan(cols, n, 0, kScales[i], 0, &pl) || pl.bytes > ws_bytes) continue;
+        if (!make_plan(cols, n, 0, scale, 0, mode, &pl) || pl.bytes > ws_bytes) continue;
         float ms_sum = 0.f;
         for (int rep = 0; rep < 3 && rc == FD_OK; rep++) {      // one warm-up, two timed
             if (hipEventRecord(a, st) != hipSuccess) { rc = FD_EHIP; break; }
@@ -303,7 +339,8 @@ fd_status autotune(const fd_column* cols, int32_t n, uint8_t* ws, size_t ws_byte
         }
         if (rc == FD_OK && ms_sum < best) {
             best = ms_sum;
-            *best_scale = kScales[i];
+            *best_mode = mode;
+            *best_scale = scale;
         }
     }
     (void)hipEventDestroy(a);
@@ -326,11 +363,14 @@ fd_status fd_batch_workspace_size(const fd_column* cols, int32_t n_cols, const f
     if (!bytes || n_cols < 0 || n_cols > kMaxCols || (n_cols > 0 && !cols)) return FD_EINVAL;
     for (int32_t c = 0; c < n_cols; c++)
         if (!column_ok(cols[c])) return FD_EINVAL;
-    if (tuning && (tuning->mode != 0 || tuning->strings_per_tile < 0 || tuning->grid < 0)) return FD_EINVAL;
+    if (tuning && ((tuning->mode != 0 && tuning->mode != 1) || tuning->strings_per_tile < 0 || tuning->grid < 0))
+        return FD_EINVAL;
     size_t need = kBHdr;
-    for (int i = 0; i < (tuning ? 1 : kNumScales); i++) {
+    for (int i = 0; i < (tuning ? 1 : 2 * kNumScales); i++) {
         BatchPlan pl;
-        if (!make_plan(cols, n_cols, tuning ? tuning->strings_per_tile : 0, tuning ? 100 : kScales[i], 1, &pl))
+        const int mode = tuning ? tuning->mode : i / kNumScales;
+        if (!make_plan(cols, n_cols, tuning ? tuning->strings_per_tile : 0, tuning ? 100 : kScales[i % kNumScales], 1,
+                       mode, &pl))
             return FD_EINVAL;
         need = std::max(need, pl.bytes);
     }
@@ -345,7 +385,8 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
         if (!workspace || ((uintptr_t)workspace & 255)) return FD_EINVAL;
         if ((flags & FD_ASYNC) && !status) return FD_EINVAL;
         if (flags & ~(FD_ASYNC | FD_GRAPH)) return FD_EINVAL;
-        if (tuning && (tuning->mode != 0 || tuning->strings_per_tile < 0 || tuning->grid < 0)) return FD_EINVAL;
+        if (tuning && ((tuning->mode != 0 && tuning->mode != 1) || tuning->strings_per_tile < 0 || tuning->grid < 0))
+            return FD_EINVAL;
         for (int32_t c = 0; c < n_cols; c++)
             if (!column_ok(cols[c])) return FD_EINVAL;
         int dev = 0;
@@ -362,24 +403,26 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
         // the tile-size choice
         int64_t sb_fixed = tuning ? tuning->strings_per_tile : 0;
         int grid = tuning ? tuning->grid : 0;
-        int scale = 100;
+        int scale = 100, mode = tuning ? tuning->mode : 0;
         if (!tuning) {
             const uint64_t sk = shape_key(cols, n_cols, dev);
             auto it = g_tuned.find(sk);
             if (it != g_tuned.end()) {
-                scale = it->second;
+                mode = it->second / 1000;
+                scale = it->second % 1000;
             } else {
-                const fd_status rc = autotune(cols, n_cols, ws, workspace_bytes, st, dev, &scale);
+                const fd_status rc = autotune(cols, n_cols, ws, workspace_bytes, st, dev, &mode, &scale);
                 if (rc != FD_OK) return rc;
-                g_tuned[sk] = scale;
+                g_tuned[sk] = mode * 1000 + scale;
             }
         }
         BatchPlan pl;
-        if (!make_plan(cols, n_cols, sb_fixed, scale, grid, &pl)) return FD_EINVAL;
+        if (!make_plan(cols, n_cols, sb_fixed, scale, grid, mode, &pl)) return FD_EINVAL;
         if (workspace_bytes < pl.bytes) return FD_EINVAL;
 
         if (flags & FD_GRAPH) {
-            const uint64_t key = exact_key(cols, n_cols, workspace, workspace_bytes, status, sb_fixed, scale, grid, dev);
+            const uint64_t key =
+                exact_key(cols, n_cols, workspace, workspace_bytes, status, sb_fixed, mode * 1000 + scale, grid, dev);
             GraphEntry* ge = nullptr;
             for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
                 if (it->first == key) {

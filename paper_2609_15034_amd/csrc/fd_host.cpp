@@ -41,8 +41,8 @@ int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings
 namespace {
 struct DevInfo {
     int cus = 0;
-    int occ[3][2][3] = {};  // [codec][index64][mode]
-    int bocc[3][2] = {};    // batch kernels: [codec][index64]
+    int occ[4][2][3] = {};  // [codec id 1..3][index64][mode]
+    int bocc[4][2][2] = {}; // batch kernels: [codec id 1..3][index64][expand]
 };
 std::mutex g_mu;
 DevInfo g_dev[64];
@@ -74,11 +74,11 @@ int resident_grid(int codec, int index_bits, int mode) {
     return d.cus * o;
 }
 
-int resident_grid_batch(int codec, int index_bits) {
+int resident_grid_batch(int codec, int index_bits, int mode) {
     std::lock_guard<std::mutex> lk(g_mu);
     DevInfo& d = dev_info(nullptr);
-    int& o = d.bocc[codec][index_bits == 64];
-    if (!o) o = batch_occupancy(codec, index_bits);
+    int& o = d.bocc[codec][index_bits == 64][mode == kModeExpand];
+    if (!o) o = batch_occupancy(codec, index_bits, mode);
     return d.cus * o;
 }
 

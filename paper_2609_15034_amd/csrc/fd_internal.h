@@ -96,9 +96,14 @@ hipError_t launch_take_compact(int codec, int index_bits, const int64_t* rows, i
 hipError_t launch_tile_totals(int codec, int index_bits, const DecodeParams& p, int cus, hipStream_t st);
 // Exclusive scan of v[0, n) in place; bsum: ceil(n / 1024) + 1 words of scratch.
 hipError_t launch_scan_multi(unsigned long long* v, int64_t n, unsigned long long* bsum, hipStream_t st);
-int batch_occupancy(int codec, int index_bits);
-hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
+int batch_occupancy(int codec, int index_bits, int mode);
+// mode: kModeLookback, or kModeExpand with each column's p.tagg pointing at the
+// group's scanned totals at the column's first tile
+hipError_t launch_decode_batch(int codec, int index_bits, int mode, const DecodeParams* cols, const int64_t* first_tile,
                                int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st);
+// A batch group's tile totals in global tile order into out[0, total).
+hipError_t launch_tile_totals_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
+                                    int32_t n_cols, int64_t total, unsigned long long* out, int cus, hipStream_t st);
 hipError_t launch_batch_reset(unsigned long long* z, int64_t n, unsigned long long* errs, int32_t n_cols,
                               hipStream_t st);
 hipError_t launch_batch_status(const unsigned long long* errs, int32_t n_cols, int32_t* status, int32_t* status2,
@@ -115,7 +120,7 @@ int64_t codes_per_pass(fd_codec c);
 int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings, double sigmas = 4.0);
 int dev_cus();   // compute units of the current device
 int resident_grid(int codec, int index_bits, int mode);
-int resident_grid_batch(int codec, int index_bits);
+int resident_grid_batch(int codec, int index_bits, int mode);
 
 }  // namespace fd
 

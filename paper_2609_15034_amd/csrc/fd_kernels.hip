@@ -1176,6 +1176,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             if (tid == 0) {
                 cur_reg = (int64_t)p.tagg[t];
                 nxt_reg = (int64_t)p.tagg[t + 1];
+                if constexpr (SRC::kBatch) {
+                    // a batch group's cursors are scanned over all its columns:
+                    // relative to the column's first tile
+                    const int64_t base = (int64_t)p.tagg[0];
+                    cur_reg -= base;
+                    nxt_reg -= base;
+                }
             }
         }
         __syncthreads();
@@ -1382,12 +1389,12 @@ __global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode(DecodeParams p
     }
 }
 
-template <int CODEC, typename IDX>
+template <int CODEC, typename IDX, int MODE>
 __global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode_batch(const DecodeParams* __restrict__ cols,
                                                       const int64_t* __restrict__ first_tile, int32_t n_cols,
                                                       int64_t total, unsigned* ctr) {
     __shared__ SmemT<CODEC> s;
-    decode_tiles<CODEC, IDX, kModeLookback>(s, ColumnBatch{cols, first_tile, n_cols, total, ctr});
+    decode_tiles<CODEC, IDX, MODE>(s, ColumnBatch{cols, first_tile, n_cols, total, ctr});
 }
 
 // Statuses of a batch: column c's error word -> status[c]; the first error in
@@ -1648,49 +1655,58 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
 }
 
 // The same totals with a workgroup per tile (OnPair: a tile's 16 length
-// gathers per lane spread over four waves finish sooner than on one).  Each
-// workgroup takes tiles blockIdx.x, + gridDim.x, ...
-template <int CODEC, typename IDX>
-__global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
+// gathers per lane spread over four waves finish sooner than on one; batches:
+// all waves of a workgroup work on one column, so its LDS table serves them).
+// The source's tile v goes to out[v]; each workgroup takes tiles blockIdx.x,
+// + gridDim.x, ..., and reloads its table when the dictionary changes.
+template <int CODEC, typename IDX, typename SRC>
+__device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
     using C = Cfg<CODEC>;
     constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
     __shared__ uint8_t s_len[256];
+    __shared__ alignas(16) uint8_t s_len12[kPacked12<CODEC> ? 4096 : 16];
     __shared__ uint32_t s_wpar[kNWave];
     __shared__ uint64_t s_wsum[kNWave];
     __shared__ int64_t s_nb[2];
     const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if constexpr (CODEC == kFsst8) {
-        // per code its length: 0 for the escape and for codes that are not symbols
-        for (unsigned c = tid; c < 256; c += kWG) {
-            uint32_t l;
-            if (p.fsst_len) {
-                l = p.fsst_len[c];
-                l = (l & 0x80u) ? 0u : l;
-            } else {
-                l = ((int)c < p.n_sym) ? (uint32_t)p.dict_lens[c] : 0u;
+    const void* table = nullptr;                  // the dictionary whose lengths are in LDS
+    int col = 0;
+    for (int64_t v = blockIdx.x; v < src.n_tiles(); v += gridDim.x) {
+        col = src.column(v, col);
+        const DecodeParams& p = src.params(col);
+        const int64_t t = v - src.first(col);
+        if constexpr (CODEC == kFsst8) {
+            const void* d = p.fsst_len ? (const void*)p.fsst_len : (const void*)p.dict_lens;
+            if (d != table) {
+                // per code its length: 0 for the escape and for codes that are not symbols
+                for (unsigned c = tid; c < 256; c += kWG) {
+                    uint32_t l;
+                    if (p.fsst_len) {
+                        l = p.fsst_len[c];
+                        l = (l & 0x80u) ? 0u : l;
+                    } else {
+                        l = ((int)c < p.n_sym) ? (uint32_t)p.dict_lens[c] : 0u;
+                    }
+                    s_len[c] = (c == 255) ? 0 : (uint8_t)l;
+                }
+                table = d;
             }
-            s_len[c] = (c == 255) ? 0 : (uint8_t)l;
+        } else if constexpr (kPacked12<CODEC>) {
+            if ((const void*)p.tok_len != table) {   // 12-bit codes: their 4,096 lengths
+                for (unsigned i = tid; i < 4096 / 16; i += kWG) ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
+                table = p.tok_len;
+            }
         }
-        __syncthreads();
-    }
-    const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
-        kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
-    // 12-bit codes: the 4,096 lengths they can name, in LDS
-    __shared__ uint8_t s_len12[kPacked12<CODEC> ? 4096 : 4];
-    if constexpr (kPacked12<CODEC>) {
-        for (unsigned i = tid; i < 4096 / 16; i += kWG)
-            ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
-        __syncthreads();
-    }
-    const IDX* co = (const IDX*)p.code_off;
-    for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+        const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
+            kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
         if (tid == 0) {
+            const IDX* co = (const IDX*)p.code_off;
             const int64_t i0 = t * (int64_t)p.sb;
             const int64_t i1 = min(i0 + (int64_t)p.sb, p.n_strings);
             s_nb[0] = (int64_t)co[i0];
             s_nb[1] = (int64_t)co[i1];
         }
-        __syncthreads();
+        __syncthreads();                          // s_nb, and the table when it was reloaded
         const Geom g = make_geom<CODEC>(p, t, s_nb[0], s_nb[1]);
         uint32_t carry = 0;
         uint64_t total = 0;
@@ -1713,8 +1729,7 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
                     for (int q = 0; q < 4; q++) {
                         const uint32_t x = w[c][q];
                         const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
-                        const uint32_t nib = ((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu;
-                        F |= nib << (c * 16 + q * 4);
+                        F |= (((m >> 7) * 0x00204081u) >> 21 & 0xfu) << (c * 16 + q * 4);
                     }
                 F &= valid;
                 const bool all_ff = (F == 0xffffffffu);
@@ -1726,23 +1741,27 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
                 uint32_t cw = carry, cout = carry;
 #pragma unroll
                 for (int i = 0; i < kNWave; i++) {
-                    const uint32_t v = s_wpar[i];
-                    if ((v & 1u) && i < (int)wv) cw = v >> 1;
-                    if (v & 1u) cout = v >> 1;
+                    const uint32_t vw = s_wpar[i];
+                    if ((vw & 1u) && i < (int)wv) cw = vw >> 1;
+                    if (vw & 1u) cout = vw >> 1;
                 }
                 carry = cout;
                 const uint32_t cin = m ? (uint32_t)((T >> (63 - __clzll(m))) & 1ull) : cw;
                 uint32_t esc, lit;
                 classify_escapes(F, cin, esc, lit);
                 lit &= valid;
+                // literals count 1 each; they and the codes outside the tile read
+                // as 255 (length 0)
+                tot = (uint32_t)__builtin_popcount(lit);
+                const uint32_t fix = ~valid | lit;
 #pragma unroll
                 for (int c = 0; c < P; c++)
 #pragma unroll
-                    for (int j = 0; j < CPC; j++) {
-                        const int b = c * CPC + j;
-                        const uint32_t code = (w[c][j >> 2] >> (8 * (j & 3))) & 0xffu;
-                        const uint32_t v = ((lit >> b) & 1u) ? 1u : (uint32_t)s_len[code];
-                        tot += ((valid >> b) & 1u) ? v : 0u;
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t fb = nib_to_bytes(fix >> (c * 16 + q * 4));
+                        const uint32_t x = w[c][q] | ((fb << 8) - fb);
+                        tot += (uint32_t)s_len[x & 0xffu] + (uint32_t)s_len[(x >> 8) & 0xffu] +
+                               (uint32_t)s_len[(x >> 16) & 0xffu] + (uint32_t)s_len[x >> 24];
                     }
                 __syncthreads();                  // s_wpar of the next super-pass
             } else {
@@ -1773,10 +1792,23 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
             uint64_t sum = 0;
 #pragma unroll
             for (int i = 0; i < kNWave; i++) sum += s_wsum[i];
-            p.tagg[t] = sum;
+            out[v] = sum;
         }
-        __syncthreads();                          // s_nb and s_wsum of the next tile
+        __syncthreads();                          // s_nb, s_wsum and the table of the next tile
     }
+}
+
+template <int CODEC, typename IDX>
+__global__ void __launch_bounds__(kWG) k_tile_totals_wg(DecodeParams p) {
+    totals_tiles_wg<CODEC, IDX>(OneColumn{p}, p.tagg);
+}
+
+// A batch group's tile totals, in global tile order: out[v] for tile v.
+template <int CODEC, typename IDX>
+__global__ void __launch_bounds__(kWG) k_tile_totals_batch(const DecodeParams* __restrict__ cols,
+                                                           const int64_t* __restrict__ first_tile, int32_t n_cols,
+                                                           int64_t total, unsigned long long* out) {
+    totals_tiles_wg<CODEC, IDX>(ColumnBatch{cols, first_tile, n_cols, total, nullptr}, out);
 }
 
 // Exclusive scan of v[0, n) in place across workgroups of 1,024 entries:
@@ -2025,35 +2057,65 @@ hipError_t launch_decode(int codec, int index_bits, int mode, const DecodeParams
     return hipErrorInvalidValue;
 }
 
-template <int CODEC, typename IDX>
+template <int CODEC, typename IDX, int MODE>
 static int batch_occupancy_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_decode_batch<CODEC, IDX>, kWG, 0) != hipSuccess) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_decode_batch<CODEC, IDX, MODE>, kWG, 0) != hipSuccess)
+        nb = 1;
     return nb < 1 ? 1 : nb;
 }
 
-int batch_occupancy(int codec, int index_bits) {
-    if (codec == kFsst8) return index_bits == 64 ? batch_occupancy_of<kFsst8, int64_t>() : batch_occupancy_of<kFsst8, int32_t>();
-    if (codec == kOnpair12)
-        return index_bits == 64 ? batch_occupancy_of<kOnpair12, int64_t>() : batch_occupancy_of<kOnpair12, int32_t>();
-    return index_bits == 64 ? batch_occupancy_of<kOnpair16, int64_t>() : batch_occupancy_of<kOnpair16, int32_t>();
+#define FD_BATCH_ALL(X)                                                                                      \
+    X(kFsst8, int32_t, kModeLookback) X(kFsst8, int64_t, kModeLookback) X(kOnpair16, int32_t, kModeLookback) \
+    X(kOnpair16, int64_t, kModeLookback) X(kOnpair12, int32_t, kModeLookback)                                \
+    X(kOnpair12, int64_t, kModeLookback) X(kFsst8, int32_t, kModeExpand) X(kFsst8, int64_t, kModeExpand)      \
+    X(kOnpair16, int32_t, kModeExpand) X(kOnpair16, int64_t, kModeExpand) X(kOnpair12, int32_t, kModeExpand)  \
+    X(kOnpair12, int64_t, kModeExpand)
+
+int batch_occupancy(int codec, int index_bits, int mode) {
+#define BOCC(C, I, M) \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8) && mode == M) return batch_occupancy_of<C, I, M>();
+    FD_BATCH_ALL(BOCC)
+#undef BOCC
+    return 1;
 }
 
-hipError_t launch_decode_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
+hipError_t launch_decode_batch(int codec, int index_bits, int mode, const DecodeParams* cols, const int64_t* first_tile,
                                int32_t n_cols, int64_t total, unsigned* ctr, int grid, hipStream_t st) {
-    if (codec == kFsst8 && index_bits == 32)
-        hipLaunchKernelGGL((k_decode_batch<kFsst8, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
-    else if (codec == kFsst8)
-        hipLaunchKernelGGL((k_decode_batch<kFsst8, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
-    else if (codec == kOnpair12 && index_bits == 32)
-        hipLaunchKernelGGL((k_decode_batch<kOnpair12, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
-    else if (codec == kOnpair12)
-        hipLaunchKernelGGL((k_decode_batch<kOnpair12, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
-    else if (index_bits == 32)
-        hipLaunchKernelGGL((k_decode_batch<kOnpair16, int32_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
-    else
-        hipLaunchKernelGGL((k_decode_batch<kOnpair16, int64_t>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, total, ctr);
-    return hipGetLastError();
+#define BL(C, I, M)                                                                                        \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8) && mode == M) {                                    \
+        hipLaunchKernelGGL((k_decode_batch<C, I, M>), dim3(grid), dim3(kWG), 0, st, cols, first_tile, n_cols, \
+                           total, ctr);                                                                     \
+        return hipGetLastError();                                                                           \
+    }
+    FD_BATCH_ALL(BL)
+#undef BL
+    return hipErrorInvalidValue;
+}
+
+template <int CODEC, typename IDX>
+static int totals_batch_occupancy_of() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile_totals_batch<CODEC, IDX>, kWG, 0) != hipSuccess)
+        nb = 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_tile_totals_batch(int codec, int index_bits, const DecodeParams* cols, const int64_t* first_tile,
+                                    int32_t n_cols, int64_t total, unsigned long long* out, int cus, hipStream_t st) {
+#define TB(C, I)                                                                                             \
+    if (codec == C && index_bits == (int)(sizeof(I) * 8)) {                                                   \
+        static int occ = 0;                                                                                   \
+        if (!occ) occ = totals_batch_occupancy_of<C, I>();                                                    \
+        const int64_t g = min(total, (int64_t)cus * occ);                                                     \
+        hipLaunchKernelGGL((k_tile_totals_batch<C, I>), dim3((unsigned)max(g, (int64_t)1)), dim3(kWG), 0, st,  \
+                           cols, first_tile, n_cols, total, out);                                             \
+        return hipGetLastError();                                                                             \
+    }
+    TB(kFsst8, int32_t) TB(kFsst8, int64_t) TB(kOnpair16, int32_t) TB(kOnpair16, int64_t)
+    TB(kOnpair12, int32_t) TB(kOnpair12, int64_t)
+#undef TB
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_reset(unsigned long long* z, int64_t n, unsigned long long* errs, int32_t n_cols,

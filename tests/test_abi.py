@@ -106,7 +106,7 @@ def test_batch_argument_errors_enqueue_nothing(fdlib):
     assert L.batch_decode(arr, 0, None, P((1 << 21) + 8), 1 << 20, None, 0, None) == fdlib.EINVAL   # misaligned
     assert L.batch_decode(arr, 0, None, ws, 1 << 20, None, 1, None) == fdlib.EINVAL          # async, no status
     assert L.batch_decode(arr, 0, None, ws, 1 << 20, None, 8, None) == fdlib.EINVAL          # unknown flag
-    tu = fdlib.Tuning(1, 0, 0, 0)                                                             # three-phase mode
+    tu = fdlib.Tuning(2, 0, 0, 0)                                                             # no such mode
     assert L.batch_decode(arr, 0, ctypes.byref(tu), ws, 1 << 20, None, 0, None) == fdlib.EINVAL
     arr[0] = fdlib.Column(0, 1 << 20, 10, 1 << 20, 64, 1, 1 << 20, 1 << 20, 10)               # no dictionary
     assert L.batch_decode(arr, 1, None, ws, 1 << 20, None, 0, None) == fdlib.EINVAL

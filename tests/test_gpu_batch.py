@@ -104,7 +104,10 @@ def run_batch(cols, tuning=None, graph=False, async_=True):
 
 
 @pytest.mark.parametrize("tuning", [None, {"mode": 0, "strings_per_tile": 0, "grid": 0, "reserved": 0},
-                                    {"mode": 0, "strings_per_tile": 3, "grid": 5, "reserved": 0}])
+                                    {"mode": 0, "strings_per_tile": 3, "grid": 5, "reserved": 0},
+                                    {"mode": 1, "strings_per_tile": 0, "grid": 0, "reserved": 0},
+                                    {"mode": 1, "strings_per_tile": 3, "grid": 5, "reserved": 0},
+                                    {"mode": 1, "strings_per_tile": 1, "grid": 0, "reserved": 0}])
 def test_batch_matches_oracle(datagen_mod, tuning):
     cols = mixed_columns(datagen_mod)
     rc, st, _, _ = run_batch(cols, tuning=tuning)
@@ -122,7 +125,8 @@ def test_batch_sync_return(datagen_mod):
         c.check(0)
 
 
-def test_batch_errors_per_column(datagen_mod):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_errors_per_column(datagen_mod, mode):
     """Each column reports its own status; the overall status is the first
     error in column order; a column's error does not touch the others."""
     s = datagen_mod.fsst_small(seed=45, n_strings=800)
@@ -136,21 +140,23 @@ def test_batch_errors_per_column(datagen_mod):
     ur = datagen_mod.onpair_urls(seed=46, target_bytes=128 << 10, sample_bytes=128 << 10)
     good2 = Col("onpair16", ur.codes, ur.code_off, ur.dict_bytes, ur.dict_lens)
     cols = [good, small, bad, good2]
-    rc, st, _, _ = run_batch(cols, async_=False)
+    rc, st, _, _ = run_batch(cols, async_=False, tuning={"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0})
     assert [c.exp.status for c in cols] == [0, 4, 2, 0]
     for c, x in zip(cols, st[:-1]):
         c.check(int(x))
     assert st[-1] == 4 and rc == 4
 
 
-def test_batch_graph_replays(datagen_mod):
+@pytest.mark.parametrize("mode", [None, 0, 1])
+def test_batch_graph_replays(datagen_mod, mode):
     """FD_GRAPH: the first call records a graph, later calls replay it; every
     replay (with other device work in between) gives the oracle's result."""
     import torch
     import paper_2609_15034_amd as fd
     cols = mixed_columns(datagen_mod)
     tups = [c.tup() for c in cols]
-    ws = torch.empty(fd.batch_workspace_size(tups), dtype=torch.uint8, device="cuda")
+    tu = None if mode is None else {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    ws = torch.empty(fd.batch_workspace_size(tups, tu), dtype=torch.uint8, device="cuda")
     status = torch.full((len(cols) + 1,), -1, dtype=torch.int32, device="cuda")
     noise = torch.randn(1 << 20, device="cuda")
     for rep in range(4):
@@ -158,7 +164,7 @@ def test_batch_graph_replays(datagen_mod):
             c.clear()
         status.fill_(-1)
         noise.mul_(1.0001).add_(0.5)                   # eager work between replays
-        rc = fd.batch_decode(tups, ws, status=status, graph=True, async_=(rep % 2 == 0))
+        rc = fd.batch_decode(tups, ws, status=status, graph=True, async_=(rep % 2 == 0), tuning=tu)
         torch.cuda.synchronize()
         assert rc == 0
         st = status.cpu().numpy()
@@ -183,7 +189,8 @@ def test_batch_equals_single(datagen_mod):
         assert torch.equal(out[:n], c.out[:n])
 
 
-def test_batch_many_small_columns(datagen_mod):
+@pytest.mark.parametrize("mode", [None, 1])
+def test_batch_many_small_columns(datagen_mod, mode):
     """256 columns, sizes log-uniform over two decades, codecs alternating."""
     rng = np.random.default_rng(47)
     s = datagen_mod.fsst_small(seed=48, n_strings=4000)
@@ -203,7 +210,8 @@ def test_batch_many_small_columns(datagen_mod):
         else:
             dp = c.d
         cols.append(c)
-    rc, st, _, _ = run_batch(cols)
+    tu = None if mode is None else {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    rc, st, _, _ = run_batch(cols, tuning=tu)
     assert rc == 0
     for c, x in zip(cols, st[:-1]):
         c.check(int(x))
