@@ -706,15 +706,12 @@ __device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], ui
         }
         if ((lit >> j) & 1u) v0 = b0;             // (an escape, a code that is not a symbol and a
         if ((lit >> (j + 1)) & 1u) v1 = b1;       // code outside the tile read zero entries)
-        // the pair: v0 | v1 << 8 * l0 over 128 bits, l0 in 0..8
+        // the pair: v0 | v1 << 8 * l0 over 128 bits, l0 in 0..8; each shift is
+        // split in two of at most 32 bits, so l0 = 0 and l0 = 8 need no select
+        const uint32_t sl = 4u * l0, sr = 32u - sl;
         U128 pr;
-        if (l0 >= 8) {
-            pr.lo = v0;
-            pr.hi = v1;
-        } else {
-            pr.lo = v0 | (v1 << (8u * l0));
-            pr.hi = (v1 >> 1) >> (63u - 8u * l0);
-        }
+        pr.lo = v0 | ((v1 << sl) << sl);
+        pr.hi = (v1 >> sr) >> sr;
         const u32x4 v = {(uint32_t)pr.lo, (uint32_t)(pr.lo >> 32), (uint32_t)pr.hi, (uint32_t)(pr.hi >> 32)};
         lds_put16(&s.stage[q], v);
         const uint32_t qr = (uint32_t)(q - q0);
