@@ -476,7 +476,8 @@ template <typename S>
 __device__ __forceinline__ uint32_t fsst_chunk_lengths(S& s, const uint32_t (&w)[4], uint32_t lit, uint32_t valid,
                                                        uint32_t esc, uint32_t (&pre)[4], uint32_t (&lenp)[4],
                                                        uint32_t& bad) {
-    uint32_t ctot = 0;
+    // the chunk's 16 length reads are all issued before any of them is used
+    uint32_t lws[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const uint32_t vn = (valid >> (q * 4)) & 0xfu;
@@ -484,14 +485,24 @@ __device__ __forceinline__ uint32_t fsst_chunk_lengths(S& s, const uint32_t (&w)
         // literals and codes outside the tile read as 255 (length 0 in the table)
         const uint32_t fb = nib_to_bytes((~vn & 0xfu) | ln);
         const uint32_t x = w[q] | ((fb << 8) - fb);
-        uint32_t lw = (uint32_t)s.fsst_len[x & 0xffu] | ((uint32_t)s.fsst_len[(x >> 8) & 0xffu] << 8) |
-                      ((uint32_t)s.fsst_len[(x >> 16) & 0xffu] << 16) | ((uint32_t)s.fsst_len[x >> 24] << 24);
-        const uint32_t m = lw & 0x80808080u;      // codes that are not symbols
-        if (__ballot(m != 0u)) {                  // rare: a scalar branch skips it in most waves
+        lws[q] = (uint32_t)s.fsst_len[x & 0xffu] | ((uint32_t)s.fsst_len[(x >> 8) & 0xffu] << 8) |
+                 ((uint32_t)s.fsst_len[(x >> 16) & 0xffu] << 16) | ((uint32_t)s.fsst_len[x >> 24] << 24);
+    }
+    // codes that are not symbols (rare: one scalar branch skips them in most waves)
+    if (__ballot(((lws[0] | lws[1] | lws[2] | lws[3]) & 0x80808080u) != 0u)) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t m = lws[q] & 0x80808080u;
             bad |= (((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu) << (q * 4);
-            lw &= 0x7f7f7f7fu;
+            lws[q] &= 0x7f7f7f7fu;
         }
-        lw += nib_to_bytes(ln);                   // a literal is one byte
+    }
+    uint32_t ctot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t vn = (valid >> (q * 4)) & 0xfu;
+        const uint32_t ln = (lit >> (q * 4)) & vn & 0xfu;
+        const uint32_t lw = lws[q] + nib_to_bytes(ln);   // a literal is one byte
         // per-code prefix inside the chunk, as bytes (every partial sum stays below 128)
         const uint32_t incl = (lw << 8) + (lw << 16) + (lw << 24);
         pre[q] = (__builtin_amdgcn_perm(0u, ctot, 0x00000000u) + incl) | bits_to_byte_msb((esc >> (q * 4)) & 0xfu);
