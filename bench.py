@@ -32,8 +32,9 @@ sidecar decode against the look-back on the FSST-8 and OnPair-16 columns
 ("sidecar"), selective decode of row subsets of those columns ("take"), and,
 in "batch" and "serve", short runs of the batched workload
 (256 columns in one replayed HIP graph, against the same columns decoded one
-call each) and of the served workload (Poisson arrivals into the
-continuous-batching server, p50/p99 latency); --no-extra skips them.
+call each) and of the served workload (5,000 Poisson arrivals per load into
+the continuous-batching server at 0.5, 0.7, 0.9 and 1.5 x its batch capacity,
+p50/p99 latency); --no-extra skips them.
 """
 from __future__ import annotations
 
@@ -341,11 +342,11 @@ def run_batch(steps: int, warmup: int, seed: int | None, n_cols: int = 256, max_
 
 def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budget: int = 16 * 10**9,
               n_slots: int = 4, max_batch: int = 64, check: bool = True, n_chunks: int = 128,
-              sat_load: float = 1.5):
+              sat_load: float = 1.5, other_loads: tuple = (0.5, 0.9)):
     """The served workload: Poisson arrivals at `load` x the server's measured
-    batch capacity (latency at a moderate load), then at `sat_load` x capacity
-    (offered above capacity: the served rate the server sustains).  Returns a
-    result dict with p50 / p99 latency."""
+    batch capacity (latency at a moderate load), at each of `other_loads`, then
+    at `sat_load` x capacity (offered above capacity: the served rate the server
+    sustains).  Returns a result dict with p50 / p99 latency."""
     import threading
     import numpy as np
     import torch
@@ -446,12 +447,17 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
         return out
 
     out = serve_once(load, n_requests, (seed or 5) + 1)
+    others = {}
+    for k, ld in enumerate(other_loads):
+        o = serve_once(ld, n_requests, (seed or 5) + 3 + k)
+        others[str(ld)] = {key: o[key] for key in ("value", "offered_GBps", "latency_ms", "mean_batch", "bit_exact")}
     sat = serve_once(sat_load, n_requests, (seed or 5) + 2)
     out.update({"batch_capacity_GBps": round(cap_bps / 1e9, 2), "one_call_per_chunk_GBps": round(each_bps / 1e9, 2),
                 "budget_bytes": budget, "slots": n_slots,
                 "saturated": {k: sat[k] for k in ("value", "load", "offered_GBps", "latency_ms", "mean_batch",
                                                   "batches", "max_inflight_bytes", "bit_exact")},
-                "saturated_over_capacity": round(sat["value"] * 1e9 / cap_bps, 3)})
+                "saturated_over_capacity": round(sat["value"] * 1e9 / cap_bps, 3),
+                "other_loads": others})
     return out
 
 
@@ -655,7 +661,7 @@ def main():
         # the batched and served legs first, on a fresh allocator (the legs after them hold large buffers)
         for key, fn in (("batch", lambda: run_batch(10, 2, None, check=not args.no_check, cpu=False,
                                                     single_rates=rates if len(rates) == 2 else None)),
-                        ("serve", lambda: run_serve(None, n_requests=2000, check=not args.no_check))):
+                        ("serve", lambda: run_serve(None, n_requests=5000, check=not args.no_check))):
             torch.cuda.empty_cache()
             try:
                 res[key] = fn()
