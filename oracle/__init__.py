@@ -259,13 +259,13 @@ def decode_onpair16_copy16(codes, code_off, dict_bytes, dict_lens):
 
 
 def time_decode(codec: str, codes, code_off, dict_bytes, dict_lens, threads: int = 1, repeats: int = 1,
-                max_strings: int | None = None, n_codes: int | None = None):
+                max_strings: int | None = None, n_codes: int | None = None, times: list | None = None):
     """Time the oracle on contiguous string-range shards decoded by `threads`
     threads at once (each shard is an independent oracle call; the calls
-    release the GIL).  Returns (best_seconds, decoded_bytes, strings_used).
-    Only the decode calls are timed; outputs are preallocated.  12-bit codes
-    are unpacked before the timed region (as the paper widens them before
-    decoding)."""
+    release the GIL).  Returns (best_seconds, decoded_bytes, strings_used);
+    every repeat's time is appended to `times` when given.  Only the decode
+    calls are timed; outputs are preallocated.  12-bit codes are unpacked
+    before the timed region (as the paper widens them before decoding)."""
     if codec == "onpair12":
         packed = np.ascontiguousarray(codes, dtype=np.uint8)
         codes = unpack12_np(packed, (len(packed) * 8) // 12 if n_codes is None else int(n_codes))
@@ -312,6 +312,8 @@ def time_decode(codec: str, codes, code_off, dict_bytes, dict_lens, threads: int
             t.join()
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
+        if times is not None:
+            times.append(dt)
     if any(r[0] != OK for r in results):
         raise RuntimeError("oracle failed on a shard: %r" % (results,))
     return best, sum(r[1] for r in results), s
