@@ -359,6 +359,7 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
     batch capacity (latency at a moderate load), at each of `other_loads`, then
     at `sat_load` x capacity (offered above capacity: the served rate the server
     sustains).  Returns a result dict with p50 / p99 latency."""
+    import gc
     import threading
     import numpy as np
     import torch
@@ -413,21 +414,31 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
         log(f"[serve] load {ld}: offered {ld * cap_bps / 1e9:.1f} GB/s = {rate:.0f} requests/s")
         torch.cuda.synchronize()
         tickets = [0] * n_req
-        with fd.Server(max_inflight_bytes=budget, n_slots=n_slots, max_batch=max_batch) as srv:
-            t_start = time.perf_counter()
+        lag = [0.0]
+        sub_t = np.zeros(n_req)                                # submission times (s from the start)
+        recs = [fd.Server.prepare(r) for r in reqs]          # built before the clock starts
+        gc.disable()                                         # no collector pauses in the producer's schedule
+        try:
+            with fd.Server(max_inflight_bytes=budget, n_slots=n_slots, max_batch=max_batch) as srv:
+                t_start = time.perf_counter()
 
-            def producer():
-                for k in range(n_req):
-                    dt = arrivals[k] - (time.perf_counter() - t_start)
-                    if dt > 0:
-                        time.sleep(dt)
-                    tickets[k] = srv.submit(reqs[k])
-            th = threading.Thread(target=producer)
-            th.start()
-            th.join()
-            res = [srv.wait(t) for t in tickets]
-            wall = time.perf_counter() - t_start
-            stats = srv.stats()
+                def producer():
+                    for k in range(n_req):
+                        dt = arrivals[k] - (time.perf_counter() - t_start)
+                        if dt > 0:
+                            time.sleep(dt)
+                        else:
+                            lag[0] = max(lag[0], -dt)
+                        sub_t[k] = time.perf_counter() - t_start
+                        tickets[k] = srv.submit(recs[k])
+                th = threading.Thread(target=producer)
+                th.start()
+                th.join()
+                res = [srv.wait(t) for t in tickets]
+                wall = time.perf_counter() - t_start
+                stats = srv.stats()
+        finally:
+            gc.enable()
         sts = np.array([r[0] for r in res])
         lat = np.array([r[1] for r in res]) / 1e3                    # ms
         if np.any(sts != 0):
@@ -440,34 +451,42 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
             bit_exact = ok
         # steady window: drop the first 5% of requests (arrival times) from the rate and the latencies
         k0 = n_req // 20
-        completion = arrivals + lat / 1e3
-        t_end = max(float(completion.max()), wall)
+        # a request completes at its submission plus its latency (the server's clock
+        # runs from the submit call to the host seeing its batch done)
+        completion = sub_t + lat / 1e3
+        t_end = float(completion.max())
         D = float(sizes[k0:].sum())
         rate_window = t_end - float(arrivals[k0])
         lat = lat[k0:]
         out = {"value": round(D / rate_window / 1e9, 2), "unit": "GB/s", "n_requests": n_req,
                "steady_window": f"requests {k0}..{n_req - 1} (first 5% dropped)", "load": ld,
                "offered_GBps": round(ld * cap_bps / 1e9, 2),
+               # the sampled arrivals' own rate over the window (Poisson noise around offered_GBps)
+               "arrived_GBps": round(float(sizes[k0:-1].sum()) / max(float(arrivals[-1] - arrivals[k0]), 1e-9) / 1e9,
+                                     2),
                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                               "p99": round(float(np.percentile(lat, 99)), 3),
                               "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
                "mean_request_MB": round(float(sizes.mean()) / 1e6, 2),
                "max_inflight_bytes": stats["max_inflight_bytes"], "batches": stats["batches"],
-               "mean_batch": round(stats["admitted"] / max(stats["batches"], 1), 2), "bit_exact": bit_exact}
+               "mean_batch": round(stats["admitted"] / max(stats["batches"], 1), 2), "bit_exact": bit_exact,
+               "producer_max_lag_ms": round(lag[0] * 1e3, 3), "wall_s": round(wall, 4)}
         log(f"[serve] load {ld}: {out['value']} GB/s, p50 {out['latency_ms']['p50']} ms, "
-            f"p99 {out['latency_ms']['p99']} ms, mean batch {out['mean_batch']}")
+            f"p99 {out['latency_ms']['p99']} ms, mean batch {out['mean_batch']}, arrived {out['arrived_GBps']} GB/s, "
+            f"submissions at most {out['producer_max_lag_ms']} ms behind their arrival times")
         return out
 
     out = serve_once(load, n_requests, (seed or 5) + 1)
     others = {}
     for k, ld in enumerate(other_loads):
         o = serve_once(ld, n_requests, (seed or 5) + 3 + k)
-        others[str(ld)] = {key: o[key] for key in ("value", "offered_GBps", "latency_ms", "mean_batch", "bit_exact")}
+        others[str(ld)] = {key: o[key] for key in ("value", "offered_GBps", "arrived_GBps", "latency_ms", "mean_batch",
+                                                   "bit_exact", "producer_max_lag_ms")}
     sat = serve_once(sat_load, n_requests, (seed or 5) + 2)
     out.update({"batch_capacity_GBps": round(cap_bps / 1e9, 2), "one_call_per_chunk_GBps": round(each_bps / 1e9, 2),
                 "budget_bytes": budget, "slots": n_slots,
                 "saturated": {k: sat[k] for k in ("value", "load", "offered_GBps", "latency_ms", "mean_batch",
-                                                  "batches", "max_inflight_bytes", "bit_exact")},
+                                                  "batches", "max_inflight_bytes", "bit_exact", "producer_max_lag_ms")},
                 "saturated_over_capacity": round(sat["value"] * 1e9 / cap_bps, 3),
                 "other_loads": others})
     return out

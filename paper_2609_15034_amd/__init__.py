@@ -455,8 +455,16 @@ class Server:
         if st:
             raise DecodeError(st, "fd_server_create")
 
+    @staticmethod
+    def prepare(col):
+        """A request's column record, built ahead of ``submit`` so that the
+        submission costs only the library call (its tensors must stay alive as
+        for ``submit``)."""
+        return make_columns([col])
+
     def submit(self, col) -> int:
-        arr = make_columns([col])
+        """Enqueue a column tuple, or a record from ``prepare``; returns the ticket."""
+        arr = col if isinstance(col, ctypes.Array) else make_columns([col])
         t = ctypes.c_uint64(0)
         st = lib().fd_server_submit(self._h, arr, ctypes.byref(t))
         if st:

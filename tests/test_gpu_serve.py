@@ -67,8 +67,9 @@ def test_served_equals_alone(pool, budget, slots, max_batch):
     reqs += [Req(c, dicts[k]) for c, k in zip(pool.chunks[::-1], pool.chunk_dict[::-1])]
     ref = [alone(r) for r in reqs]
     torch.cuda.synchronize()
+    recs = [fd.Server.prepare(r.tup()) for r in reqs[::2]]     # every other request as a prepared record
     with fd.Server(max_inflight_bytes=budget, n_slots=slots, max_batch=max_batch) as srv:
-        tickets = [srv.submit(r.tup()) for r in reqs]
+        tickets = [srv.submit(recs[k // 2] if k % 2 == 0 else r.tup()) for k, r in enumerate(reqs)]
         res = [srv.wait(t) for t in tickets]
         stats = srv.stats()
     for r, (st, lat), (st0, off0, out0) in zip(reqs, res, ref):
