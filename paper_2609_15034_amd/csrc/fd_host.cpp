@@ -272,6 +272,7 @@ fd_status run_decode(const Args& a) {
             p.n_sym = a.n_dict;
         }
     } else {
+        p.n_sym = a.dict ? a.dict->n : a.n_dict;    // codes at or past it are not tokens
         if (a.dict) {
             p.tok16 = a.dict->tok16;
             p.tok_len = a.dict->tok_len;

@@ -1662,24 +1662,36 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
     }
 }
 
-// The same totals with a workgroup per tile (OnPair: a tile's 16 length
-// gathers per lane spread over four waves finish sooner than on one; batches:
-// all waves of a workgroup work on one column, so its LDS table serves them).
-// The source's tile v goes to out[v]; each workgroup takes tiles blockIdx.x,
-// + gridDim.x, ..., and reloads its table when the dictionary changes.
+// The same totals with a workgroup per tile (OnPair: the length table in LDS
+// serves four waves; batches: all waves of a workgroup work on one column, so
+// its LDS table serves them).  The source's tile v goes to out[v]; each
+// workgroup takes tiles blockIdx.x, + gridDim.x, ... of one column, or a
+// contiguous range of a batch's tiles, and reloads its table when the
+// dictionary changes.
 template <int CODEC, typename IDX, typename SRC>
 __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
     using C = Cfg<CODEC>;
     constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
+    // OnPair-16: the 65,536 token lengths as nibbles in LDS (16 stored as 0),
+    // read once per workgroup and dictionary instead of a gather per code
+    constexpr bool kNib = CODEC == kOnpair16;
     __shared__ uint8_t s_len[256];
     __shared__ alignas(16) uint8_t s_len12[kPacked12<CODEC> ? 4096 : 16];
+    __shared__ alignas(16) uint8_t s_nib[kNib ? 32768 : 16];
     __shared__ uint32_t s_wpar[kNWave];
     __shared__ uint64_t s_wsum[kNWave];
     __shared__ int64_t s_nb[2];
     const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const void* table = nullptr;                  // the dictionary whose lengths are in LDS
     int col = 0;
-    for (int64_t v = blockIdx.x; v < src.n_tiles(); v += gridDim.x) {
+    // one column: tiles blockIdx.x, + gridDim.x, ...; a batch: a contiguous
+    // range of tiles per workgroup, so that it reloads its table only where
+    // its range crosses into a column of another dictionary
+    const int64_t n_all = src.n_tiles();
+    const int64_t v_begin = SRC::kBatch ? (int64_t)blockIdx.x * n_all / gridDim.x : (int64_t)blockIdx.x;
+    const int64_t v_end = SRC::kBatch ? ((int64_t)blockIdx.x + 1) * n_all / gridDim.x : n_all;
+    const int64_t v_step = SRC::kBatch ? 1 : (int64_t)gridDim.x;
+    for (int64_t v = v_begin; v < v_end; v += v_step) {
         col = src.column(v, col);
         const DecodeParams& p = src.params(col);
         const int64_t t = v - src.first(col);
@@ -1702,6 +1714,23 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
         } else if constexpr (kPacked12<CODEC>) {
             if ((const void*)p.tok_len != table) {   // 12-bit codes: their 4,096 lengths
                 for (unsigned i = tid; i < 4096 / 16; i += kWG) ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
+                table = p.tok_len;
+            }
+        } else if constexpr (kNib) {
+            if ((const void*)p.tok_len != table) {
+                // 16 lengths (bytes of 0..16) to 8 bytes of nibbles, code 2k in the low nibble of byte k
+                for (unsigned i = tid; i < 65536 / 16; i += kWG) {
+                    const uint4 a = ((const uint4*)p.tok_len)[i];
+                    const uint32_t x[4] = {a.x, a.y, a.z, a.w};
+                    uint32_t h[4];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const uint32_t y = x[k] & 0x0f0f0f0fu;
+                        const uint32_t z = y | (y >> 4);
+                        h[k] = (z & 0xffu) | ((z >> 8) & 0xff00u);
+                    }
+                    ((uint2*)s_nib)[i] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+                }
                 table = p.tok_len;
             }
         }
@@ -1782,10 +1811,16 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
                         for (int r = 0; r < 4; r++) {
                             const int j = q * 4 + r;
                             const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                            if constexpr (kPacked12<CODEC>)
+                            if constexpr (kPacked12<CODEC>) {
                                 lw |= (uint32_t)s_len12[cj & 0xfffu] << (8 * r);
-                            else
+                            } else if constexpr (kNib) {
+                                // the nibble, 0 read as 16; codes past the dictionary count 0
+                                const uint32_t nib = ((uint32_t)s_nib[cj >> 1] >> ((cj & 1u) * 4u)) & 0xfu;
+                                const uint32_t l = (int)cj < p.n_sym ? ((nib + 15u) & 0xfu) + 1u : 0u;
+                                lw |= l << (8 * r);
+                            } else {
                                 lw |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0) << (8 * r);
+                            }
                         }
                         lw &= nib_to_bytes(valid >> (c * CPC + q * 4)) * 0xffu;
                         tot = __builtin_amdgcn_sad_u8(lw, 0u, tot);

@@ -204,6 +204,22 @@ def test_device_errors():
     assert_parity("fsst8", u8(9), i64(0, 2), db, dl)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("bad_at", [None, 3, 200_000])
+def test_onpair16_short_dictionary_many_tiles(datagen_mod, mode, bad_at):
+    """OnPair-16 over many tiles with a 1,000-token dictionary; with bad_at a
+    code past the dictionary (and a token of 16 bytes elsewhere): the status is
+    the oracle's, and without one the output is, in both ways to the cursors."""
+    c = datagen_mod.random_onpair(seed=41, n_codes=300_000, n_strings=20_000, n_tok=1000)
+    codes = c.codes.copy()
+    dl = c.dict_lens.copy()
+    assert (dl == 16).any()
+    if bad_at is not None:
+        codes[bad_at] = 1000 + bad_at % 7
+    assert_parity("onpair16", codes, c.code_off, c.dict_bytes, dl,
+                  tuning={"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+
+
 def test_dict_create_rejects_bad_lengths():
     import torch
     import paper_2609_15034_amd as fd
