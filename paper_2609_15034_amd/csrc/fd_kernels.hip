@@ -1552,7 +1552,12 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
     constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
     constexpr int64_t CPI = 64 * P;               // chunks per step of a wave
     __shared__ uint8_t s_len[256];
+    __shared__ alignas(16) uint8_t s_len12[kPacked12<CODEC> ? 4096 : 16];
     const unsigned tid = threadIdx.x, lane = tid & 63;
+    if constexpr (kPacked12<CODEC>) {             // 12-bit codes: their 4,096 lengths
+        for (unsigned i = tid; i < 4096 / 16; i += kWG) ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
+        __syncthreads();
+    }
     if constexpr (CODEC == kFsst8) {
         // per code its length: 0 for the escape and for codes that are not symbols
         for (unsigned c = tid; c < 256; c += kWG) {
@@ -1651,7 +1656,11 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                     for (int j = 0; j < CPC; j++) {
                         const int b = c * CPC + j;
                         const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                        const uint32_t l = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
+                        uint32_t l;
+                        if constexpr (kPacked12<CODEC>)
+                            l = s_len12[cj & 0xfffu];
+                        else
+                            l = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
                         tot += ((valid >> b) & 1u) ? l : 0u;
                     }
             }
@@ -2198,10 +2207,16 @@ hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned l
     return hipGetLastError();
 }
 
+// Streamed totals of one column: a wave per tile with its loads a step ahead
+// (FSST-8, 12-bit codes with their lengths in LDS), or a workgroup per tile
+// (OnPair-16, whose length table as nibbles serves the workgroup's waves).
+template <int CODEC> constexpr bool kTotalsPerWave = CODEC == kFsst8 || CODEC == kOnpair12;
+
 template <int CODEC, typename IDX>
 static int totals_occupancy_of() {
     int nb = 0;
-    const void* k = CODEC == kFsst8 ? (const void*)k_tile_totals<CODEC, IDX> : (const void*)k_tile_totals_wg<CODEC, IDX>;
+    const void* k = kTotalsPerWave<CODEC> ? (const void*)k_tile_totals<CODEC, IDX>
+                                          : (const void*)k_tile_totals_wg<CODEC, IDX>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kWG, 0) != hipSuccess) nb = 1;
     return nb < 1 ? 1 : nb;
 }
@@ -2212,7 +2227,7 @@ hipError_t launch_tile_totals(int codec, int index_bits, const DecodeParams& p, 
         static int occ = 0;                                                                                    \
         if (!occ) occ = totals_occupancy_of<C, I>();                                                           \
         const int64_t g = min(p.n_tiles, (int64_t)cus * occ);                                                  \
-        if (C == kFsst8)                                                                                       \
+        if (kTotalsPerWave<C>)                                                                                 \
             hipLaunchKernelGGL((k_tile_totals<C, I>), dim3((unsigned)max(g, (int64_t)1)), dim3(kWG), 0, st, p); \
         else                                                                                                   \
             hipLaunchKernelGGL((k_tile_totals_wg<C, I>), dim3((unsigned)max(g, (int64_t)1)), dim3(kWG), 0, st, p); \
