@@ -1545,6 +1545,30 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
 // the tile the escape parity runs on across strings exactly as in the expand
 // phase's scan (in valid data no string ends inside a run of escapes of odd
 // length).
+// OnPair-16 token lengths as nibbles in LDS (32 KiB): 16 lengths (bytes of
+// 0..16) become 8 bytes, code 2k in the low nibble of byte k, 16 stored as 0.
+__device__ __forceinline__ void nib_table_load(uint8_t* s_nib, const uint8_t* tok_len) {
+    for (unsigned i = threadIdx.x; i < 65536 / 16; i += blockDim.x) {
+        const uint4 a = ((const uint4*)tok_len)[i];
+        const uint32_t x[4] = {a.x, a.y, a.z, a.w};
+        uint32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t y = x[k] & 0x0f0f0f0fu;
+            const uint32_t z = y | (y >> 4);
+            h[k] = (z & 0xffu) | ((z >> 8) & 0xff00u);
+        }
+        ((uint2*)s_nib)[i] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+}
+
+// A code's length from the nibble table: the nibble, 0 read as 16; codes at
+// or past the dictionary's size count 0.
+__device__ __forceinline__ uint32_t nib_length(const uint8_t* s_nib, uint32_t cj, int32_t n_tok) {
+    const uint32_t nib = ((uint32_t)s_nib[cj >> 1] >> ((cj & 1u) * 4u)) & 0xfu;
+    return (int)cj < n_tok ? ((nib + 15u) & 0xfu) + 1u : 0u;
+}
+
 // --------------------------------------------------------------------------
 template <int CODEC, typename IDX>
 __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
@@ -1553,9 +1577,14 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
     constexpr int64_t CPI = 64 * P;               // chunks per step of a wave
     __shared__ uint8_t s_len[256];
     __shared__ alignas(16) uint8_t s_len12[kPacked12<CODEC> ? 4096 : 16];
+    __shared__ alignas(16) uint8_t s_nib[CODEC == kOnpair16 ? 32768 : 16];
     const unsigned tid = threadIdx.x, lane = tid & 63;
     if constexpr (kPacked12<CODEC>) {             // 12-bit codes: their 4,096 lengths
         for (unsigned i = tid; i < 4096 / 16; i += kWG) ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
+        __syncthreads();
+    }
+    if constexpr (CODEC == kOnpair16) {           // OnPair-16: the lengths as nibbles
+        nib_table_load(s_nib, p.tok_len);
         __syncthreads();
     }
     if constexpr (CODEC == kFsst8) {
@@ -1660,7 +1689,7 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                         if constexpr (kPacked12<CODEC>)
                             l = s_len12[cj & 0xfffu];
                         else
-                            l = __builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0);
+                            l = nib_length(s_nib, cj, p.n_sym);
                         tot += ((valid >> b) & 1u) ? l : 0u;
                     }
             }
@@ -1727,19 +1756,7 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
             }
         } else if constexpr (kNib) {
             if ((const void*)p.tok_len != table) {
-                // 16 lengths (bytes of 0..16) to 8 bytes of nibbles, code 2k in the low nibble of byte k
-                for (unsigned i = tid; i < 65536 / 16; i += kWG) {
-                    const uint4 a = ((const uint4*)p.tok_len)[i];
-                    const uint32_t x[4] = {a.x, a.y, a.z, a.w};
-                    uint32_t h[4];
-#pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const uint32_t y = x[k] & 0x0f0f0f0fu;
-                        const uint32_t z = y | (y >> 4);
-                        h[k] = (z & 0xffu) | ((z >> 8) & 0xff00u);
-                    }
-                    ((uint2*)s_nib)[i] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-                }
+                nib_table_load(s_nib, p.tok_len);
                 table = p.tok_len;
             }
         }
@@ -1823,10 +1840,7 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
                             if constexpr (kPacked12<CODEC>) {
                                 lw |= (uint32_t)s_len12[cj & 0xfffu] << (8 * r);
                             } else if constexpr (kNib) {
-                                // the nibble, 0 read as 16; codes past the dictionary count 0
-                                const uint32_t nib = ((uint32_t)s_nib[cj >> 1] >> ((cj & 1u) * 4u)) & 0xfu;
-                                const uint32_t l = (int)cj < p.n_sym ? ((nib + 15u) & 0xfu) + 1u : 0u;
-                                lw |= l << (8 * r);
+                                lw |= nib_length(s_nib, cj, p.n_sym) << (8 * r);
                             } else {
                                 lw |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r_len, cj, 0, 0) << (8 * r);
                             }
@@ -2208,9 +2222,9 @@ hipError_t launch_scan_totals(unsigned long long* v, int64_t n, const unsigned l
 }
 
 // Streamed totals of one column: a wave per tile with its loads a step ahead
-// (FSST-8, 12-bit codes with their lengths in LDS), or a workgroup per tile
-// (OnPair-16, whose length table as nibbles serves the workgroup's waves).
-template <int CODEC> constexpr bool kTotalsPerWave = CODEC == kFsst8 || CODEC == kOnpair12;
+// and the lengths in LDS (FSST-8's table, 12-bit codes' 4,096 bytes, OnPair-16's
+// nibbles), or a workgroup per tile.
+template <int CODEC> constexpr bool kTotalsPerWave = true;
 
 template <int CODEC, typename IDX>
 static int totals_occupancy_of() {
