@@ -8,7 +8,9 @@ dictionary prepared beforehand (the paper repacks dictionaries before timing).
 The tile cursors come from the three-phase path by default (--mode 1: tile
 totals streamed, scanned, then the expand pass), the fastest way on these
 columns; --mode 0 takes the single pass with its decoupled look-back.
-Default workload: FSST-8 log lines, 1 GiB decoded, int64 offsets.
+Default workload: FSST-8 log lines, 1 GiB decoded, int64 offsets, with the table
+built as the configuration states it (top-255 frequent 1-8 byte n-grams of a
+1 MiB sample); "fsst_logs" is the same text with an FSST-style trained table.
 
 Prints one JSON line:
   value        decoded GB/s (1e9 output bytes per second) = decoded bytes /
@@ -21,7 +23,8 @@ Prints one JSON line:
   cpu_baseline the CPU oracle on this host's cores over the same column
   bit_exact    GPU output == the generated source text (bytes and offsets)
 
-  python bench.py [--workload fsst_logs|onpair_urls|onpair12_urls|fsst12_logs|fsst_small|batch256|serve]
+  python bench.py [--workload fsst_logs_ngram|fsst_logs|onpair_urls|onpair12_urls|fsst12_logs|fsst_small|
+                              batch256|serve]
                   [--steps K] [--warmup W] [--sidecar]
 
 --sidecar times the decode with output positions read from a stored sidecar
@@ -51,7 +54,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "decoded GB/s per GPU (fraction of HBM peak), bit-exact; p50/p99 latency served"
 WORKLOADS = {
-    "fsst_logs": dict(codec="fsst8", desc="FSST-8 log lines, 1 GiB decoded, int64 offsets"),
+    "fsst_logs_ngram": dict(codec="fsst8", desc="FSST-8 log lines, 1 GiB decoded, int64 offsets; table = top-255 "
+                                                "frequent 1-8 byte n-grams of a 1 MiB sample, greedy longest match",
+                            table="top-255 1-8-byte n-grams of a 1 MiB sample (count x length)"),
+    "fsst_logs": dict(codec="fsst8", desc="FSST-8 log lines, 1 GiB decoded, int64 offsets; table trained by "
+                                          "FSST-style rounds on a 1 MiB sample",
+                      table="FSST-style trained rounds on a 1 MiB sample"),
     "onpair_urls": dict(codec="onpair16", desc="OnPair-16 URL/identifier strings, 1 GiB decoded, int64 offsets"),
     "onpair12_urls": dict(codec="onpair12", desc="OnPair-12 (12-bit packed codes, 4,096 tokens) URL/identifier "
                                                  "strings, 1 GiB decoded, int64 offsets"),
@@ -65,6 +73,13 @@ WORKLOADS = {
 }
 KERNEL_SOURCES = ["paper_2609_15034_amd/csrc/fd_kernels.hip", "paper_2609_15034_amd/csrc/fd_internal.h",
                   "paper_2609_15034_amd/csrc/fd_host.cpp"]
+
+
+def positions_label(mode: int, sidecar: bool) -> str:
+    """How the step finds each tile's output position."""
+    if sidecar:
+        return "stored sidecar"
+    return "look-back (single pass)" if mode == 0 else "three phases (tile totals, scan, expand)"
 
 
 def log(*a):
@@ -81,6 +96,8 @@ def kernel_source_hash() -> str:
 
 def make_column(name: str, seed: int | None):
     import datagen
+    if name == "fsst_logs_ngram":
+        return datagen.fsst_logs_ngram(seed=seed or 2)
     if name == "fsst_logs":
         return datagen.fsst_logs(seed=seed or 2)
     if name == "onpair_urls":
@@ -193,6 +210,34 @@ def single_rate(workload: str, steps: int = 10, seed: int | None = None, mode: i
     if int(st.item()) != fd.OK or not torch.equal(out, torch.from_numpy(col.text).to(dev)):
         raise fd.DecodeError(int(st.item()), f"{workload} mode {mode}: output differs from the source")
     return col.decoded_bytes / mean_s / 1e9
+
+
+def small_latency(runs: int = 200, mode: int = 1, seed: int | None = None) -> dict:
+    """The small FSST-8 column (10,000 printable strings, int32 offsets): the
+    latency of one whole decode call, timed with events around each call on
+    the library's stream, over `runs` calls after a warm-up; the output is
+    checked against the source strings."""
+    import numpy as np
+    import torch
+    import paper_2609_15034_amd as fd
+    col = make_column("fsst_small", seed)
+    dev = torch.device("cuda")
+    codes, code_off = _upload_column(col, dev)
+    d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
+    out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
+    out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
+    tu = {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tu)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    _, per = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True,
+                                                 tuning=tu), runs, 10)
+    ok = int(st.item()) == fd.OK and torch.equal(out, torch.from_numpy(col.text).to(dev)) and \
+        torch.equal(out_off.to(torch.int64), torch.from_numpy(col.text_off.astype(np.int64)).to(dev))
+    us = per * 1e6
+    return {"decoded_bytes": col.decoded_bytes, "n_strings": col.n_strings, "runs": runs, "mode": mode,
+            "latency_us": {"min": round(float(us.min()), 2), "p50": round(float(np.median(us)), 2),
+                           "p99": round(float(np.percentile(us, 99)), 2)},
+            "GBps_at_p50": round(col.decoded_bytes / float(np.median(per)) / 1e9, 3), "bit_exact": bool(ok)}
 
 
 def sidecar_rates(workload: str, steps: int = 20, seed: int | None = None) -> dict:
@@ -354,7 +399,7 @@ def run_batch(steps: int, warmup: int, seed: int | None, n_cols: int = 256, max_
 
 def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budget: int = 16 * 10**9,
               n_slots: int = 4, max_batch: int = 64, check: bool = True, n_chunks: int = 128,
-              sat_load: float = 1.5, other_loads: tuple = (0.5, 0.9)):
+              sat_load: float = 1.5, other_loads: tuple = (0.5, 0.9), single_rates: dict | None = None):
     """The served workload: Poisson arrivals at `load` x the server's measured
     batch capacity (latency at a moderate load), at each of `other_loads`, then
     at `sat_load` x capacity (offered above capacity: the served rate the server
@@ -457,7 +502,9 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
         t_end = float(completion.max())
         D = float(sizes[k0:].sum())
         rate_window = t_end - float(arrivals[k0])
-        lat = lat[k0:]
+        # latency = completion - scheduled arrival (includes any lag of the producer behind the schedule)
+        lat_sub = lat[k0:]
+        lat = (completion - arrivals)[k0:] * 1e3
         out = {"value": round(D / rate_window / 1e9, 2), "unit": "GB/s", "n_requests": n_req,
                "steady_window": f"requests {k0}..{n_req - 1} (first 5% dropped)", "load": ld,
                "offered_GBps": round(ld * cap_bps / 1e9, 2),
@@ -466,7 +513,10 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
                                      2),
                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                               "p99": round(float(np.percentile(lat, 99)), 3),
-                              "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+                              "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3),
+                              "from": "scheduled arrival"},
+               "latency_from_submit_ms": {"p50": round(float(np.percentile(lat_sub, 50)), 3),
+                                          "p99": round(float(np.percentile(lat_sub, 99)), 3)},
                "mean_request_MB": round(float(sizes.mean()) / 1e6, 2),
                "max_inflight_bytes": stats["max_inflight_bytes"], "batches": stats["batches"],
                "mean_batch": round(stats["admitted"] / max(stats["batches"], 1), 2), "bit_exact": bit_exact,
@@ -476,6 +526,9 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
             f"submissions at most {out['producer_max_lag_ms']} ms behind their arrival times")
         return out
 
+    if single_rates:
+        # the bytes-weighted single-column reference of the pool (the 1 GiB columns' rates per codec)
+        ref = pool_bytes / sum(c.decoded_bytes / single_rates[c.codec] / 1e9 for c in pool.chunks)
     out = serve_once(load, n_requests, (seed or 5) + 1)
     others = {}
     for k, ld in enumerate(other_loads):
@@ -488,7 +541,15 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
                 "saturated": {k: sat[k] for k in ("value", "load", "offered_GBps", "latency_ms", "mean_batch",
                                                   "batches", "max_inflight_bytes", "bit_exact", "producer_max_lag_ms")},
                 "saturated_over_capacity": round(sat["value"] * 1e9 / cap_bps, 3),
+                "pool_stats": {codec: {"bytes_per_code": round(
+                    sum(c.decoded_bytes for c in pool.chunks if c.codec == codec) /
+                    max(1, sum(int(c.stats["n_codes"]) for c in pool.chunks if c.codec == codec)), 3)}
+                    for codec in ("fsst8", "onpair16")},
                 "other_loads": others})
+    if single_rates:
+        out["single_column_reference_GBps"] = round(ref / 1e9, 2)
+        out["saturated_over_single_column"] = round(sat["value"] * 1e9 / ref, 3)
+        out["capacity_over_single_column"] = round(cap_bps / ref, 3)
     return out
 
 
@@ -497,7 +558,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="fsst_logs", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fsst_logs_ngram", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--mode", type=int, default=1, help="0 single pass (look-back), 1 three phases (default)")
     ap.add_argument("--sb", type=int, default=0, help="strings per tile (0 = automatic)")
@@ -668,8 +729,9 @@ def main():
                    "n_strings": col.n_strings, "index_bits": 8 * col.code_off.dtype.itemsize,
                    "bytes_per_code": round(col.stats.get("bytes_per_code", 0.0), 3),
                    "escape_share": round(col.stats.get("escape_share", 0.0), 4),
+                   "table": WORKLOADS[args.workload].get("table"),
                    "mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid,
-                   "positions": "stored sidecar" if sidecar is not None else "look-back"},
+                   "positions": positions_label(args.mode, sidecar is not None)},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBPS, 4),
         "step_us": {"min": round(float(per.min()) * 1e6, 2), "p50": round(float(np.median(per)) * 1e6, 2),
                     "p99": round(float(np.percentile(per, 99)) * 1e6, 2)},
@@ -679,9 +741,18 @@ def main():
         "cpu_baseline": cpu,
         "kernel_source_sha": src_hash,
     }
-    if args.workload == "fsst_logs" and not args.no_extra:
-        # the batched and served workloads, short runs
-        rates = {"fsst8": value}
+    if args.workload == "fsst_logs_ngram" and not args.no_extra:
+        # the other columns, the small column's latency, the batched and served workloads (short runs)
+        rates = {}
+        try:
+            rates["fsst8"] = single_rate("fsst_logs", mode=args.mode)     # the batch's FSST-8 recipe
+            res["fsst_logs_GBps"] = round(rates["fsst8"], 2)
+        except Exception as e:
+            res["fsst_logs_GBps"] = {"error": f"{type(e).__name__}: {e}"}
+        try:
+            res["fsst_small"] = small_latency(mode=args.mode)
+        except Exception as e:
+            res["fsst_small"] = {"error": f"{type(e).__name__}: {e}"}
         try:
             rates["onpair16"] = single_rate("onpair_urls", mode=args.mode)
             res["onpair_urls_GBps"] = round(rates["onpair16"], 2)
@@ -690,7 +761,7 @@ def main():
         other = 1 - args.mode                           # the other way to the tile cursors
         key = "single_pass_GBps" if other == 0 else "three_phase_GBps"
         res[key] = {}
-        for wl in ("fsst_logs", "onpair_urls"):
+        for wl in ("fsst_logs_ngram", "fsst_logs", "onpair_urls"):
             try:
                 res[key][wl] = round(single_rate(wl, mode=other), 2)
             except Exception as e:
@@ -703,7 +774,8 @@ def main():
         # the batched and served legs first, on a fresh allocator (the legs after them hold large buffers)
         for key, fn in (("batch", lambda: run_batch(10, 2, None, check=not args.no_check, cpu=False,
                                                     single_rates=rates if len(rates) == 2 else None)),
-                        ("serve", lambda: run_serve(None, n_requests=5000, check=not args.no_check))):
+                        ("serve", lambda: run_serve(None, n_requests=5000, check=not args.no_check,
+                                                    single_rates=rates if len(rates) == 2 else None))):
             torch.cuda.empty_cache()
             try:
                 res[key] = fn()

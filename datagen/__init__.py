@@ -12,9 +12,13 @@ escape and OnPair-style 16-bit codes):
   table: 93 single printable bytes (2 of the 95 excluded by seed, which makes
   about 2% of bytes escapes) + 162 random printable symbols of length U[2, 8];
   greedy longest match; uint8 codes, int32 offsets.
-* ``fsst_logs``   - templated log lines, length log-normal (median 120 B,
-  sigma 0.5, clamped [32, 2048]); table = top-255 1..8-grams of a separate
-  1 MiB sample by count x length; uint8 codes, int64 offsets.
+* ``fsst_logs_ngram`` - templated log lines, length log-normal (median 120 B,
+  sigma 0.5, clamped [32, 2048]); table = the top-255 1..8-byte n-grams of a
+  separate 1 MiB sample, scored by count x length; greedy longest match
+  (bytes no symbol covers become escapes); uint8 codes, int64 offsets.
+* ``fsst_logs``   - the same log lines with a table trained by FSST-style
+  rounds on the same sample (parse, count symbols and adjacent symbol pairs
+  by bytes covered, keep the best 255): fewer escapes and longer codes.
 * ``onpair_urls`` - URL-like (70%) / identifier-like (30%) strings, length
   log-normal (median 30 B, sigma 0.5, clamped [4, 512]); OnPair-style
   dictionary trained on a separate 4 MiB sample (tau = 2, tokens <= 16 B, up
@@ -276,6 +280,19 @@ def fsst_logs(seed: int = 2, target_bytes: int = 1 << 30, sample_bytes: int = 1 
     return col
 
 
+def fsst_logs_ngram(seed: int = 2, target_bytes: int = 1 << 30, sample_bytes: int = 1 << 20,
+                    threads: int | None = None, keep_text: bool = True) -> Column:
+    """The log lines of fsst_logs (same seed, same text) with the table built
+    as the top-255 frequent 1..8-byte n-grams of the separate 1 MiB sample
+    (count x length), greedy longest-match encoded."""
+    st, so = log_lines(seed, sample_bytes, nchunk=4, threads=threads, stream_base=SAMPLE_STREAM)
+    db, dl = fsst_ngram_table(st, so, 255)
+    text, off = log_lines(seed, target_bytes, threads=threads)
+    codes, coff, esc = encode_fsst(db, dl, text, off, threads)
+    return Column("fsst_logs_ngram", "fsst8", codes, coff, db, dl, text if keep_text else None,
+                  off if keep_text else None, esc, _stats("fsst8", codes, coff, dl, esc, len(text)))
+
+
 def onpair_urls(seed: int = 3, target_bytes: int = 1 << 30, sample_bytes: int = 4 << 20,
                 threads: int | None = None, keep_text: bool = True, max_tokens: int = 65536) -> Column:
     st, so = url_strings(seed, sample_bytes, nchunk=16, threads=threads, stream_base=SAMPLE_STREAM)
@@ -375,8 +392,11 @@ def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 128, min_bytes:
     """The served workload: n_dicts dictionaries (half FSST-8 trained on log
     samples, half OnPair-16 trained on URL samples, each from its own seed) and
     a pool of request chunks with decoded sizes log-uniform in [min_bytes,
-    max_bytes], each of fresh text encoded with one of the dictionaries (chunk
-    i uses dictionary i mod n_dicts, so 128 chunks give 4 per dictionary)."""
+    max_bytes].  Chunk i uses dictionary k = i mod n_dicts (128 chunks give 4
+    per dictionary) and is fresh text of dictionary k's seed on a random
+    stream of its own: the generator draws its vocabularies from the seed, so a
+    chunk comes from the distribution its dictionary was trained on, as the
+    single columns pair their sample and their text."""
     rng = np.random.default_rng(seed)
     dicts = []
     for k in range(n_dicts):
@@ -392,12 +412,13 @@ def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 128, min_bytes:
     for i in range(n_chunks):
         k = i % n_dicts
         codec, db, dl = dicts[k]
-        cseed = seed * 100_003 + i
+        dseed = seed * 100_003 + 50_000 + k
+        sbase = (1 + i // n_dicts) << 20          # disjoint from the sample's streams and from each other
         if codec == "fsst8":
-            text, off = log_lines(cseed, int(sizes[i]), threads=threads)
+            text, off = log_lines(dseed, int(sizes[i]), threads=threads, stream_base=sbase)
             codes, coff, esc = encode_fsst(db, dl, text, off, threads)
         else:
-            text, off = url_strings(cseed, int(sizes[i]), threads=threads)
+            text, off = url_strings(dseed, int(sizes[i]), threads=threads, stream_base=sbase)
             codes, coff, esc = encode_onpair(db, dl, text, off, threads)
         chunks.append(Column("serve_chunk", codec, codes, coff, db, dl, text if keep_text else None,
                              off if keep_text else None, esc, _stats(codec, codes, coff, dl, esc, len(text))))
@@ -406,5 +427,6 @@ def serve_pool(seed: int = 5, n_dicts: int = 32, n_chunks: int = 128, min_bytes:
 
 
 def column_for(name: str, **kw) -> Column:
-    return {"fsst_small": fsst_small, "fsst_logs": fsst_logs, "onpair_urls": onpair_urls,
+    return {"fsst_small": fsst_small, "fsst_logs": fsst_logs, "fsst_logs_ngram": fsst_logs_ngram,
+            "onpair_urls": onpair_urls,
             "random_onpair": random_onpair, "onpair12_urls": onpair12_urls, "fsst12_logs": fsst12_logs}[name](**kw)

@@ -1,8 +1,10 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times (automatic tiling, resident grid, asynchronous status):
 
-- the 1 GiB FSST-8 log column, the 1 GiB OnPair-16 URL column and their 12-bit
-  packed counterparts (OnPair-12 URLs, FSST-12 logs): the whole
+- the 1 GiB FSST-8 log column (with the n-gram table and with the trained
+  table), the 1 GiB OnPair-16 URL column and their 12-bit packed counterparts
+  (OnPair-12 URLs, FSST-12 logs), in both ways to the tile positions (three
+  phases, which the benchmark times, and the single pass): the whole
   output must equal the generator's source text and offsets (decoding is
   lossless, so that is the expected result at any size), and sampled runs of
   strings across the column are checked against the oracle one run at a time;
@@ -47,8 +49,8 @@ def check_runs_against_oracle(col, out_off, out, rng, n_runs=40):
         assert np.array_equal(out[int(out_off[a]):int(out_off[b])], exp.out_bytes), (col.name, a, b)
 
 
-@pytest.mark.parametrize("workload,seed", [("fsst_logs", 2), ("onpair_urls", 3), ("onpair12_urls", 6),
-                                           ("fsst12_logs", 7)])
+@pytest.mark.parametrize("workload,seed", [("fsst_logs_ngram", 2), ("fsst_logs", 2), ("onpair_urls", 3),
+                                           ("onpair12_urls", 6), ("fsst12_logs", 7)])
 def test_full_column(datagen_mod, oracle_mod, workload, seed):
     import torch
     import paper_2609_15034_amd as fd
@@ -64,13 +66,20 @@ def test_full_column(datagen_mod, oracle_mod, workload, seed):
     out_off = torch.full((col.n_strings + 1,), -7, dtype=code_off.dtype, device=dev)
     ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings)
     status = torch.full((1,), -1, dtype=torch.int32, device=dev)
-    for _ in range(2):        # twice: the second run reuses the workspace as the benchmark does
-        assert fd.decode_into(d, codes, code_off, out_off, out, ws, status=status, async_=True) == fd.OK
-        torch.cuda.synchronize()
-        assert int(status.item()) == fd.OK
-    assert torch.equal(out, torch.from_numpy(col.text).to(dev))
-    assert torch.equal(out_off.to(torch.int64), torch.from_numpy(col.text_off).to(dev))
-    assert bool((buf[col.decoded_bytes:] == 0xA5).all()), "write past the output"
+    text = torch.from_numpy(col.text).to(dev)
+    text_off = torch.from_numpy(col.text_off).to(dev)
+    for mode in (0, 1):
+        tu = {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+        out.fill_(0x5A)
+        out_off.fill_(-7)
+        for _ in range(2):    # twice: the second run reuses the workspace as the benchmark does
+            assert fd.decode_into(d, codes, code_off, out_off, out, ws, status=status, async_=True,
+                                  tuning=tu) == fd.OK
+            torch.cuda.synchronize()
+            assert int(status.item()) == fd.OK, mode
+        assert torch.equal(out, text), mode
+        assert torch.equal(out_off.to(torch.int64), text_off), mode
+        assert bool((buf[col.decoded_bytes:] == 0xA5).all()), "write past the output"
     rng = np.random.default_rng(seed + 100)
     check_runs_against_oracle(col, out_off.cpu().numpy().astype(np.int64), out.cpu().numpy(), rng)
 
