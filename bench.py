@@ -202,7 +202,7 @@ def single_rate(workload: str, steps: int = 10, seed: int | None = None, mode: i
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
     out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
-    tu = {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    tu = {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
     ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tu)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     mean_s, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True,
@@ -226,7 +226,7 @@ def small_latency(runs: int = 200, mode: int = 1, seed: int | None = None) -> di
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
     out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
-    tu = {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    tu = {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
     ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tu)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     _, per = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True,
@@ -424,7 +424,7 @@ def run_serve(seed: int | None, n_requests: int = 5000, load: float = 0.7, budge
     tups = [(dicts[pool.chunk_dict[i]], inputs[i][0], inputs[i][1],
              torch.empty(c.n_strings + 1, dtype=inputs[i][1].dtype, device=dev),
              torch.empty(c.decoded_bytes, dtype=torch.uint8, device=dev)) for i, c in enumerate(pool.chunks)]
-    tu = {"mode": 0, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    tu = {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0}
     ws = torch.empty(fd.batch_workspace_size(tups, tu), dtype=torch.uint8, device=dev)
     cap_s, _ = _events_time(lambda: fd.batch_decode(tups, ws, tuning=tu, async_=True,
                                                     status=torch.zeros(len(tups) + 1, dtype=torch.int32,
@@ -561,7 +561,7 @@ def main():
     ap.add_argument("--workload", default="fsst_logs_ngram", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--mode", type=int, default=1, help="0 single pass (look-back), 1 three phases (default)")
-    ap.add_argument("--sb", type=int, default=0, help="strings per tile (0 = automatic)")
+    ap.add_argument("--tile-codes", type=int, default=0, help="codes per tile (0 = the largest)")
     ap.add_argument("--grid", type=int, default=0, help="workgroups (0 = all resident)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the output check")
@@ -622,7 +622,7 @@ def main():
     D = col.decoded_bytes
     out = torch.empty(D, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
-    tuning = {"mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid, "reserved": 0}
+    tuning = {"mode": args.mode, "tile_codes": args.tile_codes, "grid": args.grid, "reserved": 0}
     ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tuning)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     sidecar = None
@@ -730,7 +730,7 @@ def main():
                    "bytes_per_code": round(col.stats.get("bytes_per_code", 0.0), 3),
                    "escape_share": round(col.stats.get("escape_share", 0.0), 4),
                    "table": WORKLOADS[args.workload].get("table"),
-                   "mode": args.mode, "strings_per_tile": args.sb, "grid": args.grid,
+                   "mode": args.mode, "tile_codes": args.tile_codes, "grid": args.grid,
                    "positions": positions_label(args.mode, sidecar is not None)},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBPS, 4),
         "step_us": {"min": round(float(per.min()) * 1e6, 2), "p50": round(float(np.median(per)) * 1e6, 2),

@@ -190,23 +190,23 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                        expansion), reading the code stream twice (the
  *                        "sidecar regenerated at decode time" variant the
  *                        paper measures in its design overview).
- *   strings_per_tile  1..256 (FSST-8) or 1..1024 (OnPair); automatic = the
- *                     most strings whose codes, at the column's mean codes
- *                     per string plus a margin for their spread, fit one pass
- *                     (a pass is 8192 FSST-8 or 4096 OnPair codes; a tile
- *                     with more codes takes several passes, each recomputing
- *                     the lengths).  The margin is wider for mode 0, where a
- *                     tile of several passes delays every later tile, than
- *                     for mode 1 and the sidecar entry points.  The estimate uses n_codes / n_strings,
- *                     so a decode of a few strings out of a much larger code
- *                     buffer should pass the codes of its range (rebased
- *                     offsets) or set strings_per_tile.
+ *   tile_codes        codes per tile.  Tiles are fixed ranges of code
+ *                     positions (the paper's fixed-size batches of codes,
+ *                     design overview): tile t holds the codes at positions
+ *                     [t * tile_codes, (t + 1) * tile_codes) of the code
+ *                     buffer that lie inside the decode range, and strings
+ *                     cross tiles freely.  0 = the largest, 8176 for FSST-8
+ *                     and 4088 for OnPair-16 / OnPair-12 (a workgroup's pass
+ *                     of 8192 / 4096 codes less one 16-byte chunk, so that a
+ *                     tile of a buffer at any alignment is one pass); else a
+ *                     multiple of 16 (FSST-8) or 8 (OnPair) up to that.
+ *                     n_tiles = ceil(n_codes / tile_codes), at least 1.
  *   grid              workgroups to launch; automatic = all that can be
  *                     resident on the device (they pull tiles from a counter).
  * The decoded result does not depend on the tuning. */
 typedef struct fd_tuning {
     int32_t mode;
-    int32_t strings_per_tile;
+    int32_t tile_codes;
     int32_t grid;
     int32_t reserved;
 } fd_tuning;
@@ -229,22 +229,23 @@ fd_status fd_decode_ex(const fd_dict *dict, const void *codes, int64_t n_codes, 
  * fixed-size group of codes (its "sidecar", introduction and the design
  * section's paragraph on output placement), so that decoding needs no prefix
  * scan across groups; regenerating it at decode time costs 20-35% there.
- * Here a group is a tile of strings_per_tile consecutive strings, so the
- * sidecar of a column under a tiling is an int64 array of n_tiles + 1
- * entries (n_tiles = ceil(n_strings / strings_per_tile), 1 when n_strings is
- * 0):
- *     sidecar[k] = out_offsets[min(k * strings_per_tile, n_strings)],
- * the decoded position of tile k's first string, and sidecar[n_tiles] the
- * decoded total.  An encoder that has the source strings can fill it from
- * their offsets; fd_sidecar_build computes it on the device from the codes.
- * It is 8 bytes per tile (about 0.1% of the codes of the 1 GiB log column).
+ * Here a group is a tile (tile_codes consecutive code positions, see
+ * fd_tuning), so the sidecar of a column under a tiling is an int64 array of
+ * n_tiles + 1 entries (n_tiles = ceil(n_codes / tile_codes), at least 1):
+ *     sidecar[k] = the decoded bytes of the codes at positions
+ *                  [code_offsets[0], max(code_offsets[0], min(k * tile_codes,
+ *                  code_offsets[n_strings]))),
+ * the output position of tile k's first code (an FSST-8 escape adds no byte
+ * and its literal one), and sidecar[n_tiles] the decoded total.
+ * fd_sidecar_build computes it on the device from the codes.  It is 8 bytes
+ * per tile (about 0.1% of the codes of the 1 GiB log column).
  *
  * fd_sidecar_layout: the tiling of a column (tuning as for fd_decode_ex; its
  * mode must be 0) and the number of sidecar entries.  The sidecar is valid
- * only with that strings_per_tile: store it beside the sidecar and pass it to
- * the decode in tuning->strings_per_tile. */
+ * only with that tile_codes: store it beside the sidecar and pass it to the
+ * decode in tuning->tile_codes. */
 fd_status fd_sidecar_layout(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning *tuning,
-                            int32_t *strings_per_tile, int64_t *n_entries);
+                            int32_t *tile_codes, int64_t *n_entries);
 
 /* Compute the sidecar of a column on the device (a totals-only pass over the
  * codes and a scan of the tile totals), into the caller's device array
@@ -260,7 +261,7 @@ fd_status fd_sidecar_build(const fd_dict *dict, const void *codes, int64_t n_cod
 
 /* fd_decode_ex with the output positions taken from a sidecar (device,
  * n_entries int64, read only) instead of a scan: every tile starts at once.
- * tuning->strings_per_tile must be the sidecar's (0 = the automatic choice,
+ * tuning->tile_codes must be the sidecar's (0 = the automatic choice,
  * as in fd_sidecar_layout) and tuning->mode 0.  Each tile checks its entry
  * against the next (sidecar[k] + tile k's decoded total = sidecar[k + 1], and
  * sidecar[0] = 0); a tile that fails writes no byte, and the call reports

@@ -167,36 +167,89 @@ def decode(codec: str, codes, code_off, dict_bytes, dict_lens, index_bits: int |
     return Result(int(st), out_off, out[: min(t, cap)], t, int(err.value))
 
 
-def sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, strings_per_tile: int,
-            n_codes: int | None = None):
-    """The sidecar of a column: the output position stored for every batch of
-    the column so that a decoder can start every batch at once (introduction;
-    design section, placement of the output).  Reading: a batch is a tile of
-    ``strings_per_tile`` consecutive strings, so entry k is the decoded
-    position of string k * strings_per_tile, i.e. the sum of the decoded
-    lengths of the strings before it, for k < n_tiles = max(1, ceil(n_strings
-    / strings_per_tile)), and the last entry is the decoded total.  Returns
-    (status, int64 entries); the entries are None when the data has an error."""
-    r = decode(codec, codes, code_off, dict_bytes, dict_lens, index_bits=64, n_codes=n_codes)
-    if r.status != OK:
-        return r.status, None
-    n = len(code_off) - 1
-    sb = int(strings_per_tile)
-    if sb < 1:
-        raise ValueError("strings_per_tile must be positive")
-    n_tiles = max(1, -(-n // sb))
-    firsts = [min(k * sb, n) for k in range(n_tiles)] + [n]
-    return OK, r.out_off[firsts].astype(np.int64)
+def code_positions(codec: str, codes, code_off, dict_bytes, dict_lens, positions, n_codes: int | None = None,
+                   string_offsets=None):
+    """The output position of each code position p in ``positions`` (with
+    code_off[0] <= p <= code_off[n]): the bytes the codes at positions
+    [code_off[0], p) decode to.  It follows the decode definition (background
+    section: tokens concatenated in code order; the escape emits nothing and
+    the byte after it is one literal byte) string by string: p lies in the
+    string whose codes hold it, and its position is that string's output
+    offset plus what the string's codes before p emit, walked in order.  The
+    strings' output offsets come from decode(), or from ``string_offsets``
+    when given (a column's known string offsets, valid data only).
+    Returns (status, int64 positions); None when the data has an error."""
+    if codec == "onpair12":
+        packed = np.ascontiguousarray(codes, dtype=np.uint8)
+        n = (len(packed) * 8) // 12 if n_codes is None else int(n_codes)
+        codes, codec = unpack12_np(packed, n), "onpair16"
+    if string_offsets is None:
+        r = decode(codec, codes, code_off, dict_bytes, dict_lens, index_bits=64)
+        if r.status != OK:
+            return r.status, None
+        soff = r.out_off
+    else:
+        soff = _as_i64(string_offsets)
+    co = _as_i64(code_off)
+    dl = np.asarray(dict_lens, dtype=np.int64)
+    codes = np.asarray(codes)
+    a, b = int(co[0]), int(co[-1])
+    out = []
+    for p in (int(x) for x in positions):
+        if not a <= p <= b:
+            raise ValueError("position outside the decode range")
+        if p == b:
+            out.append(int(soff[-1]))
+            continue
+        i = int(np.searchsorted(co, p, side="right")) - 1    # the string holding code p
+        pos, j = int(soff[i]), int(co[i])
+        cl = codes[j:p].tolist()
+        j0 = j
+        while j < p:
+            c = cl[j - j0]
+            if codec == "fsst8" and c == 255:      # an escape: its literal follows
+                if j + 1 < p:
+                    pos += 1
+                    j += 2
+                else:
+                    j += 1
+            else:
+                pos += int(dl[c])
+                j += 1
+        out.append(pos)
+    return OK, np.array(out, np.int64)
 
 
-def decode_with_sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, stored, strings_per_tile: int,
+def sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, tile_codes: int, n_codes: int | None = None,
+            string_offsets=None):
+    """The sidecar of a column: the output position stored for every fixed-size
+    group of codes, so that a decoder can start every group at once
+    (introduction; design section, overview and placement of the output).  A
+    group is a tile of ``tile_codes`` code positions of the code buffer: entry
+    k is the output position of code position max(a, min(k T, b)) for
+    k < n_tiles = max(1, ceil(n_codes / T)) (n_codes: the buffer's codes), and
+    the last entry is the decoded total, where [a, b) = [code_off[0],
+    code_off[n]).  Returns (status, int64 entries); None on an error in the
+    data."""
+    T = int(tile_codes)
+    if T < 1:
+        raise ValueError("tile_codes must be positive")
+    nc = int(n_codes) if n_codes is not None else len(codes)
+    co = _as_i64(code_off)
+    a, b = int(co[0]), int(co[-1])
+    n_tiles = max(1, -(-nc // T))
+    pos = [max(a, min(k * T, b)) for k in range(n_tiles)] + [b]
+    return code_positions(codec, codes, code_off, dict_bytes, dict_lens, pos, n_codes, string_offsets)
+
+
+def decode_with_sidecar(codec: str, codes, code_off, dict_bytes, dict_lens, stored, tile_codes: int,
                         index_bits: int | None = None, out_capacity: int | None = None,
                         n_codes: int | None = None) -> Result:
     """Decode with stored output positions: the plain decode's result, except
     that stored positions other than the column's own sidecar give ESIDECAR,
     which ranks after the errors in the data and before EOVERFLOW and
     ECAPACITY (on ESIDECAR nothing of the output is defined)."""
-    st, own = sidecar(codec, codes, code_off, dict_bytes, dict_lens, strings_per_tile, n_codes)
+    st, own = sidecar(codec, codes, code_off, dict_bytes, dict_lens, tile_codes, n_codes)
     if st == OK:
         given = np.asarray(stored, dtype=np.int64)
         if len(given) != len(own):

@@ -56,8 +56,8 @@ class DecodeError(RuntimeError):
 
 
 class Tuning(ctypes.Structure):
-    """fd_tuning: mode (0 single pass / 1 three phases), strings_per_tile, grid."""
-    _fields_ = [("mode", ctypes.c_int32), ("strings_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
+    """fd_tuning: mode (0 single pass / 1 three phases), tile_codes (codes per tile, 0 = the largest), grid."""
+    _fields_ = [("mode", ctypes.c_int32), ("tile_codes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -312,7 +312,7 @@ def decode(d: Dict, codes, code_off, tuning=None, stream=None):
 # persisted output positions (sidecar)
 # --------------------------------------------------------------------------- #
 def sidecar_layout(codec, n_codes: int, n_strings: int, tuning=None):
-    """fd_sidecar_layout: (strings_per_tile, n_entries) of a column's sidecar."""
+    """fd_sidecar_layout: (tile_codes, n_entries) of a column's sidecar."""
     sb, n = ctypes.c_int32(0), ctypes.c_int64(0)
     tu = Tuning(**tuning) if isinstance(tuning, dict) else tuning
     st = lib().fd_sidecar_layout(_codec_id(codec), int(n_codes), int(n_strings),

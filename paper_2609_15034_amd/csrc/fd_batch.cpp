@@ -34,10 +34,10 @@ constexpr size_t kBOffStatus = 128;
 constexpr int kMaxGroups = 6;          // (codec, offset width) pairs
 constexpr int32_t kMaxCols = 65536;
 
-// Candidate tile sizes of the autotuner: fractions (percent) of the automatic
-// strings-per-tile of each column (smaller tiles: more tiles and more
-// parallel look-back, larger: fewer tiles and less overhead per byte).
-constexpr int kScales[] = {100, 70, 45};
+// Candidate tile sizes of the autotuner: fractions (percent) of the largest
+// tile (smaller tiles: more tiles for the small columns and more parallel
+// look-back, larger: fewer tiles and less overhead per byte).
+constexpr int kScales[] = {100, 50, 25};
 constexpr int kNumScales = 3;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -46,6 +46,7 @@ struct Group {
     int codec = 0, index_bits = 0;
     std::vector<int32_t> cols;   // column indices (caller order)
     int64_t total = 0;           // tiles
+    int64_t max_samples = 0;     // the largest coarse index sample count of its columns
     int grid = 0;
     size_t off_sum = 0;          // mode 1: tile totals, then cursors (total + 1 words)
     size_t off_gsum = 0;         // mode 1: block sums of their scan
@@ -53,8 +54,10 @@ struct Group {
 
 struct BatchPlan {
     int mode = 0;                         // 0: look-back per column, 1: three phases per group
-    std::vector<int64_t> sb, n_tiles;     // per column
+    std::vector<int64_t> tcodes, n_tiles; // per column
+    std::vector<int> g_shift;             // per column
     std::vector<size_t> off_state;        // per column: tile aggregates, then block states
+    std::vector<size_t> off_coarse;       // per column: its coarse string index
     std::vector<Group> groups;
     size_t states_end = 0;                // [0, states_end) is zeroed per call
     size_t off_errs = 0, off_table = 0, table_bytes = 0, bytes = 0;
@@ -83,38 +86,45 @@ bool column_ok(const fd_column& c) {
     return true;
 }
 
-// Plan of a batch for one tile-size choice: `sb_fixed` > 0 sets every column's
-// strings per tile, else `scale` percent of the automatic value.
-bool make_plan(const fd_column* cols, int32_t n, int64_t sb_fixed, int scale, int grid_req, int mode,
+// Plan of a batch for one tile-size choice: `tc_fixed` > 0 sets every
+// column's codes per tile, else `scale` percent of the largest tile (rounded
+// to whole chunks).
+bool make_plan(const fd_column* cols, int32_t n, int64_t tc_fixed, int scale, int grid_req, int mode,
                BatchPlan* pl) {
     pl->mode = mode;
-    pl->sb.assign(n, 0);
+    pl->tcodes.assign(n, 0);
     pl->n_tiles.assign(n, 0);
+    pl->g_shift.assign(n, 0);
     pl->off_state.assign(n, 0);
+    pl->off_coarse.assign(n, 0);
     pl->groups.assign(kMaxGroups, Group());
     size_t off = kBHdr;
     for (int32_t c = 0; c < n; c++) {
         const fd_column& col = cols[c];
         const fd_codec codec = col.dict->codec;
-        const int64_t sb_max = codec == FD_FSST8 ? kSbMaxFsst : kSbMax;
-        int64_t sb = sb_fixed;
-        if (sb > sb_max) return false;
-        if (sb == 0) {
-            // the look-back needs a wider margin against tiles of several passes
-            sb = auto_strings_per_tile(codec, col.n_codes, col.n_strings, mode == 1 ? 2.0 : 4.0) * scale / 100;
-            sb = std::max<int64_t>(1, std::min(sb, sb_max));
+        int64_t T = tc_fixed;
+        if (T == 0) {
+            const int64_t q = codes_per_chunk((int)codec);
+            T = std::max<int64_t>(q, tile_codes_max(codec) * scale / 100 / q * q);
         }
-        const int64_t tiles = col.n_strings == 0 ? 1 : (col.n_strings + sb - 1) / sb;
+        T = tile_codes_for(codec, T);
+        if (T < 0) return false;
+        const int64_t tiles = tiles_of(col.n_codes, T);
+        if (tiles > (int64_t)UINT32_MAX / 4) return false;
         const int64_t tiles_pad = (tiles + kBlk - 1) / kBlk * kBlk;
-        pl->sb[c] = sb;
+        pl->tcodes[c] = T;
         pl->n_tiles[c] = tiles;
+        pl->g_shift[c] = coarse_shift(col.n_codes, col.n_strings, T);
         pl->off_state[c] = off;
         if (mode == 0) off += (size_t)tiles_pad * 8 + (size_t)(tiles_pad / kBlk) * 8;
+        pl->off_coarse[c] = off;
+        off += (size_t)tiles * 8;
         Group& g = pl->groups[group_of((int)codec, col.index_bits)];
         g.codec = (int)codec;
         g.index_bits = col.index_bits;
         g.cols.push_back(c);
         g.total += tiles;
+        g.max_samples = std::max(g.max_samples, (col.n_strings + ((int64_t)1 << pl->g_shift[c]) - 1) >> pl->g_shift[c]);
     }
     // inside a group, columns of one dictionary run back to back: a workgroup
     // then keeps its LDS table, and the dictionary stays warm in L2
@@ -176,7 +186,9 @@ void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* 
             p.out = col.out_bytes;
             p.out_cap = col.out_capacity;
             p.n_tiles = pl.n_tiles[c];
-            p.sb = (int32_t)pl.sb[c];
+            p.tile_codes = pl.tcodes[c];
+            p.g_shift = pl.g_shift[c];
+            p.coarse = (int64_t*)(ws + pl.off_coarse[c]);
             p.err = (unsigned long long*)(ws + pl.off_errs) + c;
             p.counters = nullptr;
             if (pl.mode == 1) {
@@ -214,6 +226,8 @@ hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
         if (g.cols.empty()) continue;
         unsigned* ctr = (unsigned*)(ws + 8 * gi);
         const int32_t nc = (int32_t)g.cols.size();
+        e = launch_coarse_batch(g.index_bits, dp + k, nc, g.max_samples, st);
+        if (e != hipSuccess) return e;
         if (pl.mode == 1) {
             unsigned long long* sum = (unsigned long long*)(ws + g.off_sum);
             e = launch_tile_totals_batch(g.codec, g.index_bits, dp + k, ft, nc, g.total, sum, dev_cus(), st);
@@ -363,13 +377,13 @@ fd_status fd_batch_workspace_size(const fd_column* cols, int32_t n_cols, const f
     if (!bytes || n_cols < 0 || n_cols > kMaxCols || (n_cols > 0 && !cols)) return FD_EINVAL;
     for (int32_t c = 0; c < n_cols; c++)
         if (!column_ok(cols[c])) return FD_EINVAL;
-    if (tuning && ((tuning->mode != 0 && tuning->mode != 1) || tuning->strings_per_tile < 0 || tuning->grid < 0))
+    if (tuning && ((tuning->mode != 0 && tuning->mode != 1) || tuning->tile_codes < 0 || tuning->grid < 0))
         return FD_EINVAL;
     size_t need = kBHdr;
     for (int i = 0; i < (tuning ? 1 : 2 * kNumScales); i++) {
         BatchPlan pl;
         const int mode = tuning ? tuning->mode : i / kNumScales;
-        if (!make_plan(cols, n_cols, tuning ? tuning->strings_per_tile : 0, tuning ? 100 : kScales[i % kNumScales], 1,
+        if (!make_plan(cols, n_cols, tuning ? tuning->tile_codes : 0, tuning ? 100 : kScales[i % kNumScales], 1,
                        mode, &pl))
             return FD_EINVAL;
         need = std::max(need, pl.bytes);
@@ -385,7 +399,7 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
         if (!workspace || ((uintptr_t)workspace & 255)) return FD_EINVAL;
         if ((flags & FD_ASYNC) && !status) return FD_EINVAL;
         if (flags & ~(FD_ASYNC | FD_GRAPH)) return FD_EINVAL;
-        if (tuning && ((tuning->mode != 0 && tuning->mode != 1) || tuning->strings_per_tile < 0 || tuning->grid < 0))
+        if (tuning && ((tuning->mode != 0 && tuning->mode != 1) || tuning->tile_codes < 0 || tuning->grid < 0))
             return FD_EINVAL;
         for (int32_t c = 0; c < n_cols; c++)
             if (!column_ok(cols[c])) return FD_EINVAL;
@@ -401,7 +415,7 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
 
         std::lock_guard<std::mutex> lk(g_bmu);
         // the tile-size choice
-        int64_t sb_fixed = tuning ? tuning->strings_per_tile : 0;
+        int64_t sb_fixed = tuning ? tuning->tile_codes : 0;
         int grid = tuning ? tuning->grid : 0;
         int scale = 100, mode = tuning ? tuning->mode : 0;
         if (!tuning) {

@@ -19,23 +19,25 @@ int64_t codes_per_pass(fd_codec c) {
     return (int64_t)kWG * chunks_per_lane(codec) * codes_per_chunk(codec);
 }
 
-// Strings per tile: the largest count whose expected code count plus `sigmas`
-// standard deviations (per-string coefficient of variation taken as 0.6) fits
-// in one super-pass.  The look-back takes 4: a tile of two passes publishes its
-// total late and every later tile waits for it.  Paths without a look-back
-// (three phases, stored positions) take 2: such a tile then costs only itself,
-// and fuller tiles pay more (FSST-8 logs: 640 against 596 GB/s).
-int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings, double sigmas) {
-    const double cap = (double)codes_per_pass(codec) - 16.0;
-    const double m = n_strings ? (double)n_codes / (double)n_strings : 1.0;
-    const double mean = m < 1.0 ? 1.0 : m;
-    int64_t sb = 1;
-    for (int64_t lo = 1, hi = codec == FD_FSST8 ? kSbMaxFsst : kSbMax; lo <= hi;) {
-        const int64_t mid = (lo + hi) / 2;
-        const double need = mid * mean + sigmas * 0.6 * mean * __builtin_sqrt((double)mid);
-        if (need <= cap) { sb = mid; lo = mid + 1; } else { hi = mid - 1; }
-    }
-    return sb;
+int64_t tile_codes_max(fd_codec c) { return c == FD_FSST8 ? kTileMaxFsst : kTileMaxOnpair; }
+
+int64_t tile_codes_for(fd_codec c, int64_t requested) {
+    const int64_t mx = tile_codes_max(c), q = codes_per_chunk((int)c);
+    if (requested == 0) return mx;
+    if (requested < q || requested > mx || requested % q) return -1;
+    return requested;
+}
+
+int64_t tiles_of(int64_t n_codes, int64_t tile_codes) {
+    const int64_t t = (n_codes + tile_codes - 1) / tile_codes;
+    return t < 1 ? 1 : t;
+}
+
+int coarse_shift(int64_t n_codes, int64_t n_strings, int64_t tile_codes) {
+    const double spt = n_codes > 0 ? (double)tile_codes * (double)n_strings / (double)n_codes : 4096.0;
+    int sh = kCoarseShiftMin;
+    while (sh < kCoarseShiftMax && (double)((int64_t)2 << sh) <= spt / 2.0) sh++;
+    return sh;
 }
 
 namespace {
@@ -97,35 +99,35 @@ constexpr size_t kTokLenBytes = 65536;
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Plan {
-    int64_t sb;
+    int64_t T;          // codes per tile
     int64_t n_tiles;
     int64_t n_blocks;
-    size_t off_tiles;
-    size_t off_blocks;
-    size_t off_scan;   // three-phase mode: block sums of the cursor scan
-    size_t off_dict;   // OnPair: prepared dictionary for the one-shot entry point
+    int g_shift;        // coarse string index stride (log2)
+    size_t off_tiles;   // n_tiles + 1 tile words
+    size_t off_blocks;  // look-back block states
+    size_t off_coarse;  // coarse string index, one word per tile
+    size_t off_scan;    // three-phase mode: block sums of the cursor scan
+    size_t off_dict;    // OnPair: prepared dictionary for the one-shot entry point
     size_t bytes;
 };
 
-// The automatic tile margin of a decode: 2 standard deviations without a
-// look-back (three-phase mode, sidecar operations), else 4.
-double tile_sigmas(const fd_tuning* tu, bool sidecar) { return (sidecar || (tu && tu->mode == 1)) ? 2.0 : 4.0; }
-
-bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl,
-              double sigmas = 4.0) {
+bool plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tu, Plan* pl) {
     if (n_codes < 0 || n_strings < 0) return false;
     if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
-    const int64_t sb_max = codec == FD_FSST8 ? kSbMaxFsst : kSbMax;
-    int64_t sb = tu ? tu->strings_per_tile : 0;
-    if (sb < 0 || sb > sb_max) return false;
-    if (sb == 0) sb = auto_strings_per_tile(codec, n_codes, n_strings, sigmas);
-    pl->sb = sb;
-    pl->n_tiles = n_strings == 0 ? 1 : (n_strings + sb - 1) / sb;
+    const int64_t T = tile_codes_for(codec, tu ? tu->tile_codes : 0);
+    if (T < 0) return false;
+    pl->T = T;
+    pl->n_tiles = tiles_of(n_codes, T);
+    if (pl->n_tiles > (int64_t)UINT32_MAX / 2) return false;   // tile ids are 32-bit
     pl->n_blocks = (pl->n_tiles + kBlk - 1) / kBlk;
+    pl->g_shift = coarse_shift(n_codes, n_strings, T);
     pl->off_tiles = kHdr;
-    // n_tiles + 1 tile words: the three-phase scan leaves the decoded total in the last
+    // n_tiles + 1 tile words (the three-phase scan leaves the decoded total in
+    // the last), the block states and the coarse index, contiguous: one
+    // zeroing covers them
     pl->off_blocks = pl->off_tiles + (size_t)(pl->n_tiles + 1) * 8;
-    pl->off_scan = pl->off_blocks + (size_t)pl->n_blocks * 8;
+    pl->off_coarse = pl->off_blocks + (size_t)pl->n_blocks * 8;
+    pl->off_scan = pl->off_coarse + (size_t)pl->n_tiles * 8;
     pl->off_dict = align_up(pl->off_scan + (size_t)((pl->n_tiles + 1 + 1023) / 1024 + 1) * 8, 256);
     pl->bytes = pl->off_dict + (codec == FD_ONPAIR16 ? align_up(kTok16Bytes + kTokLenBytes, 256) : 0);
     return true;
@@ -150,10 +152,12 @@ bool take_plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n
     if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
     if (tu && tu->mode != 0) return false;
     tp->codec2 = codec == FD_ONPAIR12 ? FD_ONPAIR16 : codec;
-    // tile size from the column's mean codes per string (the rows are a sample of it)
+    // tiles over the compacted buffer of max_codes codes (the tiles past the
+    // selection's codes are skipped on the device); the coarse index stride
+    // from the column's mean codes per string (the rows are a sample of it)
+    if (!plan_for(tp->codec2, max_codes, n_rows, tu, &tp->dec)) return false;
     const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
-    const int64_t est = (int64_t)(mean * (double)n_rows) + 1;
-    if (!plan_for(tp->codec2, est, n_rows, tu, &tp->dec)) return false;
+    tp->dec.g_shift = coarse_shift((int64_t)(mean * (double)n_rows) + 1, n_rows, tp->dec.T);
     tp->nblk = n_rows > 0 ? (n_rows + 1023) / 1024 : 1;
     tp->off_bsum = tp->dec.off_dict;                                   // no dictionary repack here
     tp->off_noff = align_up(tp->off_bsum + (size_t)(tp->nblk + 1) * 8, 256);
@@ -221,8 +225,7 @@ fd_status run_decode(const Args& a) {
         if (a.n_dict > 0 && (!a.dict_lens || !a.dict_bytes)) return FD_EINVAL;
     }
     Plan pl;
-    if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl, tile_sigmas(a.tuning, a.sidecar_op != 0)))
-        return FD_EINVAL;
+    if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl)) return FD_EINVAL;
     if (a.ws_bytes < pl.bytes) return FD_EINVAL;
     if (a.sidecar_op && a.sidecar_n != pl.n_tiles + 1) return FD_EINVAL;   // another tiling's sidecar
 
@@ -237,7 +240,9 @@ fd_status run_decode(const Args& a) {
     p.out = a.out;
     p.out_cap = a.out_cap;
     p.n_tiles = pl.n_tiles;
-    p.sb = (int32_t)pl.sb;
+    p.tile_codes = pl.T;
+    p.g_shift = pl.g_shift;
+    p.coarse = (int64_t*)(ws + pl.off_coarse);
     p.err = (unsigned long long*)(ws + kOffErr);
     p.counters = (unsigned*)(ws + kOffCounters);
     p.tagg = (unsigned long long*)(ws + pl.off_tiles);
@@ -246,17 +251,16 @@ fd_status run_decode(const Args& a) {
     p.status2 = (int32_t*)(ws + kOffStatus);
 
     hipStream_t st = a.stream;
+    // tile words, block states and the coarse index are contiguous: one zeroing covers them
+    const int64_t nz = (int64_t)((pl.off_scan - pl.off_tiles) / 8);
+    if (launch_reset(p.err, p.counters, (unsigned long long*)(ws + pl.off_tiles), nz, st) != hipSuccess)
+        return hip_fail();
     if (a.sidecar_op == kSidecarBuild) {
-        // the totals pass writes entries [0, n_tiles); the scan then needs a zero in the last
+        // the totals pass writes the entries of the tiles with codes; the rest and the last start at zero
         p.tagg = (unsigned long long*)a.sidecar;
-        if (launch_reset(p.err, p.counters, p.tagg + pl.n_tiles, 1, st) != hipSuccess) return hip_fail();
+        if (launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + 1, st) != hipSuccess) return hip_fail();
     } else if (a.sidecar_op == kSidecarDecode) {
         p.tagg = (unsigned long long*)a.sidecar;     // read only (entries t and t + 1 per tile)
-        if (launch_reset(p.err, p.counters, nullptr, 0, st) != hipSuccess) return hip_fail();
-    } else {
-        // tile words and block states are contiguous: one zeroing covers both
-        if (launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + 1 + pl.n_blocks, st) != hipSuccess)
-            return hip_fail();
     }
 
     if (a.codec == FD_FSST8) {
@@ -288,6 +292,7 @@ fd_status run_decode(const Args& a) {
 
     const int codec = (int)a.codec;
     int grid_req = a.tuning ? a.tuning->grid : 0;
+    if (launch_coarse_one(a.index_bits, p, st) != hipSuccess) return hip_fail();
     if (a.sidecar_op == kSidecarBuild) {
         int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
         if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
@@ -348,7 +353,7 @@ fd_status fd_workspace_size_ex(fd_codec codec, int64_t n_codes, int64_t n_string
     if (!bytes) return FD_EINVAL;
     // a margin of 4 standard deviations gives the most tiles: enough for every path
     Plan pl;
-    if (!plan_for(codec, n_codes, n_strings, tuning, &pl, 4.0)) return FD_EINVAL;
+    if (!plan_for(codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
     *bytes = pl.bytes;
     return FD_OK;
 }
@@ -410,12 +415,12 @@ fd_status fd_decode_ex(const fd_dict* dict, const void* codes, int64_t n_codes, 
 }
 
 fd_status fd_sidecar_layout(fd_codec codec, int64_t n_codes, int64_t n_strings, const fd_tuning* tuning,
-                            int32_t* strings_per_tile, int64_t* n_entries) {
-    if (!strings_per_tile || !n_entries) return FD_EINVAL;
+                            int32_t* tile_codes, int64_t* n_entries) {
+    if (!tile_codes || !n_entries) return FD_EINVAL;
     if (tuning && tuning->mode != 0) return FD_EINVAL;
     Plan pl;
-    if (!plan_for(codec, n_codes, n_strings, tuning, &pl, tile_sigmas(tuning, true))) return FD_EINVAL;
-    *strings_per_tile = (int32_t)pl.sb;
+    if (!plan_for(codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
+    *tile_codes = (int32_t)pl.T;
     *n_entries = pl.n_tiles + 1;
     return FD_OK;
 }
@@ -493,7 +498,9 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     unsigned long long* err = (unsigned long long*)(ws + kOffErr);
     unsigned* counters = (unsigned*)(ws + kOffCounters);
     unsigned long long* tagg = (unsigned long long*)(ws + tp.dec.off_tiles);
-    if (launch_reset(err, counters, tagg, tp.dec.n_tiles + 1 + tp.dec.n_blocks, st) != hipSuccess) return hip_fail();
+    // tile words, block states and the coarse index of the compacted column
+    if (launch_reset(err, counters, tagg, (int64_t)((tp.dec.off_scan - tp.dec.off_tiles) / 8), st) != hipSuccess)
+        return hip_fail();
     // compaction: the selected strings' codes, whole, one after another
     uint8_t* ccodes = ws + tp.off_codes;
     void* coff = ws + tp.off_noff;
@@ -516,7 +523,9 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     p.out = out_bytes;
     p.out_cap = out_capacity;
     p.n_tiles = tp.dec.n_tiles;
-    p.sb = (int32_t)tp.dec.sb;
+    p.tile_codes = tp.dec.T;
+    p.g_shift = tp.dec.g_shift;
+    p.coarse = (int64_t*)(ws + tp.dec.off_coarse);
     p.err = err;
     p.counters = counters;
     p.tagg = tagg;
@@ -534,6 +543,7 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
         p.tok_len = dict->tok_len;
     }
     const int codec2 = (int)tp.codec2;
+    if (launch_coarse_one(index_bits, p, st) != hipSuccess) return hip_fail();
     int grid = (tuning && tuning->grid) ? tuning->grid : resident_grid(codec2, index_bits, kModeLookback);
     if ((int64_t)grid > tp.dec.n_tiles) grid = (int)tp.dec.n_tiles;
     if (launch_decode(codec2, index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();

@@ -16,8 +16,18 @@ constexpr int kWG = 256;            // threads per workgroup
 constexpr int kNWave = kWG / 64;    // waves per workgroup
 constexpr int kWinFsst = 16384;     // LDS staging window (bytes), FSST-8
 constexpr int kWinOnpair = 32768;   // LDS staging window (bytes), OnPair-16 (3 workgroups per CU by VGPRs: room for a pass)
-constexpr int kSbMax = 1024;        // strings per tile, at most (OnPair-16)
-constexpr int kSbMaxFsst = 256;     // strings per tile, at most (FSST-8)
+// A tile is a fixed range of code positions: tile t of a column holds the
+// codes at positions [t T, (t + 1) T) of its code buffer that lie inside the
+// decode range [code_offsets[0], code_offsets[n]).  T is a multiple of the
+// codes in a 16-byte chunk (16 FSST-8, 8 OnPair) and at most one pass of a
+// workgroup less one chunk (a tile whose buffer is not 16-byte aligned then
+// still fits one pass).
+constexpr int kTileMaxFsst = 8192 - 16;
+constexpr int kTileMaxOnpair = 4096 - 8;
+// Each tile finds its strings from a coarse index: sample j is code offset
+// j G, and coarse[t] is the last sample below the tile's first position.
+constexpr int kCoarseShiftMin = 6;     // G >= 64
+constexpr int kCoarseShiftMax = 10;    // G <= 1024
 constexpr int kBlkShift = 6;        // tiles per look-back block: 64
 constexpr int kBlk = 1 << kBlkShift;
 
@@ -61,8 +71,10 @@ struct DecodeParams {
     uint8_t* out;
     int64_t out_cap;
     // tiling
-    int64_t n_tiles;
-    int32_t sb;
+    int64_t n_tiles;               // ceil(n_codes / tile_codes), at least 1
+    int64_t tile_codes;            // T
+    int64_t* coarse;               // per tile: the coarse sample group its strings start in
+    int32_t g_shift;               // log2 of the coarse sample stride G
     // workspace
     unsigned long long* err;
     unsigned* counters;            // [0] tile counter, [1] finished workgroups
@@ -115,9 +127,20 @@ hipError_t launch_onpair_prepare(const uint8_t* bytes, const uint8_t* lens, int3
 
 // host runtime helpers shared by the single-column and batch entry points
 int64_t codes_per_pass(fd_codec c);
-// Automatic strings per tile; sigmas: the margin for the spread of codes per
-// string (4 for the look-back, 2 for paths without one).
-int64_t auto_strings_per_tile(fd_codec codec, int64_t n_codes, int64_t n_strings, double sigmas = 4.0);
+int64_t tile_codes_max(fd_codec c);
+// Tile size of a decode: 0 = the largest; else a multiple of the codes per
+// chunk in [that, the largest]; -1 when invalid.
+int64_t tile_codes_for(fd_codec c, int64_t requested);
+int64_t tiles_of(int64_t n_codes, int64_t tile_codes);
+// The coarse index stride of a column (log2): about half the strings of a
+// tile at the column's mean codes per string, within [2^6, 2^10].
+int coarse_shift(int64_t n_codes, int64_t n_strings, int64_t tile_codes);
+// The coarse index of a column into p.coarse (n_tiles words, zeroed before),
+// or of every column of a batch group (cols: the device table; max_samples:
+// the largest ceil(n_strings / G) of its columns).
+hipError_t launch_coarse_one(int index_bits, const DecodeParams& p, hipStream_t st);
+hipError_t launch_coarse_batch(int index_bits, const DecodeParams* cols, int32_t n_cols, int64_t max_samples,
+                               hipStream_t st);
 int dev_cus();   // compute units of the current device
 int resident_grid(int codec, int index_bits, int mode);
 int resident_grid_batch(int codec, int index_bits, int mode);

@@ -1,23 +1,26 @@
 // Decode kernels for FSST-8 and OnPair-16 string columns on gfx950 (CDNA4).
 //
-// Work decomposition.  A tile is a block of `sb` consecutive strings, so every
-// tile starts at a string boundary, where the FSST-8 escape state is "expect a
-// code" (an escape never crosses a string).  A workgroup (4 waves of 64 lanes)
+// Work decomposition.  A tile is a fixed range of T code positions (the
+// paper's fixed-size batches of codes, design overview): tile t holds the
+// codes at positions [t T, (t + 1) T) of the buffer that lie inside the decode
+// range [code_offsets[0], code_offsets[n]), so every tile but the last at each
+// end is full and strings may cross tiles.  A workgroup (4 waves of 64 lanes)
 // decodes one tile at a time and takes tiles from a global counter in
-// increasing order (the next tile id is requested while the current one is
-// decoded).  Inside a tile the code range is cut into 16-byte-aligned chunks
-// (16 FSST codes or 8 OnPair codes); lane l owns P consecutive chunks, so its
-// codes are contiguous in the stream and stay in registers from the length
-// scan to the emit.  A tile with more chunks than one such "super-pass" holds
-// is decoded in several super-passes (lengths are recomputed for the emit).
+// increasing order.  Inside a tile the code range is cut into 16-byte-aligned
+// chunks (16 FSST codes or 8 OnPair codes); lane l owns P consecutive chunks,
+// so its codes are contiguous in the stream and stay in registers from the
+// length scan to the emit.  T is at most one pass of the workgroup (256 lanes
+// x P chunks) less one chunk, so a tile is always one pass.
 //
-// Steps per super-pass (the stages of the paper's Algorithm 1, re-cut for
-// wave64 and LDS):
+// Steps per tile (the stages of the paper's Algorithm 1, re-cut for wave64
+// and LDS):
 //   load    - P 16-byte loads per lane (the input stage);
 //   parity  - FSST-8: a position is a literal iff the run of 255 bytes right
 //             before it has odd length; lanes classify their codes with a
 //             bit-parallel carry trick, and the run parity entering a lane
 //             comes from ballots over the wave and the waves of the workgroup;
+//             the parity entering the tile comes from the run of 255 bytes
+//             just before its first code;
 //   lengths - decoded length per code (token length, 0 for an escape, 1 for a
 //             literal), lane totals and per-code prefixes inside each chunk;
 //   scan    - workgroup exclusive scan of lane totals (WarpPrefixSum at
@@ -32,8 +35,10 @@
 //             writes exact lengths where the excess would leave its range;
 //   drain   - aligned 16-byte nontemporal stores, byte stores only for the
 //             head and tail of the range (the drain stage);
-//   offsets - Arrow offsets of the strings starting in the super-pass from the
-//             per-code prefixes kept in LDS.
+//   offsets - Arrow offsets of the strings starting in the tile, from the
+//             per-code prefixes kept in LDS; the tile finds its strings from a
+//             coarse index (every G-th code offset, built by k_coarse) and
+//             checks every code offset it reads.
 // All arithmetic is integer.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -178,6 +183,16 @@ __device__ __forceinline__ void classify_escapes(uint32_t F, uint32_t cin, uint3
     lit = (esc << 1) | cin;
 }
 
+// The escape parity entering a tile applies at its first code, bit f of the
+// first lane's mask (f = the codes of the first chunk before the tile, 0..15
+// when the code buffer is not 16-byte aligned).  For f > 0 it is placed as one
+// escape at bit f - 1 (an out-of-tile position, whose length and output are
+// masked anyway), so that the bit-parallel classification sees the run
+// parity right where the tile starts; the carry into bit 0 is then 0.
+__device__ __forceinline__ uint32_t tile_entry_mask(int64_t f, uint32_t cin) {
+    return (f > 0 && f < 32 && cin) ? (1u << (uint32_t)(f - 1)) : 0u;
+}
+
 // expand 4 bits into bit 7 of each byte of a dword
 // 4 bits -> bytes 0x01 / 0x00 (a 24-bit multiply places bit k at bit 8k)
 __device__ __forceinline__ uint32_t nib_to_bytes(uint32_t nib) { return ((nib & 0xfu) * 0x00204081u) & 0x01010101u; }
@@ -194,7 +209,6 @@ template <> struct Cfg<kFsst8> {
     static constexpr int P = 2;       // chunks per lane
     static constexpr int CPL = 32;    // codes per lane
     static constexpr int W = 8;       // bytes written per token (fixed-stride entry)
-    static constexpr int SB = kSbMaxFsst;
     static constexpr int WIN = kWinFsst;   // LDS staging window (bytes)
 };
 template <> struct Cfg<kOnpair16> {
@@ -203,7 +217,6 @@ template <> struct Cfg<kOnpair16> {
     static constexpr int P = 2;
     static constexpr int CPL = 16;
     static constexpr int W = 16;
-    static constexpr int SB = kSbMax;
     static constexpr int WIN = kWinOnpair;
 };
 // OnPair-12 (and FSST-12: the same decode with tokens of at most 8 bytes):
@@ -216,7 +229,6 @@ template <> struct Cfg<kOnpair12> {
     static constexpr int P = 2;
     static constexpr int CPL = 16;
     static constexpr int W = 16;
-    static constexpr int SB = kSbMax;
     static constexpr int WIN = kWinOnpair;
 };
 template <int CODEC> constexpr bool kPacked12 = CODEC == kOnpair12;
@@ -226,45 +238,52 @@ template <int CODEC> constexpr bool kIsOnpair = CODEC == kOnpair16 || CODEC == k
 __host__ __device__ __forceinline__ int64_t packed12_bytes(int64_t n) { return (n * 12 + 7) / 8; }
 
 template <int CODEC> struct SmemT {
-    static constexpr int P = Cfg<CODEC>::P, CPC = Cfg<CODEC>::CPC, SB = Cfg<CODEC>::SB;
+    static constexpr int P = Cfg<CODEC>::P, CPC = Cfg<CODEC>::CPC;
     uint8_t stage[Cfg<CODEC>::WIN + 16];  // staging window (+16: slack for the drain's 16-byte reads)
     uint8_t pre8[kWG * P * CPC];          // per code: prefix inside its chunk | escape bit
-    uint32_t lane_pre[kWG];               // per lane: exclusive prefix inside the super-pass
+    uint32_t lane_pre[kWG];               // per lane: exclusive prefix inside the tile
     uint16_t cbase[kWG * P];              // per chunk: prefix inside its lane
-    int64_t coff[SB + 1];                 // the current tile's code offsets
     uint64_t fsst_tab[CODEC == kFsst8 ? 256 : 1];
     uint8_t fsst_len[CODEC == kFsst8 ? 256 : 4];
     alignas(16) uint8_t len12[kPacked12<CODEC> ? 4096 : 16];   // 12-bit codes: the lengths of their 4,096 tokens
     uint32_t wsum[kNWave];
     uint32_t wlast[kNWave];               // total of each wave's last lane
     uint32_t wpar[kNWave];
-    int64_t nb[2];                        // first / last code offset of the next tile
+    int64_t hdr[2];                       // the column's decode range [code_offsets[0], code_offsets[n])
+    int64_t gix[2];                       // coarse groups of this tile and the next
+    int64_t cur2[2];                      // stored cursors of this tile and the next (expand mode)
+    int64_t emin;                         // offsets: the first code-offset index past the tile
+    uint32_t cin;                         // FSST-8: escape parity entering the tile
     int64_t cursor;
     uint32_t wbase[kMaxWin + 1];          // staging windows: first output byte of each
     uint32_t nwin;
     int32_t next_id;
 };
 
-// Geometry of a tile: its strings, code range and 16-byte chunks.
+// Geometry of a tile: its code range, the string starts it owns and its
+// 16-byte chunks.
 struct Geom {
-    int64_t i0;         // first string
-    int64_t a, b;       // code range [a, b) (clamped)
+    int64_t a, b;       // the tile's codes [a, b) inside the decode range (a <= b)
+    int64_t own_lo, own_hi;   // it writes the offsets of strings starting in [own_lo, own_hi)
     int64_t pos0;       // code position of byte 0 of chunk 0 (may be negative)
     int64_t nchunk;
     uintptr_t base;     // address of chunk 0
-    int ns;             // strings in the tile
-    int nsp;            // super-passes
 };
 
+// Tile t of a column whose decode range is [ca, cb) (clamped to the buffer,
+// so bad offsets cannot move a tile outside it; they are reported by the
+// offsets step).  The last tile also owns the strings that start at the end.
 template <int CODEC>
-__device__ __forceinline__ Geom make_geom(const DecodeParams& p, int64_t t, int64_t c_first, int64_t c_last) {
+__device__ __forceinline__ Geom make_geom(const DecodeParams& p, int64_t t, int64_t ca, int64_t cb) {
     using C = Cfg<CODEC>;
     Geom g;
-    g.i0 = t * (int64_t)p.sb;
-    const int64_t i1 = min(g.i0 + (int64_t)p.sb, p.n_strings);
-    g.ns = (int)(i1 - g.i0);
-    g.a = min(max(c_first, (int64_t)0), p.n_codes);
-    g.b = min(max(c_last, g.a), p.n_codes);
+    const int64_t T = p.tile_codes;
+    ca = min(max(ca, (int64_t)0), p.n_codes);
+    cb = min(max(cb, ca), p.n_codes);
+    g.own_lo = t * T;
+    g.own_hi = (t + 1 >= p.n_tiles) ? INT64_MAX : (t + 1) * T;
+    g.a = min(max(g.own_lo, ca), cb);
+    g.b = min(max((t + 1) * T, g.a), cb);
     const uintptr_t lo = (uintptr_t)p.codes;
     if constexpr (kPacked12<CODEC>) {
         // chunks are groups of 8 codes (12 bytes) from the start of the stream
@@ -276,44 +295,52 @@ __device__ __forceinline__ Geom make_geom(const DecodeParams& p, int64_t t, int6
         g.nchunk = (g.b > g.a) ? (int64_t)((lo + (uintptr_t)g.b * C::CB - g.base + 15) >> 4) : 0;
         g.pos0 = ((int64_t)g.base - (int64_t)lo) / C::CB;
     }
-    g.nsp = (int)((g.nchunk + (int64_t)kWG * C::P - 1) / ((int64_t)kWG * C::P));
     return g;
 }
 
-// A thread's share of a tile's code offsets: indices tid + kWG * r.
-template <int CODEC, typename IDX> struct CoffRegs {
-    static constexpr int R = (Cfg<CODEC>::SB + 1 + kWG - 1) / kWG;
-    IDX v[R];
-};
-
-template <int CODEC, typename IDX>
-__device__ __forceinline__ void coff_load(const DecodeParams& p, int64_t t, CoffRegs<CODEC, IDX>& cr) {
-    const int64_t i0 = t * (int64_t)p.sb;
-    const int ns = (int)(min(i0 + (int64_t)p.sb, p.n_strings) - i0);
-    const IDX* src = (const IDX*)p.code_off;
-#pragma unroll
-    for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
-        const int j = (int)threadIdx.x + kWG * r;
-        cr.v[r] = (j <= ns) ? src[i0 + j] : (IDX)0;
-    }
+// The last tile with work: the one that holds the end of the decode range
+// (it owns the strings that start there).  The tiles after it have no codes
+// and no strings.
+__device__ __forceinline__ int64_t last_tile(const DecodeParams& p, int64_t ca, int64_t cb) {
+    ca = min(max(ca, (int64_t)0), p.n_codes);
+    cb = min(max(cb, ca), p.n_codes);
+    return min(cb / p.tile_codes, p.n_tiles - 1);
 }
 
-// Broadcast the first and last code offset of tile t from the registers that
-// hold them (one barrier) and return the tile's geometry.
-template <int CODEC, typename S, typename IDX>
-__device__ __forceinline__ Geom geom_from_regs(S& s, const DecodeParams& p, int64_t t,
-                                               const CoffRegs<CODEC, IDX>& cr) {
-    const int64_t i0 = t * (int64_t)p.sb;
-    const int ns = (int)(min(i0 + (int64_t)p.sb, p.n_strings) - i0);
-#pragma unroll
-    for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
-        const int j = (int)threadIdx.x + kWG * r;
-        if (j == 0) s.nb[0] = (int64_t)cr.v[r];
-        if (j == ns) s.nb[1] = (int64_t)cr.v[r];
+// The first tile with work: the one that holds the start of the decode range.
+// The tiles before it have no codes and no strings.
+__device__ __forceinline__ int64_t first_tile(const DecodeParams& p, int64_t ca, int64_t cb) {
+    ca = min(max(ca, (int64_t)0), p.n_codes);
+    return min(ca / p.tile_codes, last_tile(p, ca, cb));
+}
+
+// The column's decode range, read once per column (two uniform loads).
+template <typename IDX>
+__device__ __forceinline__ void column_range(const DecodeParams& p, int64_t& ca, int64_t& cb) {
+    const IDX* co = (const IDX*)p.code_off;
+    ca = (int64_t)co[0];
+    cb = (int64_t)co[p.n_strings];
+}
+
+// FSST-8: the escape parity entering code position a, i.e. the parity of the
+// run of 255 bytes right before a, counted back to the previous other byte or
+// to the start of the decode range ca (one wave; a loop step per 64 bytes of
+// run).  In valid data no string ends inside an escape, so this stream-level
+// parity is the one the string's own decode has.
+__device__ __forceinline__ uint32_t fsst_carry_in(const uint8_t* codes, int64_t ca, int64_t a) {
+    const int64_t lane = (int64_t)lane_id();
+    int64_t run = 0;
+    for (int64_t q0 = a - 1; q0 >= ca; q0 -= 64) {
+        const int64_t q = q0 - lane;
+        const bool stop = q < ca || codes[q] != 0xFF;
+        const uint64_t m = __ballot(stop);
+        if (m) {
+            run += (int64_t)__ffsll((unsigned long long)m) - 1;
+            break;
+        }
+        run += 64;
     }
-    __syncthreads();
-    const int64_t c0 = uniform64(s.nb[0]), c1 = uniform64(s.nb[1]);
-    return make_geom<CODEC>(p, t, c0, c1);
+    return (uint32_t)(run & 1);
 }
 
 // Issue the loads of one super-pass's chunks (P per lane).  Chunks that only
@@ -571,6 +598,9 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
                 F |= nib << (c * 16 + q * 4);
             }
         F &= L.valid;
+        // the parity entering the tile, at its first code
+        if (tid == 0) F |= tile_entry_mask(g.a - q0, carry);
+        if (g.a > g.pos0) carry = 0;
         const bool all_ff = (F == 0xffffffffu);
         const uint32_t trail = __clz(~F);                       // 255s at the top of the lane
         const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
@@ -860,41 +890,83 @@ __device__ __forceinline__ void drain(S& s, const DecodeParams& p, int64_t O, in
     }
 }
 
-// Arrow offsets of the strings of the tile that start in super-pass sp (output
-// position O), and the FSST-8 dangling-escape check of the strings that end in
-// it.
-template <int CODEC, typename IDX, typename S>
-__device__ __forceinline__ void offsets(S& s, const DecodeParams& p, const Geom& g, int sp, int64_t O) {
+// Decoded bytes of the tile's codes before code position x (a <= x <= b).
+template <int CODEC, typename S>
+__device__ __forceinline__ uint32_t local_prefix(S& s, const Geom& g, int64_t x, uint32_t total) {
     using C = Cfg<CODEC>;
-    constexpr int P = C::P, CPC = C::CPC, SPC = kWG * C::P;
-    const int64_t k_lo = (int64_t)sp * SPC, k_hi = k_lo + SPC;
-    for (int j = threadIdx.x; j < g.ns; j += kWG) {
-        const int64_t st = min(max(s.coff[j], g.a), g.b);
-        if (st < g.b) {
-            const int64_t k = (int64_t)((uint64_t)(st - g.pos0) / CPC);
-            if (k >= k_lo && k < k_hi) {
-                const int kk = (int)(k - k_lo);
-                const int jj = (int)(st - (g.pos0 + k * CPC));
-                uint32_t e = s.pre8[kk * CPC + jj];
-                if constexpr (CODEC == kFsst8) e &= 0x7fu;
-                const int64_t val = O + (int64_t)s.lane_pre[kk / P] + (int64_t)s.cbase[kk] + (int64_t)e;
-                ((IDX*)p.out_off)[g.i0 + j] = (IDX)val;
-            }
+    if (x >= g.b) return total;
+    const int64_t r = x - g.pos0;
+    const int k = (int)(r / C::CPC), jj = (int)(r - (int64_t)k * C::CPC);
+    uint32_t e = s.pre8[k * C::CPC + jj];
+    if constexpr (CODEC == kFsst8) e &= 0x7fu;
+    return s.lane_pre[k / C::P] + (uint32_t)s.cbase[k] + e;
+}
+
+// Arrow offsets of the strings starting in the tile (output position O, total
+// decoded bytes `total`; OUT = false: no output, the checks only), the FSST-8
+// dangling-escape check of the strings that end in it, and the checks of
+// every code offset it reads.
+//
+// The tile reads the code offsets from index G gcur on (gcur: its coarse
+// group, so code_offsets[G gcur] is below its first position) in steps of one
+// per thread, until the first index e whose offset is at or past own_hi.  On
+// valid offsets its first string comes at most G entries after G gcur, and e
+// is the next tile's first string, which lies within G entries after the next
+// tile's start G gnext: both are checked, so that the ranges the tiles read
+// meet end to end and every pair of adjacent offsets is compared by some
+// tile (a decreasing pair anywhere is found, whatever the coarse index holds).
+template <int CODEC, typename IDX, bool OUT, typename S>
+__device__ __forceinline__ void tile_offsets(S& s, const DecodeParams& p, const Geom& g, int64_t t, int64_t O,
+                                             uint32_t total, uint32_t cin, int64_t ca, int64_t gcur, int64_t gnext) {
+    const IDX* co = (const IDX*)p.code_off;
+    IDX* oo = (IDX*)p.out_off;
+    const int64_t n = p.n_strings;
+    const int64_t G = (int64_t)1 << p.g_shift;
+    const int64_t S0 = min(max(gcur, (int64_t)0) << p.g_shift, n);
+    bool bad = false, found = false;
+    int64_t e = INT64_MAX;
+    for (int64_t base = S0; base <= n; base += kWG) {
+        const int64_t i = base + (int64_t)threadIdx.x;
+        const bool in = i <= n;
+        int64_t v = 0;
+        if (in) {
+            v = (int64_t)co[i];
+            if (i == 0) bad |= v < 0;
+            else bad |= v < (int64_t)co[i - 1];
+            if (i == n) bad |= v > p.n_codes;
         }
-        if constexpr (CODEC == kFsst8) {
-            const int64_t en = min(max(s.coff[j + 1], g.a), g.b);
-            if (en > st) {
-                const int64_t last = en - 1;
-                const int64_t k = (int64_t)((uint64_t)(last - g.pos0) / CPC);
-                if (k >= k_lo && k < k_hi) {
-                    const int kk = (int)(k - k_lo);
-                    const int jj = (int)(last - (g.pos0 + k * CPC));
-                    if (s.pre8[kk * CPC + jj] & 0x80u)
-                        atomicMin(p.err, (unsigned long long)data_error_key(last, FD_EESCAPE));
+        const bool past = in && v >= g.own_hi;
+        if (in && !past && v >= g.own_lo) {
+            const int64_t x = min(max(v, g.a), g.b);
+            if constexpr (OUT) oo[i] = (IDX)(O + (int64_t)local_prefix<CODEC>(s, g, x, total));
+            if constexpr (CODEC == kFsst8) {
+                // the string ending at v ends with an escape iff v is a literal position
+                if (v > ca && x == v) {
+                    const bool esc = (x == g.a) ? (cin != 0)
+                                                : ((s.pre8[(int)(x - 1 - g.pos0)] & 0x80u) != 0u);
+                    if (esc) atomicMin(p.err, (unsigned long long)data_error_key(x - 1, FD_EESCAPE));
                 }
             }
         }
+        if (past) atomicMin((unsigned long long*)&s.emin, (unsigned long long)i);
+        const bool any_past = __syncthreads_or(past);
+        found = found || __syncthreads_or(in && v >= g.own_lo);
+        if (any_past) break;
+        // on valid offsets the tile's first string comes by index S0 + G (or
+        // there is none: then the column ends before the tile, and S0 = n)
+        const int64_t last = base + kWG - 1;
+        if (!found && last >= S0 + G && last < n) {
+            bad = true;
+            break;
+        }
     }
+    e = s.emin;
+    if (threadIdx.x == 0 && t + 1 < p.n_tiles) {
+        const int64_t S1 = min(max(gnext, (int64_t)0) << p.g_shift, n);
+        if (e == INT64_MAX) e = n + 1;
+        if (e < S1 || e > S1 + G) bad = true;
+    }
+    if (bad) record_error(p.err, kRankOffsets, FD_EOFFSETS);
 }
 
 // --------------------------------------------------------------------------
@@ -1057,18 +1129,6 @@ template <int CODEC> constexpr int kMinWaves = CODEC == kFsst8 ? 4 : 3;
 // own block, loses to the extra loads).
 template <int CODEC> constexpr bool kPrevTiles = CODEC == kFsst8;
 
-// Whether the next tile's id is requested before the look-back completes and
-// its offsets are loaded before the drain (FSST-8), or the id once the cursor
-// is known and the offsets after the drain (OnPair-16, whose look-back waits
-// longer and varies more: requesting earlier lets tiles start out of order).
-template <int CODEC> constexpr bool kEarlyNext = CODEC == kFsst8;
-
-// The tile counter's top bit: set by a workgroup that meets a tile of several
-// passes.  Such a tile publishes its total late, and with early requests the
-// starts of the tiles after it drift out of order (measured: a convoy), so
-// every workgroup that sees the bit in a returned id requests late from then on.
-constexpr uint32_t kLateBit = 0x80000000u;
-
 // --------------------------------------------------------------------------
 // where a launch's tiles come from: one column, or a batch of columns whose
 // tiles are numbered consecutively (column c owns ids first_tile[c] ..
@@ -1118,257 +1178,169 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     const int64_t n_all = src.n_tiles();
     unsigned* const ctr = src.counter();
 
-    // ---- prologue: the first tile of this workgroup ----
-    // A workgroup requests its next tile only as the current tile's look-back
-    // completes, and loads its offsets during the current tile's drain: tiles
-    // then start in about the order of their ids, so a tile's look-back finds
-    // its predecessors' totals already published (requesting tiles further
-    // ahead spreads the start of consecutive tiles over a whole tile's time,
-    // and the look-back waits for the latest of them).
-    if (tid == 0) s.nb[0] = (int64_t)atomicAdd(ctr, 1u);
+    if (tid == 0) s.next_id = (int32_t)atomicAdd(ctr, 1u);
     __syncthreads();
-    const uint32_t raw0 = (uint32_t)uniform64(s.nb[0]);
-    int64_t v = (int64_t)(raw0 & ~kLateBit);                 // global tile id
-    bool late = (raw0 & kLateBit) != 0;                      // request late from now on
-    __syncthreads();
-    int col = 0, table_col = -1;
-    const void* table_src = nullptr;      // the prepared table in LDS (batches)
-    if (v < n_all) col = src.column(v, 0);
-    int64_t t = v - src.first(col);                           // tile inside its column
-    CoffRegs<CODEC, IDX> cr;
-    Geom g{};
-    uint32_t wc[P][4];
-    if (v < n_all) {
-        const DecodeParams& p = src.params(col);
-        coff_load<CODEC, IDX>(p, t, cr);
-        g = geom_from_regs<CODEC>(s, p, t, cr);
-        codes_load<CODEC>(p, g, 0, wc);
+    int64_t v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+    int col = -1;
+    const void* table_src = nullptr;      // the table in LDS (FSST-8 symbols, 12-bit lengths)
+    int64_t ca = 0, cb = 0;               // the column's decode range
+    if constexpr (CODEC == kFsst8 && !SRC::kBatch) {
+        fsst_build_table(s, src.params(0));
+        table_src = (const void*)1;
     }
-
-    if constexpr (CODEC == kFsst8 && !SRC::kBatch) fsst_build_table(s, src.params(0));
-    if constexpr (kPacked12<CODEC> && !SRC::kBatch) len12_load(s, src.params(0));
+    if constexpr (kPacked12<CODEC> && !SRC::kBatch) {
+        len12_load(s, src.params(0));
+        table_src = (const void*)1;
+    }
     while (v < n_all) {
-        const DecodeParams& p = src.params(col);
-        if constexpr (CODEC == kFsst8 && SRC::kBatch) {
-            // a column of the batch with another table (columns of one
-            // prepared dictionary share it)
-            if (p.fsst_tab ? (const void*)p.fsst_tab != table_src : col != table_col) {
-                fsst_build_table(s, p);
-                table_col = col;
-                table_src = p.fsst_tab;
+        const int c = src.column(v, col < 0 ? 0 : col);
+        const DecodeParams& p = src.params(c);
+        if (c != col) {
+            if constexpr (SRC::kBatch) {
+                // a column of another dictionary: its table (columns of one
+                // prepared dictionary share it)
+                if constexpr (CODEC == kFsst8) {
+                    if (p.fsst_tab ? (const void*)p.fsst_tab != table_src : true) {
+                        fsst_build_table(s, p);
+                        table_src = p.fsst_tab;
+                    }
+                }
+                if constexpr (kPacked12<CODEC>) {
+                    if ((const void*)p.tok_len != table_src) {
+                        len12_load(s, p);
+                        table_src = p.tok_len;
+                    }
+                }
             }
+            col = c;
+            int64_t x0 = 0, x1 = 0;
+            if (tid == 0) column_range<IDX>(p, x0, x1);
+            if (tid == 0) { s.hdr[0] = x0; s.hdr[1] = x1; }
+            __syncthreads();
+            ca = uniform64(s.hdr[0]);
+            cb = uniform64(s.hdr[1]);
         }
-        if constexpr (kPacked12<CODEC> && SRC::kBatch) {
-            if ((const void*)p.tok_len != table_src) {    // a column of another dictionary
-                len12_load(s, p);
-                table_src = p.tok_len;
+        const int64_t t = v - src.first(col);
+        const bool after = t > last_tile(p, ca, cb);
+        if (after || t < first_tile(p, ca, cb)) {
+            // a tile outside the decode range: no codes, no strings.  Past the
+            // tile that holds the range's end, no later tile of the column looks
+            // at it; before the one holding its start, the look-back of the tiles
+            // after it reads it as a total of zero
+            if (!SRC::kBatch && after) break;
+            if (tid == 0) {
+                if constexpr (MODE == kModeLookback) {
+                    if (!after) {
+                        lb_publish(&p.tagg[t], kFlagAgg);
+                        if ((t & (kBlk - 1)) == kBlk - 1) lb_publish(&p.bstate[t >> kBlkShift], kFlagIncl);
+                    }
+                }
+                s.next_id = (int32_t)atomicAdd(ctr, 1u);
             }
+            __syncthreads();
+            v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+            __syncthreads();
+            continue;
         }
+        const Geom g = make_geom<CODEC>(p, t, ca, cb);
         // OnPair-16 gathers go through range-checked buffer loads (FSST-8 keeps its table in LDS)
         const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
             kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
         const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
             kIsOnpair<CODEC> ? (const void*)p.tok16 : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u * 16u : 0u);
-        // requests for the next tile: early unless a tile of several passes was seen
-        if (kEarlyNext<CODEC> && g.nsp > 1 && tid == 0 && !late) atomicOr(ctr, kLateBit);
-        const bool early = kEarlyNext<CODEC> && !late;
-        // (A) the tile's code offsets into LDS, validation
-        uint32_t nid = 0;               // the next tile's id (requested as the look-back completes)
-        int64_t cur_reg = 0, nxt_reg = 0;
-#pragma unroll
-        for (int r = 0; r < CoffRegs<CODEC, IDX>::R; r++) {
-            const int j = (int)tid + kWG * r;
-            if (j <= g.ns) s.coff[j] = (int64_t)cr.v[r];
+
+        Lane<CODEC> L;
+        codes_load<CODEC>(p, g, 0, L.w);
+        if (tid == 0) {
+            s.gix[0] = p.coarse[t];
+            s.gix[1] = (t + 1 < p.n_tiles) ? p.coarse[t + 1] : 0;
+            s.emin = INT64_MAX;
+            if constexpr (MODE == kModeExpand) {
+                s.cur2[0] = (int64_t)p.tagg[t];
+                s.cur2[1] = (int64_t)p.tagg[t + 1];
+            }
         }
-        if constexpr (MODE == kModeExpand) {
-            if (tid == 0) {
-                cur_reg = (int64_t)p.tagg[t];
-                nxt_reg = (int64_t)p.tagg[t + 1];
-                if constexpr (SRC::kBatch) {
-                    // a batch group's cursors are scanned over all its columns:
-                    // relative to the column's first tile
-                    const int64_t base = (int64_t)p.tagg[0];
-                    cur_reg -= base;
-                    nxt_reg -= base;
-                }
+        if constexpr (CODEC == kFsst8) {
+            if (wv == 0) {
+                const uint32_t ci = fsst_carry_in(p.codes, min(max(ca, (int64_t)0), p.n_codes), g.a);
+                if (tid == 0) s.cin = ci;
             }
         }
         __syncthreads();
-        {
-            bool bad = false;
-            for (int j = tid; j < g.ns; j += kWG) bad |= s.coff[j + 1] < s.coff[j];
-            if (tid == 0) {
-                if (t == 0 && s.coff[0] < 0) bad = true;
-                if (g.i0 + g.ns == p.n_strings && s.coff[g.ns] > p.n_codes) bad = true;
-            }
-            if (bad) record_error(p.err, kRankOffsets, FD_EOFFSETS);
-        }
-
-        // One super-pass (the common case): lengths, look-back issued, window 0
-        // assembled, next tile prefetched, look-back completed, drain, offsets.
-        // Several super-passes: the lengths of all of them first (tile total,
-        // blocking look-back), then each super-pass again with its emit.
-        Lane<CODEC> L;
-        int64_t nv = n_all, nt = 0;     // the next tile (known from the cursor barrier on)
-        int ncol = col;
         uint32_t carry = 0;
-        int64_t cursor = 0;
-        uint64_t tile_total = 0, sp_base = 0;
-        const int nsp = g.nsp;
-        const int iters = nsp <= 1 ? 1 : 2 * nsp;
-        for (int it = 0; it < iters; it++) {
-            const bool counting = nsp > 1 && it < nsp;
-            const int sp = nsp <= 1 ? 0 : (counting ? it : it - nsp);
-            if (nsp > 1 && it == nsp) carry = 0;
-            if (sp == 0) {
-#pragma unroll
-                for (int c = 0; c < P; c++)
-#pragma unroll
-                    for (int i = 0; i < 4; i++) L.w[c][i] = wc[c][i];
-            } else {
-                codes_load<CODEC>(p, g, sp, L.w);
-            }
-            uint32_t tsp = 0;
-            if (nsp >= 1) tsp = lengths<CODEC>(s, p, g, sp, L, carry, !counting, r_len, r_tok);
-            if (counting) {
-                tile_total += tsp;
-                if (it == nsp - 1) {
-                    if (early && tid == 0) nid = atomicAdd(ctr, 1u);
-                    if constexpr (MODE == kModeTotals) {
-                        if (tid == 0) p.tagg[t] = tile_total;
-                    } else if constexpr (MODE == kModeLookback) {
-                        if (wv == 0) {
-                            LookBack lb;
-                            lookback_issue<kPrevTiles<CODEC>>(p, t, tile_total, lb);
-                            const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tile_total, lb);
-                            if (tid == 0) s.cursor = (int64_t)ex;
-                        }
-                    } else {
-                        if (tid == 0) s.cursor = checked_cursor(p, t, cur_reg, nxt_reg, tile_total);
-                    }
-                    if (early && tid == 0) s.next_id = (int32_t)nid;
-                    __syncthreads();
-                    cursor = uniform64(s.cursor);
-                    if (early) {
-                        const uint32_t raw = uniform32((uint32_t)s.next_id);
-                        nv = (int64_t)(raw & ~kLateBit);
-                        late = late || (raw & kLateBit) != 0;
-                        if (nv < n_all) {
-                            ncol = src.column(nv, col);
-                            nt = nv - src.first(ncol);
-                            coff_load<CODEC, IDX>(src.params(ncol), nt, cr);
-                        }
-                    } else {
-                        if (tid == 0) nid = atomicAdd(ctr, 1u);
-                    }
-                }
-                continue;
-            }
-            const bool single = nsp <= 1;
-            LookBack lb{};
-            U128 head{0, 0};            // the lane's first 16 output bytes in the window being assembled
-            if (single) {
-                tile_total = tsp;
-                if constexpr (MODE == kModeTotals) {
-                    if (tid == 0) p.tagg[t] = tsp;
-                } else if constexpr (MODE == kModeLookback) {
-                    if (wv == 0) lookback_issue<kPrevTiles<CODEC>>(p, t, tsp, lb);
-                }
-            }
-            if constexpr (MODE != kModeTotals) {
-                if (nsp >= 1) {
-                    assemble<CODEC>(s, L, 0, 0, head, r_tok);
-                    if constexpr (MODE == kModeLookback) {
-                        if (single && wv == 0) lookback_mid<kPrevTiles<CODEC>>(p, t, tsp, lb);
-                    }
-#pragma unroll
-                    for (int c = 1; c < P; c++) assemble<CODEC>(s, L, 0, c, head, r_tok);
-                }
-            }
-            if (single) {
-                if (early && tid == 0) nid = atomicAdd(ctr, 1u);
-                if constexpr (MODE == kModeLookback) {
-                    if (wv == 0) {
-                        const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tsp, lb);
-                        if (tid == 0) s.cursor = (int64_t)ex;
-                    }
-                } else if constexpr (MODE == kModeExpand) {
-                    if (tid == 0) s.cursor = checked_cursor(p, t, cur_reg, nxt_reg, tsp);
-                }
-                if (early && tid == 0) s.next_id = (int32_t)nid;
-            }
-            __syncthreads();
-            if (single) {
-                if (early) {
-                    const uint32_t raw = uniform32((uint32_t)s.next_id);
-                    nv = (int64_t)(raw & ~kLateBit);
-                    late = late || (raw & kLateBit) != 0;
-                    if (nv < n_all) {
-                        ncol = src.column(nv, col);
-                        nt = nv - src.first(ncol);
-                        coff_load<CODEC, IDX>(src.params(ncol), nt, cr);
-                    }
-                } else {
-                    if (tid == 0) nid = atomicAdd(ctr, 1u);
-                }
-            }
-            if constexpr (MODE != kModeTotals) {
-                if (single) cursor = uniform64(s.cursor);
-                if (nsp >= 1 && (MODE != kModeExpand || cursor >= 0)) {
-                    const int64_t O = cursor + (int64_t)sp_base;
-                    const int nwin = (int)uniform32(s.nwin);
-                    for (int win = 0; win < nwin; win++) {
-                        if (win > 0) {
-                            __syncthreads();
-                            head = U128{0, 0};
-#pragma unroll
-                            for (int c = 0; c < P; c++) assemble<CODEC>(s, L, win, c, head, r_tok);
-                            __syncthreads();
-                        }
-                        fixup<CODEC>(s, L, win, head);
-                        __syncthreads();
-                        drain(s, p, O, win);
-                    }
-                    offsets<CODEC, IDX>(s, p, g, sp, O);
-                    if (it + 1 < iters) __syncthreads();     // the next super-pass rewrites the prefixes
-                }
-            }
-            sp_base += tsp;
-        }
+        if constexpr (CODEC == kFsst8) carry = uniform32(s.cin);
+        const uint32_t cin = carry;
 
-        if (MODE == kModeLookback || (MODE == kModeExpand && cursor >= 0)) {
-            const int64_t endv = cursor + (int64_t)tile_total;
-            for (int j = tid; j < g.ns; j += kWG) {
-                if (min(max(s.coff[j], g.a), g.b) >= g.b) ((IDX*)p.out_off)[g.i0 + j] = (IDX)endv;
-            }
+        const uint32_t tot = lengths<CODEC>(s, p, g, 0, L, carry, true, r_len, r_tok);
+        if constexpr (MODE == kModeTotals) {
+            // the sidecar build: every check of the decode, the tile's total, no output
             if (tid == 0) {
-                if (g.i0 + g.ns == p.n_strings) ((IDX*)p.out_off)[p.n_strings] = (IDX)endv;
+                p.tagg[t] = tot;
+                s.next_id = (int32_t)atomicAdd(ctr, 1u);
+            }
+            tile_offsets<CODEC, IDX, false>(s, p, g, t, 0, tot, cin, ca, uniform64(s.gix[0]), uniform64(s.gix[1]));
+            v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+            __syncthreads();            // this tile's LDS is free for the next
+            continue;
+        }
+        LookBack lb{};
+        U128 head{0, 0};                // the lane's first 16 output bytes in the window being assembled
+        if constexpr (MODE == kModeLookback) {
+            if (wv == 0) lookback_issue<kPrevTiles<CODEC>>(p, t, tot, lb);
+        }
+        assemble<CODEC>(s, L, 0, 0, head, r_tok);
+        if constexpr (MODE == kModeLookback) {
+            if (wv == 0) lookback_mid<kPrevTiles<CODEC>>(p, t, tot, lb);
+        }
+#pragma unroll
+        for (int cc = 1; cc < P; cc++) assemble<CODEC>(s, L, 0, cc, head, r_tok);
+        if constexpr (MODE == kModeLookback) {
+            if (wv == 0) {
+                const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tot, lb);
+                if (tid == 0) s.cursor = (int64_t)ex;
+            }
+        } else {
+            if (tid == 0) {
+                int64_t cur = s.cur2[0], nxt = s.cur2[1];
+                if constexpr (SRC::kBatch) {
+                    // a batch group's cursors are scanned over all its columns:
+                    // relative to the column's first tile
+                    const int64_t b0 = (int64_t)p.tagg[0];
+                    cur -= b0;
+                    nxt -= b0;
+                }
+                s.cursor = checked_cursor(p, t, cur, nxt, tot);
+            }
+        }
+        // the next tile, requested once this one's cursor is known (tiles then
+        // start in about the order of their ids, which the look-back wants)
+        if (tid == 0) s.next_id = (int32_t)atomicAdd(ctr, 1u);
+        __syncthreads();
+        const int64_t cursor = uniform64(s.cursor);
+        if (cursor >= 0) {
+            const int nwin = (int)uniform32(s.nwin);
+            for (int win = 0; win < nwin; win++) {
+                if (win > 0) {
+                    __syncthreads();
+                    head = U128{0, 0};
+#pragma unroll
+                    for (int cc = 0; cc < P; cc++) assemble<CODEC>(s, L, win, cc, head, r_tok);
+                    __syncthreads();
+                }
+                fixup<CODEC>(s, L, win, head);
+                __syncthreads();
+                drain(s, p, cursor, win);
+            }
+            tile_offsets<CODEC, IDX, true>(s, p, g, t, cursor, tot, cin, ca, uniform64(s.gix[0]),
+                                           uniform64(s.gix[1]));
+            if (tid == 0) {
+                const int64_t endv = cursor + (int64_t)tot;
                 if (sizeof(IDX) == 4 && endv > (int64_t)INT32_MAX) record_error(p.err, kRankOverflow, FD_EOVERFLOW);
                 if (endv > p.out_cap) record_error(p.err, kRankCapacity, FD_ECAPACITY);
             }
         }
-        if (!early) {
-            if (tid == 0) s.next_id = (int32_t)nid;
-            __syncthreads();
-            const uint32_t raw = uniform32((uint32_t)s.next_id);
-            nv = (int64_t)(raw & ~kLateBit);
-            late = late || (raw & kLateBit) != 0;
-            if (nv < n_all) {
-                ncol = src.column(nv, col);
-                nt = nv - src.first(ncol);
-                coff_load<CODEC, IDX>(src.params(ncol), nt, cr);
-            }
-        }
-        // the next tile: geometry from its offsets (with kEarlyNext loaded since
-        // the cursor barrier; its barrier also ends this tile's use of LDS) and codes
-        v = nv;
-        if (v < n_all) {
-            col = ncol;
-            t = nt;
-            const DecodeParams& pn = src.params(col);
-            g = geom_from_regs<CODEC>(s, pn, t, cr);
-            codes_load<CODEC>(pn, g, 0, wc);
-        }
+        v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+        __syncthreads();                // this tile's LDS is free for the next
     }
 }
 
@@ -1540,11 +1512,10 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
 // checks each tile's total against the cursors scanned from these).  One wave
 // per tile, without barriers, so that many tiles' loads are in flight: the
 // wave walks the tile's chunks 64 lanes x P at a time, loading each step's
-// chunks one step ahead (FSST-8; OnPair uses k_tile_totals_wg below).  A tile
-// starts at a string boundary, where an FSST-8 code is never a literal; inside
-// the tile the escape parity runs on across strings exactly as in the expand
-// phase's scan (in valid data no string ends inside a run of escapes of odd
-// length).
+// chunks one step ahead.  The FSST-8 escape parity entering a tile comes from
+// the run of 255 bytes just before it; inside the tile it runs on across
+// strings exactly as in the expand phase's scan (in valid data no string ends
+// inside a run of escapes of odd length).
 // OnPair-16 token lengths as nibbles in LDS (32 KiB): 16 lengths (bytes of
 // 0..16) become 8 bytes, code 2k in the low nibble of byte k, 16 stored as 0.
 __device__ __forceinline__ void nib_table_load(uint8_t* s_nib, const uint8_t* tok_len) {
@@ -1603,26 +1574,19 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
     }
     const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
         kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
-    const IDX* co = (const IDX*)p.code_off;
+    int64_t ca, cb;                               // the decode range
+    column_range<IDX>(p, ca, cb);
+    ca = uniform64(ca);
+    cb = uniform64(cb);
+    const int64_t ca_c = min(max(ca, (int64_t)0), p.n_codes);
     const int64_t nw = (int64_t)gridDim.x * kNWave;
-    int64_t t = (int64_t)blockIdx.x * kNWave + (tid >> 6);
-    // lane 0 holds the code offsets of the wave's next tile, loaded a tile ahead
-    IDX n0 = 0, n1 = 0;
-    auto offsets_of = [&](int64_t tt) {
-        if (lane == 0 && tt < p.n_tiles) {
-            const int64_t i0 = tt * (int64_t)p.sb;
-            const int64_t i1 = min(i0 + (int64_t)p.sb, p.n_strings);
-            n0 = co[i0];
-            n1 = co[i1];
-        }
-    };
-    offsets_of(t);
-    for (; t < p.n_tiles; t += nw) {
-        const int64_t c0 = uniform64((int64_t)n0), c1 = uniform64((int64_t)n1);
-        offsets_of(t + nw);
-        const Geom g = make_geom<CODEC>(p, t, c0, c1);
+    // the tiles outside [first_tile, last_tile] have zero totals (zeroed)
+    const int64_t t_end = last_tile(p, ca, cb) + 1;
+    for (int64_t t = first_tile(p, ca, cb) + (int64_t)blockIdx.x * kNWave + (tid >> 6); t < t_end; t += nw) {
+        const Geom g = make_geom<CODEC>(p, t, ca, cb);
         const int64_t steps = (g.nchunk + CPI - 1) / CPI;
         uint32_t carry = 0;
+        if constexpr (CODEC == kFsst8) carry = fsst_carry_in(p.codes, ca_c, g.a);
         uint64_t total = 0;
         uint32_t wn[P][4];                        // the next step's chunks, loaded a step ahead
         if (steps > 0) codes_load_at<CODEC>(p, g, (int64_t)lane * P, wn);
@@ -1653,6 +1617,10 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                         F |= (((m >> 7) * 0x00204081u) >> 21 & 0xfu) << (c * 16 + q * 4);
                     }
                 F &= valid;
+                if (it == 0) {                    // the parity entering the tile, at its first code
+                    if (lane == 0) F |= tile_entry_mask(g.a - q0, carry);
+                    if (g.a > g.pos0) carry = 0;
+                }
                 // the parity entering each lane: the trailing run of the nearest
                 // lower lane that is not all escapes, else the previous step's
                 const bool all_ff = (F == 0xffffffffu);
@@ -1720,8 +1688,10 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
     __shared__ uint64_t s_wsum[kNWave];
     __shared__ int64_t s_nb[2];
     const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ uint32_t s_cin;
     const void* table = nullptr;                  // the dictionary whose lengths are in LDS
-    int col = 0;
+    int col = 0, hdr_col = -1;
+    int64_t ca = 0, cb = 0;                       // the decode range of column hdr_col
     // one column: tiles blockIdx.x, + gridDim.x, ...; a batch: a contiguous
     // range of tiles per workgroup, so that it reloads its table only where
     // its range crosses into a column of another dictionary
@@ -1762,18 +1732,26 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
         }
         const __amdgpu_buffer_rsrc_t r_len = make_rsrc(
             kIsOnpair<CODEC> ? (const void*)p.tok_len : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u : 0u);
-        if (tid == 0) {
-            const IDX* co = (const IDX*)p.code_off;
-            const int64_t i0 = t * (int64_t)p.sb;
-            const int64_t i1 = min(i0 + (int64_t)p.sb, p.n_strings);
-            s_nb[0] = (int64_t)co[i0];
-            s_nb[1] = (int64_t)co[i1];
+        if (col != hdr_col) {
+            if (tid == 0) column_range<IDX>(p, s_nb[0], s_nb[1]);
+            __syncthreads();                      // s_nb, and the table when it was reloaded
+            ca = uniform64(s_nb[0]);
+            cb = uniform64(s_nb[1]);
+            hdr_col = col;
         }
-        __syncthreads();                          // s_nb, and the table when it was reloaded
-        const Geom g = make_geom<CODEC>(p, t, s_nb[0], s_nb[1]);
+        if (t > last_tile(p, ca, cb) || t < first_tile(p, ca, cb)) continue;   // zero totals (zeroed)
+        const Geom g = make_geom<CODEC>(p, t, ca, cb);
+        if constexpr (CODEC == kFsst8) {
+            if (wv == 0) {
+                const uint32_t ci = fsst_carry_in(p.codes, min(max(ca, (int64_t)0), p.n_codes), g.a);
+                if (tid == 0) s_cin = ci;
+            }
+        }
+        __syncthreads();                          // s_cin, and the table when it was reloaded
         uint32_t carry = 0;
+        if constexpr (CODEC == kFsst8) carry = uniform32(s_cin);
         uint64_t total = 0;
-        for (int sp = 0; sp < g.nsp; sp++) {
+        for (int sp = 0; sp < (g.nchunk > 0 ? 1 : 0); sp++) {
             uint32_t w[P][4];
             codes_load<CODEC>(p, g, sp, w);
             const int64_t k0 = (int64_t)sp * kWG * P + (int64_t)tid * P;
@@ -1795,6 +1773,8 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
                         F |= (((m >> 7) * 0x00204081u) >> 21 & 0xfu) << (c * 16 + q * 4);
                     }
                 F &= valid;
+                if (tid == 0) F |= tile_entry_mask(g.a - q0, carry);   // the parity entering the tile
+                if (g.a > g.pos0) carry = 0;
                 const bool all_ff = (F == 0xffffffffu);
                 const uint32_t trail = __clz(~F);
                 const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
@@ -1860,7 +1840,7 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
             for (int i = 0; i < kNWave; i++) sum += s_wsum[i];
             out[v] = sum;
         }
-        __syncthreads();                          // s_nb, s_wsum and the table of the next tile
+        __syncthreads();                          // s_wsum, s_cin and the table of the next tile
     }
 }
 
@@ -1875,6 +1855,78 @@ __global__ void __launch_bounds__(kWG) k_tile_totals_batch(const DecodeParams* _
                                                            const int64_t* __restrict__ first_tile, int32_t n_cols,
                                                            int64_t total, unsigned long long* out) {
     totals_tiles_wg<CODEC, IDX>(ColumnBatch{cols, first_tile, n_cols, total, nullptr}, out);
+}
+
+// --------------------------------------------------------------------------
+// The coarse string index of a column.  Sample j is code_offsets[min(j G, n)]
+// (j = 0 .. J, J = ceil(n / G)); coarse[t] is the largest j whose sample lies
+// below tile t's first position t T (0 when none does, which the zeroed array
+// already holds).  Sample j covers the tiles t >= 1 with c_j < t T <= c_{j+1}
+// (c_{J+1} taken as past the last tile).  A wave handles 64 samples and writes
+// their tiles together, a loop step per 64 tiles, so a sample spanning many
+// tiles (a very long string) does not serialise one lane.  On decreasing
+// offsets some tiles keep their zero or get any candidate: the decode's
+// offsets step checks what it reads against the index and reports EOFFSETS.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
+    const unsigned lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, 64);
+        if (lane >= (unsigned)d) x += y;
+    }
+    return x;
+}
+
+template <typename IDX>
+__device__ __forceinline__ void coarse_column(const DecodeParams& p) {
+    const unsigned lane = lane_id();
+    const IDX* co = (const IDX*)p.code_off;
+    const int64_t n = p.n_strings, T = p.tile_codes, nt = p.n_tiles;
+    const int sh = p.g_shift;
+    const int64_t J = (n + ((int64_t)1 << sh) - 1) >> sh;
+    // only the tiles up to the one after the tile holding the end of the
+    // range are read (the later ones are skipped by the decode)
+    const int64_t cb = min(max((int64_t)co[n], (int64_t)0), p.n_codes);
+    const int64_t t_max = min(cb / T + 1, nt - 1);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j - (int64_t)lane <= J; j += step) {
+        int64_t t_lo = 0, len = 0;
+        if (j <= J) {
+            const int64_t c0 = (int64_t)co[min(j << sh, n)];
+            const int64_t c1 = (j < J) ? (int64_t)co[min((j + 1) << sh, n)] : INT64_MAX;
+            const int64_t lo_t = max(c0 < 0 ? (int64_t)1 : c0 / T + 1, (int64_t)1);
+            const int64_t hi_t = (c1 == INT64_MAX) ? t_max : (c1 < 0 ? (int64_t)-1 : min(c1 / T, t_max));
+            if (hi_t >= lo_t) {
+                t_lo = lo_t;
+                len = hi_t - lo_t + 1;
+            }
+        }
+        const int64_t incl = wave_incl_scan64(len);
+        const int64_t total = __shfl(incl, 63, 64);
+        const int64_t excl = incl - len;
+        for (int64_t kb = 0; kb < total; kb += 64) {   // uniform: every lane takes part in the shuffles
+            const int64_t k = kb + (int64_t)lane;
+            // the lane whose range holds entry k: the count of lanes ending at or before k
+            int o = 0;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1)
+                if (__shfl(incl, o + d - 1, 64) <= k) o += d;
+            o = min(o, 63);
+            const int64_t tk = __shfl(t_lo, o, 64) + (k - __shfl(excl, o, 64));
+            if (k < total) p.coarse[tk] = j - (int64_t)lane + o;
+        }
+    }
+}
+
+template <typename IDX>
+__global__ void __launch_bounds__(256) k_coarse(DecodeParams p) {
+    coarse_column<IDX>(p);
+}
+
+template <typename IDX>
+__global__ void __launch_bounds__(256) k_coarse_batch(const DecodeParams* __restrict__ cols, int32_t n_cols) {
+    for (int32_t c = (int32_t)blockIdx.y; c < n_cols; c += (int32_t)gridDim.y) coarse_column<IDX>(cols[c]);
 }
 
 // Exclusive scan of v[0, n) in place across workgroups of 1,024 entries:
@@ -2251,6 +2303,28 @@ hipError_t launch_tile_totals(int codec, int index_bits, const DecodeParams& p, 
     TT(kOnpair12, int32_t) TT(kOnpair12, int64_t)
 #undef TT
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_coarse_one(int index_bits, const DecodeParams& p, hipStream_t st) {
+    const int64_t J = (p.n_strings + ((int64_t)1 << p.g_shift) - 1) >> p.g_shift;
+    const int64_t blocks = min((J + 1 + 255) / 256, (int64_t)8192);
+    if (index_bits == 32)
+        hipLaunchKernelGGL(k_coarse<int32_t>, dim3((unsigned)blocks), dim3(256), 0, st, p);
+    else
+        hipLaunchKernelGGL(k_coarse<int64_t>, dim3((unsigned)blocks), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_batch(int index_bits, const DecodeParams* cols, int32_t n_cols, int64_t max_samples,
+                               hipStream_t st) {
+    if (n_cols <= 0) return hipSuccess;
+    const int64_t blocks = min((max_samples + 1 + 255) / 256, (int64_t)8192);
+    const unsigned gy = (unsigned)min(n_cols, 32768);
+    if (index_bits == 32)
+        hipLaunchKernelGGL(k_coarse_batch<int32_t>, dim3((unsigned)blocks, gy), dim3(256), 0, st, cols, n_cols);
+    else
+        hipLaunchKernelGGL(k_coarse_batch<int64_t>, dim3((unsigned)blocks, gy), dim3(256), 0, st, cols, n_cols);
+    return hipGetLastError();
 }
 
 hipError_t launch_scan_multi(unsigned long long* v, int64_t n, unsigned long long* bsum, hipStream_t st) {

@@ -48,14 +48,19 @@ def test_host_only_entry_points(fdlib):
     assert "gfx950" in fd.version()
     assert fd.decoded_bound("fsst8", 10) == 80 and fd.decoded_bound("onpair16", 10) == 160
     a = fd.workspace_size("fsst8", 1000, 10)
-    b = fd.workspace_size("fsst8", 1000, 10, {"mode": 0, "strings_per_tile": 1, "grid": 0, "reserved": 0})
+    b = fd.workspace_size("fsst8", 1000, 10, {"mode": 0, "tile_codes": 16, "grid": 0, "reserved": 0})
     assert b >= a > 0
     # OnPair one-shot decodes repack the dictionary inside the workspace
     assert fd.workspace_size("onpair16", 1000, 10) > 65536 * 17
     with pytest.raises(fd.DecodeError):
         fd.workspace_size("fsst8", -1, 10)
-    with pytest.raises(fd.DecodeError):
-        fd.workspace_size("fsst8", 10, 10, {"mode": 0, "strings_per_tile": 257, "grid": 0, "reserved": 0})
+    # tile sizes: whole 16-byte chunks of codes, at most one pass less a chunk
+    for codec, bad in (("fsst8", 8), ("fsst8", 24), ("fsst8", 8192), ("onpair16", 4), ("onpair16", 4096),
+                       ("onpair12", 12), ("fsst8", -16)):
+        with pytest.raises(fd.DecodeError):
+            fd.workspace_size(codec, 10, 10, {"mode": 0, "tile_codes": bad, "grid": 0, "reserved": 0})
+    for codec, good in (("fsst8", 16), ("fsst8", 8176), ("onpair16", 8), ("onpair12", 4088)):
+        assert fd.workspace_size(codec, 10, 10, {"mode": 0, "tile_codes": good, "grid": 0, "reserved": 0}) > 0
 
 
 def test_argument_errors_enqueue_nothing(fdlib):
@@ -121,13 +126,14 @@ def test_sidecar_host_checks(fdlib):
     missing dictionary, a sidecar of another tiling and three-phase tuning
     before touching the device."""
     fd = fdlib
-    tu = {"mode": 0, "strings_per_tile": 3, "grid": 0, "reserved": 0}
-    assert fd.sidecar_layout("fsst8", 1000, 10, tu) == (3, 5)
-    assert fd.sidecar_layout("onpair12", 1000, 0, tu) == (3, 2)
-    sb, n = fd.sidecar_layout("onpair16", 10 ** 6, 10 ** 4)
-    assert 1 <= sb <= 1024 and n == -(-10 ** 4 // sb) + 1
+    tu = {"mode": 0, "tile_codes": 48, "grid": 0, "reserved": 0}
+    assert fd.sidecar_layout("fsst8", 1000, 10, tu) == (48, 22)        # ceil(1000 / 48) + 1
+    assert fd.sidecar_layout("onpair12", 0, 0, tu) == (48, 2)          # one tile even without codes
+    T, n = fd.sidecar_layout("onpair16", 10 ** 6, 10 ** 4)
+    assert T == 4088 and n == -(-10 ** 6 // T) + 1
+    assert fd.sidecar_layout("fsst8", 10 ** 6, 10 ** 4) == (8176, -(-10 ** 6 // 8176) + 1)
     with pytest.raises(fd.DecodeError):
-        fd.sidecar_layout("fsst8", 1000, 10, {"mode": 1, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+        fd.sidecar_layout("fsst8", 1000, 10, {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0})
     L = fd.lib()
     P = ctypes.c_void_p
     fake, ws = P(1 << 20), P(1 << 21)
@@ -150,7 +156,7 @@ def test_take_host_checks(fdlib):
         with pytest.raises(fd.DecodeError):
             fd.take_workspace_size("fsst8", *bad)
     with pytest.raises(fd.DecodeError):
-        fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 1, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+        fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0})
     L = fd.lib()
     P = ctypes.c_void_p
     fake, ws = P(1 << 20), P(1 << 21)

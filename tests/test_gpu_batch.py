@@ -103,11 +103,11 @@ def run_batch(cols, tuning=None, graph=False, async_=True):
     return rc, status.cpu().numpy(), ws, status
 
 
-@pytest.mark.parametrize("tuning", [None, {"mode": 0, "strings_per_tile": 0, "grid": 0, "reserved": 0},
-                                    {"mode": 0, "strings_per_tile": 3, "grid": 5, "reserved": 0},
-                                    {"mode": 1, "strings_per_tile": 0, "grid": 0, "reserved": 0},
-                                    {"mode": 1, "strings_per_tile": 3, "grid": 5, "reserved": 0},
-                                    {"mode": 1, "strings_per_tile": 1, "grid": 0, "reserved": 0}])
+@pytest.mark.parametrize("tuning", [None, {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0},
+                                    {"mode": 0, "tile_codes": 48, "grid": 5, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 48, "grid": 5, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 16, "grid": 0, "reserved": 0}])
 def test_batch_matches_oracle(datagen_mod, tuning):
     cols = mixed_columns(datagen_mod)
     rc, st, _, _ = run_batch(cols, tuning=tuning)
@@ -140,7 +140,7 @@ def test_batch_errors_per_column(datagen_mod, mode):
     ur = datagen_mod.onpair_urls(seed=46, target_bytes=128 << 10, sample_bytes=128 << 10)
     good2 = Col("onpair16", ur.codes, ur.code_off, ur.dict_bytes, ur.dict_lens)
     cols = [good, small, bad, good2]
-    rc, st, _, _ = run_batch(cols, async_=False, tuning={"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+    rc, st, _, _ = run_batch(cols, async_=False, tuning={"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0})
     assert [c.exp.status for c in cols] == [0, 4, 2, 0]
     for c, x in zip(cols, st[:-1]):
         c.check(int(x))
@@ -155,7 +155,7 @@ def test_batch_graph_replays(datagen_mod, mode):
     import paper_2609_15034_amd as fd
     cols = mixed_columns(datagen_mod)
     tups = [c.tup() for c in cols]
-    tu = None if mode is None else {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    tu = None if mode is None else {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
     ws = torch.empty(fd.batch_workspace_size(tups, tu), dtype=torch.uint8, device="cuda")
     status = torch.full((len(cols) + 1,), -1, dtype=torch.int32, device="cuda")
     noise = torch.randn(1 << 20, device="cuda")
@@ -210,7 +210,7 @@ def test_batch_many_small_columns(datagen_mod, mode):
         else:
             dp = c.d
         cols.append(c)
-    tu = None if mode is None else {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+    tu = None if mode is None else {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
     rc, st, _, _ = run_batch(cols, tuning=tu)
     assert rc == 0
     for c, x in zip(cols, st[:-1]):

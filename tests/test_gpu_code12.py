@@ -77,9 +77,9 @@ def test_unaligned_streams(cols, misalign):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("sb", [0, 1, 7, 512])
+@pytest.mark.parametrize("tc", [0, 8, 56, 2000])
 @pytest.mark.parametrize("grid", [0, 3])
-def test_tuning(cols, mode, sb, grid):
+def test_tuning(cols, mode, tc, grid):
     c = cols["fsst12"]
     n = 3001                                    # an odd number of strings, a partial last group of codes
     m = int(c.code_off[n])
@@ -87,7 +87,7 @@ def test_tuning(cols, mode, sb, grid):
     codes16 = oracle.unpack12(c.codes[: (m * 12 + 7) // 8 + 2], m)
     packed = oracle.pack12(codes16)
     assert_parity12(packed, m, c.code_off[: n + 1], c.dict_bytes, c.dict_lens,
-                    tuning={"mode": mode, "strings_per_tile": sb, "grid": grid, "reserved": 0})
+                    tuning={"mode": mode, "tile_codes": tc, "grid": grid, "reserved": 0})
 
 
 @pytest.mark.parametrize("n_codes", [0, 1, 2, 3, 7, 8, 9, 4095, 4097])

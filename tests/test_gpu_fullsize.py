@@ -69,7 +69,7 @@ def test_full_column(datagen_mod, oracle_mod, workload, seed):
     text = torch.from_numpy(col.text).to(dev)
     text_off = torch.from_numpy(col.text_off).to(dev)
     for mode in (0, 1):
-        tu = {"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0}
+        tu = {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
         out.fill_(0x5A)
         out_off.fill_(-7)
         for _ in range(2):    # twice: the second run reuses the workspace as the benchmark does
@@ -118,8 +118,10 @@ def test_full_batch(datagen_mod, oracle_mod):
 @pytest.mark.parametrize("workload,seed", [("fsst_logs", 2), ("onpair_urls", 3)])
 def test_full_column_sidecar_and_take(datagen_mod, workload, seed):
     """The 1 GiB columns through the stored-sidecar decode and a 10% selection
-    in random order, as the benchmark runs them: the sidecar equals the source
-    offsets at every tile's first string, both outputs equal the source text."""
+    in random order, as the benchmark runs them: the sidecar equals the
+    output position of every tile's first code (the source offsets of the
+    string holding it plus the oracle's walk of that string), both outputs
+    equal the source text."""
     import torch
     import paper_2609_15034_amd as fd
     col = getattr(datagen_mod, workload)(seed=seed)
@@ -130,10 +132,15 @@ def test_full_column_sidecar_and_take(datagen_mod, workload, seed):
     text = torch.from_numpy(col.text).to(dev)
     to = np.asarray(col.text_off, np.int64)
     # sidecar: built on the device, checked against the source offsets, then decoded with
-    sb, n_entries = fd.sidecar_layout(col.codec, codes.numel(), col.n_strings)
+    import oracle
+    T, n_entries = fd.sidecar_layout(col.codec, codes.numel(), col.n_strings)
     sc = fd.sidecar_build(d, codes, code_off)
-    firsts = [min(k * sb, col.n_strings) for k in range(n_entries - 1)] + [col.n_strings]
-    assert np.array_equal(sc.cpu().numpy(), to[firsts])
+    # every tile start's output position: the source strings' offsets plus
+    # the oracle's walk of the string holding the tile start
+    st, exp = oracle.sidecar(col.codec, col.codes, col.code_off, col.dict_bytes, col.dict_lens, T,
+                             string_offsets=to)
+    assert st == 0 and len(exp) == n_entries
+    assert np.array_equal(sc.cpu().numpy(), exp)
     out = torch.full((col.decoded_bytes + 64,), 0xA5, dtype=torch.uint8, device=dev)
     out_off = torch.full((col.n_strings + 1,), -7, dtype=code_off.dtype, device=dev)
     ws = fd.alloc_workspace(col.codec, codes.numel(), col.n_strings)

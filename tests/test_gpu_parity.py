@@ -52,24 +52,27 @@ def test_random_full_dictionary(datagen_mod):
 
 
 # --------------------------------------------------------------------------- #
-# tuning: modes, tiny tiles (long look-back chains), small grids
+# tuning: modes, tiny tiles (strings across many tiles, long look-back
+# chains), small grids
 # --------------------------------------------------------------------------- #
+def tu(mode=0, tc=0, grid=0):
+    return {"mode": mode, "tile_codes": tc, "grid": grid, "reserved": 0}
+
+
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("sb", [0, 1, 3, 17, 256])
+@pytest.mark.parametrize("tc", [0, 16, 48, 272, 2048])
 @pytest.mark.parametrize("grid", [0, 1, 7])
-def test_tuning_fsst(datagen_mod, mode, sb, grid):
+def test_tuning_fsst(datagen_mod, mode, tc, grid):
     c = datagen_mod.fsst_small(seed=4, n_strings=3000)
-    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens,
-                  tuning={"mode": mode, "strings_per_tile": sb, "grid": grid, "reserved": 0})
+    assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, tuning=tu(mode, tc, grid))
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("sb", [0, 1, 5, 512])
+@pytest.mark.parametrize("tc", [0, 8, 40, 1000])
 @pytest.mark.parametrize("grid", [0, 2])
-def test_tuning_onpair(datagen_mod, mode, sb, grid):
+def test_tuning_onpair(datagen_mod, mode, tc, grid):
     c = datagen_mod.onpair_urls(seed=5, target_bytes=1 << 20, sample_bytes=1 << 20)
-    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens,
-                  tuning={"mode": mode, "strings_per_tile": sb, "grid": grid, "reserved": 0})
+    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens, tuning=tu(mode, tc, grid))
 
 
 # --------------------------------------------------------------------------- #
@@ -98,11 +101,14 @@ def _ff_column(seed, n_strings, max_run=300):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("sb", [0, 1, 2, 7])
-def test_ff_runs(sb, mode):
+@pytest.mark.parametrize("tc", [0, 16, 32, 112])
+def test_ff_runs(tc, mode):
+    """Runs of 255 of every length up to 300, across lane, wave and (with
+    small tiles) tile starts: a tile that starts inside a run takes its parity
+    from the bytes before it."""
     codes, off = _ff_column(7, 2500)
     db, dl = pack([b"x", b"yz", b"0123456"])
-    assert_parity("fsst8", codes, off, db, dl, tuning={"mode": mode, "strings_per_tile": sb, "grid": 0, "reserved": 0})
+    assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode, tc))
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -114,8 +120,8 @@ def test_ff_run_longer_than_a_pass(mode):
         codes = np.frombuffer(b"\x00" + b"\xff" * L + (b"\x01" if L % 2 else b"") + b"\x02", np.uint8).copy()
         off = np.array([0, len(codes)], np.int64)
         db, dl = pack([b"a", b"bc", b"def"])
-        assert_parity("fsst8", codes, off, db, dl, tuning={"mode": mode, "strings_per_tile": 0, "grid": 0,
-                                                            "reserved": 0})
+        assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode))
+        assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode, 16))
 
 
 # --------------------------------------------------------------------------- #
@@ -216,8 +222,8 @@ def test_onpair16_short_dictionary_many_tiles(datagen_mod, mode, bad_at):
     assert (dl == 16).any()
     if bad_at is not None:
         codes[bad_at] = 1000 + bad_at % 7
-    assert_parity("onpair16", codes, c.code_off, c.dict_bytes, dl,
-                  tuning={"mode": mode, "strings_per_tile": 0, "grid": 0, "reserved": 0})
+    for tc in (0, 64):
+        assert_parity("onpair16", codes, c.code_off, c.dict_bytes, dl, tuning=tu(mode, tc))
 
 
 def test_dict_create_rejects_bad_lengths():
@@ -270,8 +276,7 @@ def test_determinism_repeated(datagen_mod):
     c = datagen_mod.fsst_small(seed=41, n_strings=4000)
     for rep in range(12):
         grid = [0, 1, 3, 64][rep % 4]
-        assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens,
-                      tuning={"mode": 0, "strings_per_tile": 1 + rep % 3, "grid": grid, "reserved": 0})
+        assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens, tuning=tu(0, 16 * (1 + rep % 3), grid))
 
 
 def test_decode_convenience(datagen_mod):
@@ -283,3 +288,65 @@ def test_decode_convenience(datagen_mod):
     off, out = fd.decode(d, torch.from_numpy(c.codes.view(np.int16)).cuda(), torch.from_numpy(c.code_off).cuda())
     exp = oracle.decode("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens)
     assert np.array_equal(off.cpu().numpy(), exp.out_off) and np.array_equal(out.cpu().numpy(), exp.out_bytes)
+
+
+# --------------------------------------------------------------------------- #
+# tiles at fixed code positions: slices, strings across many tiles, runs of
+# empty strings, offsets that are wrong anywhere
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tc", [0, 16, 48])
+def test_slice_small_tiles(datagen_mod, mode, tc):
+    """A slice: tiles are positions of the whole buffer, so the first and last
+    tiles hold part of the range and tiles before it hold nothing."""
+    c = datagen_mod.fsst_small(seed=12, n_strings=4000)
+    sl = c.code_off[1000:3001].astype(np.int64)
+    assert_parity("fsst8", c.codes, sl, c.dict_bytes, c.dict_lens, tuning=tu(mode, tc))
+    c2 = datagen_mod.onpair_urls(seed=13, target_bytes=512 << 10, sample_bytes=512 << 10)
+    sl2 = c2.code_off[777:5555]
+    assert_parity("onpair16", c2.codes, sl2, c2.dict_bytes, c2.dict_lens, tuning=tu(mode, tc))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tc", [0, 16])
+def test_string_across_many_tiles(mode, tc):
+    """One string of 300,000 codes among short ones: 18,750 tiles of 16 codes
+    own no string start (the coarse index writes them in one wave's loop)."""
+    rng = np.random.default_rng(61)
+    db, dl = pack([b"a", b"bc", b"def", b"\xff\x00"])
+    lens = [3, 0, 300_000, 5, 0, 0, 7, 1]
+    codes = rng.integers(0, 4, size=sum(lens)).astype(np.uint8)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode, tc))
+    assert_parity("onpair16", codes.astype(np.uint16), off, db, dl, tuning=tu(mode, 8 if tc else 0))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tc", [0, 16])
+def test_runs_of_empty_strings(mode, tc):
+    """Tens of thousands of empty strings at a few positions (a tile owning
+    many strings reads its code offsets in several steps), also at both ends."""
+    db, dl = pack([b"a", b"bc", b"def"])
+    rng = np.random.default_rng(62)
+    codes = rng.integers(0, 3, size=5000).astype(np.uint8)
+    pos = np.sort(np.concatenate([np.zeros(20_000), np.full(30_000, 2500), rng.integers(0, 5001, 3000),
+                                  np.full(10_000, 5000)])).astype(np.int64)
+    off = np.concatenate([[0], pos, [5000]]).astype(np.int64)
+    assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode, tc))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tc", [0, 16, 160])
+def test_bad_offsets_anywhere(datagen_mod, mode, tc):
+    """A code offset that breaks the order anywhere is found, whichever tile
+    reads it: a too large or a too small entry at random places."""
+    c = datagen_mod.fsst_small(seed=63, n_strings=3000)
+    rng = np.random.default_rng(64)
+    for k in range(12):
+        off = c.code_off.astype(np.int64).copy()
+        i = int(rng.integers(1, len(off) - 1))
+        off[i] = off[i + 1] + 1 + int(rng.integers(0, 50)) if k % 2 == 0 else max(0, off[i - 1] - 1 - int(
+            rng.integers(0, 50)))
+        if np.all(np.diff(off) >= 0):
+            continue
+        assert_parity("fsst8", c.codes, off, c.dict_bytes, c.dict_lens, tuning=tu(mode, tc))

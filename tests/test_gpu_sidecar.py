@@ -46,7 +46,7 @@ class Col:
         return (c.codec, c.codes, c.code_off, c.dict_bytes, c.dict_lens)
 
     def build(self, tuning=None, async_=False):
-        """(status, sidecar tensor, strings_per_tile) from the GPU."""
+        """(status, sidecar tensor, tile_codes) from the GPU."""
         import torch
         import paper_2609_15034_amd as fd
         sb, n = fd.sidecar_layout(self.codec, self.n_codes, self.n_strings, tuning)
@@ -102,14 +102,16 @@ def cols(datagen_mod):
 
 
 @pytest.mark.parametrize("name", ["fsst_small", "fsst_logs", "onpair_urls", "onpair12_urls", "fsst12_logs"])
-@pytest.mark.parametrize("sb", [0, 1, 7, "max"])
-def test_build_and_decode(cols, name, sb):
-    """Tile sizes from one string to the largest (tiles of several passes)."""
+@pytest.mark.parametrize("tc", [0, "min", "mid"])
+def test_build_and_decode(cols, name, tc):
+    """Tile sizes from one 16-byte chunk of codes to the largest."""
     import oracle
     col = cols[name]
-    if sb == "max":
-        sb = 256 if col.codec == "fsst8" else 1024
-    tu = {"mode": 0, "strings_per_tile": sb, "grid": 0, "reserved": 0}
+    if tc == "min":
+        tc = 16 if col.codec == "fsst8" else 8
+    elif tc == "mid":
+        tc = 1024 if col.codec == "fsst8" else 600
+    tu = {"mode": 0, "tile_codes": tc, "grid": 0, "reserved": 0}
     st, sc, sb_used = col.build(tu)
     kw = {"n_codes": col.n_codes} if col.codec == "onpair12" else {}
     est, exp = oracle.sidecar(*col.oracle_args(), sb_used, **kw)
@@ -122,7 +124,7 @@ def test_build_and_decode(cols, name, sb):
 @pytest.mark.parametrize("grid", [1, 3])
 def test_small_grids(cols, grid):
     col = cols["fsst_logs"]
-    tu = {"mode": 0, "strings_per_tile": 0, "grid": grid, "reserved": 0}
+    tu = {"mode": 0, "tile_codes": 0, "grid": grid, "reserved": 0}
     st, sc, sb = col.build(tu)
     assert st == 0
     check_decode(col, sc, sb, tu)
@@ -130,15 +132,39 @@ def test_small_grids(cols, grid):
 
 @pytest.mark.parametrize("name", ["fsst_logs", "onpair_urls"])
 def test_sidecar_from_source_offsets(cols, name):
-    """A sidecar written by an encoder from its source strings' offsets (no
-    decode involved) decodes the column."""
+    """A sidecar written by an encoder, which knows what each code it emitted
+    stands for (a token's length; for FSST-8 an escape stands for nothing and
+    its literal for one byte), sampled at every tile start (no decode
+    involved), decodes the column."""
     import torch
     import paper_2609_15034_amd as fd
     col = cols[name]
-    sb, n = fd.sidecar_layout(col.codec, col.n_codes, col.n_strings)
-    firsts = [min(k * sb, col.n_strings) for k in range(n - 1)] + [col.n_strings]
-    sc = torch.from_numpy(np.asarray(col.c.text_off, np.int64)[firsts].copy()).cuda()
-    exp = check_decode(col, sc, sb)
+    c = col.c
+    T, n = fd.sidecar_layout(col.codec, col.n_codes, col.n_strings)
+    lens = c.dict_lens.astype(np.int64)
+    if c.codec == "fsst8":
+        # escapes and literals: inside a run of 255 the codes alternate escape / literal,
+        # starting with an escape at the run's start (every string starts with a code)
+        per = np.zeros(len(c.codes), np.int64)
+        co = np.asarray(c.code_off, np.int64)
+        is_ff = c.codes == 255
+        for i in range(c.n_strings):
+            a, e = int(co[i]), int(co[i + 1])
+            expect_code = True
+            for p in range(a, e):
+                if expect_code and is_ff[p]:
+                    expect_code = False          # an escape: nothing
+                elif not expect_code:
+                    per[p] = 1                   # its literal
+                    expect_code = True
+                else:
+                    per[p] = lens[c.codes[p]]
+    else:
+        per = lens[c.codes]
+    cum = np.concatenate([[0], np.cumsum(per)])
+    pos = [min(k * T, col.n_codes) for k in range(n - 1)] + [col.n_codes]
+    sc = torch.from_numpy(cum[pos].copy()).cuda()
+    exp = check_decode(col, sc, T)
     assert exp.status == 0
 
 
@@ -215,11 +241,14 @@ def test_empty_and_one_string(datagen_mod):
     import paper_2609_15034_amd as fd
     c = datagen_mod.fsst_small(seed=3)
     col = Col(c)
+    import oracle
     for n in (0, 1):
         col.off = torch.from_numpy(np.ascontiguousarray(c.code_off[: n + 1])).cuda()
         col.n_strings = n
         st, sc, sb = col.build()
-        assert st == 0 and sc.cpu().tolist() == [0, int(c.text_off[n])]
+        est, exp = oracle.sidecar("fsst8", c.codes, c.code_off[: n + 1], c.dict_bytes, c.dict_lens, sb)
+        assert st == est == 0 and np.array_equal(sc.cpu().numpy(), exp)
+        assert exp[-1] == int(c.text_off[n]) and exp[0] == 0
         st, off, out = col.decode(sc)
         assert st == 0 and off.tolist() == [int(x) for x in c.text_off[: n + 1]]
 
@@ -227,8 +256,8 @@ def test_empty_and_one_string(datagen_mod):
 def test_sidecar_of_another_tiling(cols):
     import paper_2609_15034_amd as fd
     col = cols["fsst_small"]
-    st, sc, sb = col.build({"mode": 0, "strings_per_tile": 5, "grid": 0, "reserved": 0})
+    st, sc, sb = col.build({"mode": 0, "tile_codes": 16, "grid": 0, "reserved": 0})
     assert st == 0
-    tu = {"mode": 0, "strings_per_tile": 6, "grid": 0, "reserved": 0}
+    tu = {"mode": 0, "tile_codes": 32, "grid": 0, "reserved": 0}
     st, _, _ = col.decode(sc, tu)
     assert st == fd.EINVAL

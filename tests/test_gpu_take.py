@@ -118,14 +118,12 @@ def test_take(cols, name, order):
         assert exp.out_off[-1] == int((co[rows + 1] - co[rows]).sum())
 
 
-@pytest.mark.parametrize("tuning", [{"mode": 0, "strings_per_tile": 1, "grid": 0, "reserved": 0},
-                                    {"mode": 0, "strings_per_tile": 256, "grid": 3, "reserved": 0},
-                                    {"mode": 0, "strings_per_tile": 1024, "grid": 0, "reserved": 0}])
+@pytest.mark.parametrize("tuning", [{"mode": 0, "tile_codes": 16, "grid": 0, "reserved": 0},
+                                    {"mode": 0, "tile_codes": 400, "grid": 3, "reserved": 0},
+                                    {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0}])
 @pytest.mark.parametrize("name", ["fsst_logs", "onpair12_urls"])
 def test_take_tuning(cols, name, tuning):
     c = cols[name]
-    if c.codec == "fsst8" and tuning["strings_per_tile"] > 256:
-        pytest.skip("FSST-8 tiles hold at most 256 strings")
     rows = make_rows(c.n_strings, "random10", np.random.default_rng(8))
     assert assert_take(c, rows, tuning=tuning).status == 0
 

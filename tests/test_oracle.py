@@ -348,50 +348,84 @@ def test_roundtrip_code12(oracle_mod, datagen_mod):
 # --------------------------------------------------------------------------- #
 
 
-def tile_firsts(n_strings, sb):
-    """The first string of every tile, then n_strings (the sidecar's entries)."""
-    n_tiles = max(1, -(-n_strings // sb))
-    return [min(k * sb, n_strings) for k in range(n_tiles)] + [n_strings]
+def tile_starts(n_codes, a, b, T):
+    """The code position of every tile's first code, then the end b."""
+    n_tiles = max(1, -(-n_codes // T))
+    return [max(a, min(k * T, b)) for k in range(n_tiles)] + [b]
 
 
 def test_sidecar_by_hand(oracle_mod):
     """Positions derived by hand.  FSST-8 table {0: "ab", 1: "c"}; strings
     "abc" (codes 0 1), "x" (escape + literal), "ab" (0), "" and "cc" (1 1):
-    decoded lengths 3, 1, 2, 0, 2.  OnPair-16 tokens {"a", "bcd", "ef"};
-    strings of codes [1 2], [0], [2 2 1]: lengths 5, 1, 7."""
+    code positions 0..7 start at output bytes 0, 2, 3, 3, 4, 6, 7, 8 (the
+    escape at 2 emits nothing, its literal at 3 one byte).  OnPair-16 tokens
+    {"a", "bcd", "ef"}; codes 1 2 | 0 | 2 2 1 (lengths 3 2 1 2 2 3): code
+    positions start at 0, 3, 5, 6, 8, 10, 13."""
     O = oracle_mod
     db, dl = pack([b"ab", b"c"])
     codes = np.array([0, 1, 255, ord("x"), 0, 1, 1], np.uint8)
     off = np.array([0, 2, 4, 5, 5, 7], np.int64)
-    for sb, exp in ((1, [0, 3, 4, 6, 6, 8]), (2, [0, 4, 6, 8]), (3, [0, 6, 8]), (5, [0, 8]), (9, [0, 8])):
-        st, sc = O.sidecar("fsst8", codes, off, db, dl, sb)
-        assert st == O.OK and list(sc) == exp, sb
-    db, dl = pack([b"a", b"bcd", b"ef"])
+    for T, exp in ((1, [0, 2, 3, 3, 4, 6, 7, 8]), (2, [0, 3, 4, 7, 8]), (3, [0, 3, 7, 8]), (16, [0, 8])):
+        st, sc = O.sidecar("fsst8", codes, off, db, dl, T)
+        assert st == O.OK and list(sc) == exp, T
+    db2, dl2 = pack([b"a", b"bcd", b"ef"])
     st, sc = O.sidecar("onpair16", np.array([1, 2, 0, 2, 2, 1], np.uint16), np.array([0, 2, 3, 6], np.int64),
-                       db, dl, 2)
-    assert st == O.OK and list(sc) == [0, 6, 13]
+                       db2, dl2, 2)
+    assert st == O.OK and list(sc) == [0, 5, 8, 13]
+    # a slice: the decode range [2, 6) of the same codes (the strings 0 | 2 2 1... from position 2)
+    st, sc = O.sidecar("onpair16", np.array([1, 2, 0, 2, 2, 1], np.uint16), np.array([2, 3, 6], np.int64),
+                       db2, dl2, 4)
+    assert st == O.OK and list(sc) == [0, 3, 8]
+    # a tile boundary right after an escape: position 3 is the literal
+    st, sc = O.sidecar("fsst8", codes, off, db, dl, 3)
+    assert list(sc)[1] == 3
     # no strings: one empty tile
     st, sc = O.sidecar("fsst8", np.zeros(0, np.uint8), np.array([0], np.int64), db[:1], dl[:1], 4)
     assert st == O.OK and list(sc) == [0, 0]
 
 
-@pytest.mark.parametrize("sb", [1, 3, 64, 1000, 100000])
-def test_sidecar_is_the_source_offsets(oracle_mod, datagen_mod, sb):
-    """Decoding is lossless, so the stored positions are the source strings'
-    own offsets sampled at every tile's first string (the generator's offsets,
-    not a decode)."""
+@pytest.mark.parametrize("T", [16, 48, 1000, 4088])
+def test_sidecar_at_string_starts_is_the_source_offsets(oracle_mod, datagen_mod, T):
+    """Decoding is lossless, so where a tile starts exactly at a string, the
+    stored position is that source string's own offset (the generator's
+    offsets, not a decode); every entry is non-decreasing and the last is the
+    total of the source text."""
     cols = [(datagen_mod.fsst_small(), "fsst8", None),
             (datagen_mod.onpair_urls(target_bytes=1 << 20, sample_bytes=1 << 20), "onpair16", None)]
     c12 = datagen_mod.onpair12_urls(target_bytes=1 << 19)
     cols.append((c12, "onpair12", c12.stats["n_codes"]))
     for c, codec, n_codes in cols:
-        st, sc = oracle_mod.sidecar(codec, c.codes, c.code_off, c.dict_bytes, c.dict_lens, sb, n_codes=n_codes)
+        nc = len(c.codes) if n_codes is None else n_codes
+        st, sc = oracle_mod.sidecar(codec, c.codes, c.code_off, c.dict_bytes, c.dict_lens, T, n_codes=n_codes)
         assert st == 0
-        assert np.array_equal(sc, np.asarray(c.text_off, np.int64)[tile_firsts(c.n_strings, sb)]), codec
+        co = np.asarray(c.code_off, np.int64)
+        pos = tile_starts(nc, int(co[0]), int(co[-1]), T)
+        hits = 0
+        for k, p in enumerate(pos):
+            i = np.searchsorted(co, p, side="right") - 1
+            if co[i] == p:                            # a string starts here (the last of any empty ones)
+                assert sc[k] == c.text_off[i], (codec, k)
+                hits += 1
+        assert hits >= 2
+        assert np.all(np.diff(sc) >= 0) and sc[-1] == len(c.text)
 
 
-def test_sidecar_escape_closed_form(oracle_mod, datagen_mod):
-    """With escapes, against the run-parity characterisation's offsets."""
+def test_sidecar_onpair_cumulative_lengths(oracle_mod, datagen_mod):
+    """OnPair has no escapes: the position of code p is the sum of the token
+    lengths of the codes before it (a cumulative sum, another formulation)."""
+    c = datagen_mod.onpair_urls(target_bytes=1 << 20, sample_bytes=1 << 20)
+    cum = np.concatenate([[0], np.cumsum(c.dict_lens[c.codes].astype(np.int64))])
+    co = np.asarray(c.code_off, np.int64)
+    for T in (8, 200, 4088):
+        st, sc = oracle_mod.sidecar("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens, T)
+        pos = tile_starts(len(c.codes), int(co[0]), int(co[-1]), T)
+        assert st == 0 and np.array_equal(sc, cum[pos] - cum[co[0]])
+
+
+def test_sidecar_escape_closed_form(oracle_mod):
+    """With escapes, against the run-parity characterisation: every code's
+    length (1 for a literal, 0 for an escape, else its symbol's) summed up to
+    each tile start."""
     rng = np.random.default_rng(5)
     syms = [bytes(rng.integers(97, 123, int(k)).astype(np.uint8)) for k in rng.integers(1, 9, 200)]
     db, dl = pack(syms)
@@ -407,9 +441,19 @@ def test_sidecar_escape_closed_form(oracle_mod, datagen_mod):
     st, offs, _ = closed_form_fsst8(codes.tobytes(), [int(x) for x in code_off], syms)
     if st != 0:
         pytest.skip("the random stream ended a string in an escape run")
-    for sb in (1, 7, 64):
-        st2, sc = oracle_mod.sidecar("fsst8", codes, code_off, db, dl, sb)
-        assert st2 == 0 and list(sc) == [offs[k] for k in tile_firsts(n, sb)]
+    per = np.zeros(len(codes), np.int64)
+    for i in range(n):
+        a, e = int(code_off[i]), int(code_off[i + 1])
+        for p in range(a, e):
+            run, q = 0, p - 1
+            while q >= a and codes[q] == 255:
+                run, q = run + 1, q - 1
+            per[p] = 1 if run % 2 else (0 if codes[p] == 255 else len(syms[codes[p]]))
+    cum = np.concatenate([[0], np.cumsum(per)])
+    assert cum[-1] == offs[-1]
+    for T in (1, 7, 16, 64):
+        st2, sc = oracle_mod.sidecar("fsst8", codes, code_off, db, dl, T)
+        assert st2 == 0 and np.array_equal(sc, cum[tile_starts(len(codes), 0, len(codes), T)]), T
 
 
 def test_decode_with_sidecar_precedence(oracle_mod):
@@ -419,13 +463,13 @@ def test_decode_with_sidecar_precedence(oracle_mod):
     db, dl = pack([b"ab", b"c"])
     codes = np.array([0, 1, 255, ord("x"), 0, 1, 1], np.uint8)
     off = np.array([0, 2, 4, 5, 5, 7], np.int64)
-    good = np.array([0, 4, 6, 8], np.int64)
+    good = np.array([0, 3, 4, 7, 8], np.int64)        # tiles of 2 code positions
     r = O.decode_with_sidecar("fsst8", codes, off, db, dl, good, 2)
     assert r.status == O.OK and bytes(r.out_bytes) == b"abcxabcc" and list(r.out_off) == [0, 3, 4, 6, 6, 8]
-    for bad in ([0, 4, 6, 9], [1, 4, 6, 8], [0, 5, 6, 8], [0, -4, 6, 8], [0, 4, 6, 1 << 62]):
+    for bad in ([0, 3, 4, 7, 9], [1, 3, 4, 7, 8], [0, 4, 4, 7, 8], [0, -3, 4, 7, 8], [0, 3, 4, 7, 1 << 62]):
         assert O.decode_with_sidecar("fsst8", codes, off, db, dl, np.array(bad, np.int64), 2).status == O.ESIDECAR
     # a wrong sidecar and too little room: ESIDECAR; the right one: ECAPACITY
-    assert O.decode_with_sidecar("fsst8", codes, off, db, dl, np.array([0, 4, 7, 8]), 2,
+    assert O.decode_with_sidecar("fsst8", codes, off, db, dl, np.array([0, 3, 5, 7, 8]), 2,
                                  out_capacity=3).status == O.ESIDECAR
     assert O.decode_with_sidecar("fsst8", codes, off, db, dl, good, 2, out_capacity=3).status == O.ECAPACITY
     # an error in the data wins over a wrong sidecar
