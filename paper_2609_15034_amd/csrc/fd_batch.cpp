@@ -188,6 +188,8 @@ void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* 
             p.n_tiles = pl.n_tiles[c];
             p.tile_codes = pl.tcodes[c];
             p.g_shift = pl.g_shift[c];
+            p.off_pref = offsets_prefetch_count(col.dict->codec, col.n_codes, col.n_strings, pl.tcodes[c],
+                                                pl.g_shift[c]);
             p.coarse = (int64_t*)(ws + pl.off_coarse[c]);
             p.err = (unsigned long long*)(ws + pl.off_errs) + c;
             p.counters = nullptr;

@@ -33,6 +33,15 @@ int64_t tiles_of(int64_t n_codes, int64_t tile_codes) {
     return t < 1 ? 1 : t;
 }
 
+int offsets_prefetch_count(fd_codec c, int64_t n_codes, int64_t n_strings, int64_t tile_codes, int g_shift) {
+    const int cap = c == FD_FSST8 ? kWG : 4 * kWG;
+    const double spt = n_codes > 0 ? (double)tile_codes * (double)n_strings / (double)n_codes : (double)cap;
+    const double want = 1.25 * spt + (double)((int64_t)1 << g_shift) + 2.0;
+    int k = want >= (double)cap ? cap : (int)want;
+    k = (k + 63) / 64 * 64;
+    return k < 64 ? 64 : (k > cap ? cap : k);
+}
+
 int coarse_shift(int64_t n_codes, int64_t n_strings, int64_t tile_codes) {
     const double spt = n_codes > 0 ? (double)tile_codes * (double)n_strings / (double)n_codes : 4096.0;
     int sh = kCoarseShiftMin;
@@ -242,6 +251,7 @@ fd_status run_decode(const Args& a) {
     p.n_tiles = pl.n_tiles;
     p.tile_codes = pl.T;
     p.g_shift = pl.g_shift;
+    p.off_pref = offsets_prefetch_count(a.codec, a.n_codes, a.n_strings, pl.T, pl.g_shift);
     p.coarse = (int64_t*)(ws + pl.off_coarse);
     p.err = (unsigned long long*)(ws + kOffErr);
     p.counters = (unsigned*)(ws + kOffCounters);
@@ -525,6 +535,11 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     p.n_tiles = tp.dec.n_tiles;
     p.tile_codes = tp.dec.T;
     p.g_shift = tp.dec.g_shift;
+    {
+        const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+        p.off_pref = offsets_prefetch_count(tp.codec2, (int64_t)(mean * (double)n_rows) + 1, n_rows, tp.dec.T,
+                                            tp.dec.g_shift);
+    }
     p.coarse = (int64_t*)(ws + tp.dec.off_coarse);
     p.err = err;
     p.counters = counters;

@@ -75,6 +75,7 @@ struct DecodeParams {
     int64_t tile_codes;            // T
     int64_t* coarse;               // per tile: the coarse sample group its strings start in
     int32_t g_shift;               // log2 of the coarse sample stride G
+    int32_t off_pref;              // code offsets a tile prefetches from its coarse sample on
     // workspace
     unsigned long long* err;
     unsigned* counters;            // [0] tile counter, [1] finished workgroups
@@ -135,6 +136,10 @@ int64_t tiles_of(int64_t n_codes, int64_t tile_codes);
 // The coarse index stride of a column (log2): about half the strings of a
 // tile at the column's mean codes per string, within [2^6, 2^10].
 int coarse_shift(int64_t n_codes, int64_t n_strings, int64_t tile_codes);
+// How many code offsets a tile prefetches from its coarse sample on: its
+// expected strings with a margin plus one stride of the index, at most what
+// the kernel holds (256 FSST-8, 1,024 OnPair).
+int offsets_prefetch_count(fd_codec c, int64_t n_codes, int64_t n_strings, int64_t tile_codes, int g_shift);
 // The coarse index of a column into p.coarse (n_tiles words, zeroed before),
 // or of every column of a batch group (cols: the device table; max_samples:
 // the largest ceil(n_strings / G) of its columns).

@@ -54,6 +54,16 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
+// The thread's index as an opaque value: the decode loop runs for many
+// tiles, and values derived from the index would otherwise be hoisted out of
+// it and kept live (spilled) across the whole loop body; recomputing them
+// costs an instruction or two.
+__device__ __forceinline__ unsigned ltid() {
+    unsigned t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // values the workgroup shares through LDS are uniform: keep them in SGPRs
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
@@ -232,6 +242,11 @@ template <> struct Cfg<kOnpair12> {
     static constexpr int WIN = kWinOnpair;
 };
 template <int CODEC> constexpr bool kPacked12 = CODEC == kOnpair12;
+// Code offsets each thread prefetches at a tile's start (the first block of
+// the tile's strings, read from the coarse index's sample on): enough for the
+// usual strings per tile (about 100 FSST-8 log lines, 500-800 short OnPair
+// strings) and the entries before the tile's first string.
+template <int CODEC> constexpr int kOffR = CODEC == kFsst8 ? 1 : 4;
 template <int CODEC> constexpr bool kIsOnpair = CODEC == kOnpair16 || CODEC == kOnpair12;
 
 // bytes of a 12-bit packed stream of n codes
@@ -243,6 +258,7 @@ template <int CODEC> struct SmemT {
     uint8_t pre8[kWG * P * CPC];          // per code: prefix inside its chunk | escape bit
     uint32_t lane_pre[kWG];               // per lane: exclusive prefix inside the tile
     uint16_t cbase[kWG * P];              // per chunk: prefix inside its lane
+    int64_t off[1 + kWG * kOffR<CODEC>];  // code offsets S0 - 1 .. S0 + kWG R - 1 of the tile (prefetched)
     uint64_t fsst_tab[CODEC == kFsst8 ? 256 : 1];
     uint8_t fsst_len[CODEC == kFsst8 ? 256 : 4];
     alignas(16) uint8_t len12[kPacked12<CODEC> ? 4096 : 16];   // 12-bit codes: the lengths of their 4,096 tokens
@@ -250,9 +266,9 @@ template <int CODEC> struct SmemT {
     uint32_t wlast[kNWave];               // total of each wave's last lane
     uint32_t wpar[kNWave];
     int64_t hdr[2];                       // the column's decode range [code_offsets[0], code_offsets[n])
-    int64_t gix[2];                       // coarse groups of this tile and the next
     int64_t cur2[2];                      // stored cursors of this tile and the next (expand mode)
-    int64_t emin;                         // offsets: the first code-offset index past the tile
+    int64_t pfirst[2][kNWave];            // offsets: per-wave first index past the tile, double-buffered
+    uint32_t vote[2][kNWave];             // offsets: per-wave "first string found" flags
     uint32_t cin;                         // FSST-8: escape parity entering the tile
     int64_t cursor;
     uint32_t wbase[kMaxWin + 1];          // staging windows: first output byte of each
@@ -327,6 +343,31 @@ __device__ __forceinline__ void column_range(const DecodeParams& p, int64_t& ca,
 // to the start of the decode range ca (one wave; a loop step per 64 bytes of
 // run).  In valid data no string ends inside an escape, so this stream-level
 // parity is the one the string's own decode has.
+// The lane's byte of the first window, a - 1 - lane (0x100 before ca): loaded
+// ahead, one tile early, by fsst_window_byte.
+__device__ __forceinline__ uint32_t fsst_window_byte(const uint8_t* codes, int64_t ca, int64_t a) {
+    const int64_t q = a - 1 - (int64_t)lane_id();
+    return q >= ca ? (uint32_t)codes[q] : 0x100u;
+}
+
+__device__ __forceinline__ uint32_t fsst_carry_in_from(const uint8_t* codes, int64_t ca, int64_t a, uint32_t first) {
+    const uint64_t m0 = __ballot(first != 0xFFu);
+    if (m0) return (uint32_t)(((int64_t)__ffsll((unsigned long long)m0) - 1) & 1);
+    const int64_t lane = (int64_t)lane_id();
+    int64_t run = 64;
+    for (int64_t q0 = a - 65; q0 >= ca; q0 -= 64) {
+        const int64_t q = q0 - lane;
+        const bool stop = q < ca || codes[q] != 0xFF;
+        const uint64_t m = __ballot(stop);
+        if (m) {
+            run += (int64_t)__ffsll((unsigned long long)m) - 1;
+            break;
+        }
+        run += 64;
+    }
+    return (uint32_t)(run & 1);
+}
+
 __device__ __forceinline__ uint32_t fsst_carry_in(const uint8_t* codes, int64_t ca, int64_t a) {
     const int64_t lane = (int64_t)lane_id();
     int64_t run = 0;
@@ -407,10 +448,10 @@ __device__ __forceinline__ void codes_load_at(const DecodeParams& p, const Geom&
     }
 }
 
-// The chunks of super-pass sp that lane threadIdx.x owns.
+// The chunks of super-pass sp that lane ltid() owns.
 template <int CODEC>
 __device__ __forceinline__ void codes_load(const DecodeParams& p, const Geom& g, int sp, uint32_t w[][4]) {
-    codes_load_at<CODEC>(p, g, (int64_t)sp * kWG * Cfg<CODEC>::P + (int64_t)threadIdx.x * Cfg<CODEC>::P, w);
+    codes_load_at<CODEC>(p, g, (int64_t)sp * kWG * Cfg<CODEC>::P + (int64_t)ltid() * Cfg<CODEC>::P, w);
 }
 
 // Per-lane state of one super-pass between its length scan and its emit.
@@ -432,7 +473,7 @@ template <int CODEC> struct Lane {
 template <typename S>
 __device__ void fsst_build_table(S& s, const DecodeParams& p) {
     constexpr int CPT = 256 / kWG;     // codes per thread, consecutive
-    const unsigned tid = threadIdx.x;
+    const unsigned tid = ltid();
     if (p.fsst_tab) {                  // prepared with the dictionary: a copy
 #pragma unroll
         for (int i = 0; i < CPT; i++) {
@@ -490,7 +531,7 @@ __device__ void fsst_build_table(S& s, const DecodeParams& p) {
 // dictionary.
 template <typename S>
 __device__ void len12_load(S& s, const DecodeParams& p) {
-    for (unsigned i = threadIdx.x; i < 4096 / 16; i += kWG) ((uint4*)s.len12)[i] = ((const uint4*)p.tok_len)[i];
+    for (unsigned i = ltid(); i < 4096 / 16; i += kWG) ((uint4*)s.len12)[i] = ((const uint4*)p.tok_len)[i];
     __syncthreads();
 }
 
@@ -572,7 +613,7 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
                                             const __amdgpu_buffer_rsrc_t& r_tok) {
     using C = Cfg<CODEC>;
     constexpr int P = C::P, CPC = C::CPC, CPL = C::CPL;
-    const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned tid = ltid(), lane = tid & 63, wv = tid >> 6;
     const int64_t k0 = (int64_t)sp * kWG * P + (int64_t)tid * P;
     const int64_t q0 = g.pos0 + k0 * CPC;
     {
@@ -862,7 +903,7 @@ __device__ __forceinline__ void drain(S& s, const DecodeParams& p, int64_t O, in
     const int64_t cap_rel = p.out_cap - X;
     const int hi_all = (int)min((int64_t)len, max(cap_rel, (int64_t)0));
     const int nch = (shift + len + 15) >> 4;
-    for (int c = threadIdx.x; c < nch; c += kWG) {
+    for (int c = ltid(); c < nch; c += kWG) {
         const int s0 = c * 16 - shift;
         if (s0 >= 0 && s0 + 16 <= hi_all) {
             // five dword-aligned LDS reads realigned in registers (a byte-granular
@@ -880,14 +921,43 @@ __device__ __forceinline__ void drain(S& s, const DecodeParams& p, int64_t O, in
     }
     // the partial chunks: the first one and the one holding the last byte
     // below the capacity, one byte per lane
-    if (threadIdx.x < 32 && hi_all > 0) {
+    if (ltid() < 32 && hi_all > 0) {
         const int c_last = (shift + hi_all - 1) >> 4;
-        const int c = threadIdx.x < 16 ? 0 : c_last;
+        const int c = ltid() < 16 ? 0 : c_last;
         const int s0 = c * 16 - shift;
         const bool full = s0 >= 0 && s0 + 16 <= hi_all;
-        const int y = s0 + (int)(threadIdx.x & 15u);
-        if (!full && (threadIdx.x < 16 || c_last != 0) && y >= 0 && y < hi_all) p.out[X + y] = s.stage[y];
+        const int y = s0 + (int)(ltid() & 15u);
+        if (!full && (ltid() < 16 || c_last != 0) && y >= 0 && y < hi_all) p.out[X + y] = s.stage[y];
     }
+}
+
+// A thread's share of the prefetched code offsets: entries S0 + r kWG + tid
+// (consecutive threads, consecutive entries), and thread 0 also the entry
+// before S0.
+template <int CODEC, typename IDX> struct OffRegs {
+    static constexpr int R = kOffR<CODEC>;
+    IDX v[R];
+    IDX before;
+};
+
+template <int CODEC, typename IDX>
+__device__ __forceinline__ void offsets_prefetch(const DecodeParams& p, int64_t S0, OffRegs<CODEC, IDX>& r) {
+    const IDX* co = (const IDX*)p.code_off;
+    const int64_t i0 = S0 + (int64_t)ltid();
+    const int64_t lim = min(S0 + (int64_t)p.off_pref - 1, p.n_strings);
+#pragma unroll
+    for (int k = 0; k < OffRegs<CODEC, IDX>::R; k++)
+        r.v[k] = (i0 + (int64_t)k * kWG <= lim) ? co[i0 + (int64_t)k * kWG] : (IDX)0;
+    r.before = (ltid() == 0 && S0 > 0) ? co[S0 - 1] : (IDX)0;
+}
+
+template <int CODEC, typename IDX, typename S>
+__device__ __forceinline__ void offsets_stage(S& s, const OffRegs<CODEC, IDX>& r) {
+    constexpr int R = OffRegs<CODEC, IDX>::R;
+    const unsigned tid = ltid();
+#pragma unroll
+    for (int k = 0; k < R; k++) s.off[1 + k * kWG + tid] = (int64_t)r.v[k];
+    if (tid == 0) s.off[0] = (int64_t)r.before;
 }
 
 // Decoded bytes of the tile's codes before code position x (a <= x <= b).
@@ -918,53 +988,87 @@ __device__ __forceinline__ uint32_t local_prefix(S& s, const Geom& g, int64_t x,
 template <int CODEC, typename IDX, bool OUT, typename S>
 __device__ __forceinline__ void tile_offsets(S& s, const DecodeParams& p, const Geom& g, int64_t t, int64_t O,
                                              uint32_t total, uint32_t cin, int64_t ca, int64_t gcur, int64_t gnext) {
+    constexpr int R = kOffR<CODEC>;
     const IDX* co = (const IDX*)p.code_off;
     IDX* oo = (IDX*)p.out_off;
+    const unsigned tid = ltid(), lane = tid & 63, w = tid >> 6;
     const int64_t n = p.n_strings;
     const int64_t G = (int64_t)1 << p.g_shift;
     const int64_t S0 = min(max(gcur, (int64_t)0) << p.g_shift, n);
     bool bad = false, found = false;
-    int64_t e = INT64_MAX;
-    for (int64_t base = S0; base <= n; base += kWG) {
-        const int64_t i = base + (int64_t)threadIdx.x;
-        const bool in = i <= n;
-        int64_t v = 0;
-        if (in) {
-            v = (int64_t)co[i];
-            if (i == 0) bad |= v < 0;
-            else bad |= v < (int64_t)co[i - 1];
-            if (i == n) bad |= v > p.n_codes;
-        }
-        const bool past = in && v >= g.own_hi;
-        if (in && !past && v >= g.own_lo) {
-            const int64_t x = min(max(v, g.a), g.b);
-            if constexpr (OUT) oo[i] = (IDX)(O + (int64_t)local_prefix<CODEC>(s, g, x, total));
-            if constexpr (CODEC == kFsst8) {
-                // the string ending at v ends with an escape iff v is a literal position
-                if (v > ca && x == v) {
-                    const bool esc = (x == g.a) ? (cin != 0)
-                                                : ((s.pre8[(int)(x - 1 - g.pos0)] & 0x80u) != 0u);
-                    if (esc) atomicMin(p.err, (unsigned long long)data_error_key(x - 1, FD_EESCAPE));
+    int64_t e = INT64_MAX;               // the first index at or past own_hi
+    // blocks of up to kWG R entries, entry base + k kWG + tid for thread tid:
+    // the first block is the off_pref entries prefetched into LDS, any further
+    // one (a tile with many strings) is loaded here
+    int64_t span = p.off_pref;
+    for (int64_t base = S0, blk = 0; base <= n; base += span, span = (int64_t)kWG * R, blk++) {
+        int64_t wfirst = INT64_MAX;      // the wave's first entry at or past own_hi
+        bool wfound = false;
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int64_t idx = (int64_t)k * kWG + tid;
+            const int64_t i = base + idx;
+            const bool in = idx < span && i <= n;
+            int64_t v = 0, vp = 0;
+            if (in) {
+                if (blk == 0) {
+                    v = s.off[1 + idx];
+                    vp = s.off[idx];
+                } else {
+                    v = (int64_t)co[i];
+                    vp = i > 0 ? (int64_t)co[i - 1] : 0;
+                }
+                if (i == 0) bad |= v < 0;
+                else bad |= v < vp;
+                if (i == n) bad |= v > p.n_codes;
+            }
+            const bool past = in && v >= g.own_hi;
+            if (in && !past && v >= g.own_lo) {
+                const int64_t x = min(max(v, g.a), g.b);
+                if constexpr (OUT) oo[i] = (IDX)(O + (int64_t)local_prefix<CODEC>(s, g, x, total));
+                if constexpr (CODEC == kFsst8) {
+                    // the string ending at v ends with an escape iff v is a literal position
+                    if (v > ca && x == v) {
+                        const bool esc = (x == g.a) ? (cin != 0)
+                                                    : ((s.pre8[(int)(x - 1 - g.pos0)] & 0x80u) != 0u);
+                        if (esc) atomicMin(p.err, (unsigned long long)data_error_key(x - 1, FD_EESCAPE));
+                    }
                 }
             }
+            // entries rise with k, then with the lane: the wave's first past one is
+            // in the lowest k with any, at the lowest such lane
+            const uint64_t bp = __ballot(past);
+            if (bp && wfirst == INT64_MAX)
+                wfirst = base + (int64_t)k * kWG + (int64_t)(w * 64) + (int64_t)__ffsll((unsigned long long)bp) - 1;
+            wfound = wfound || __ballot(in && v >= g.own_lo) != 0;
         }
-        if (past) atomicMin((unsigned long long*)&s.emin, (unsigned long long)i);
-        const bool any_past = __syncthreads_or(past);
-        found = found || __syncthreads_or(in && v >= g.own_lo);
-        if (any_past) break;
+        // the workgroup's: through LDS, slots alternating between blocks (one barrier each)
+        if (lane == 0) {
+            s.pfirst[blk & 1][w] = wfirst;
+            s.vote[blk & 1][w] = wfound ? 1u : 0u;
+        }
+        __syncthreads();
+        bool any_found = false;
+#pragma unroll
+        for (int q = 0; q < kNWave; q++) {
+            e = min(e, s.pfirst[blk & 1][q]);
+            any_found = any_found || s.vote[blk & 1][q] != 0u;
+        }
+        e = uniform64(e);
+        found = found || any_found;
+        if (e != INT64_MAX) break;
         // on valid offsets the tile's first string comes by index S0 + G (or
         // there is none: then the column ends before the tile, and S0 = n)
-        const int64_t last = base + kWG - 1;
+        const int64_t last = base + span - 1;
         if (!found && last >= S0 + G && last < n) {
             bad = true;
             break;
         }
     }
-    e = s.emin;
-    if (threadIdx.x == 0 && t + 1 < p.n_tiles) {
+    if (tid == 0 && t + 1 < p.n_tiles) {
         const int64_t S1 = min(max(gnext, (int64_t)0) << p.g_shift, n);
-        if (e == INT64_MAX) e = n + 1;
-        if (e < S1 || e > S1 + G) bad = true;
+        const int64_t ee = (e == INT64_MAX) ? n + 1 : e;
+        if (ee < S1 || ee > S1 + G) bad = true;
     }
     if (bad) record_error(p.err, kRankOffsets, FD_EOFFSETS);
 }
@@ -1006,7 +1110,7 @@ __device__ __forceinline__ void lb_publish(unsigned long long* a, uint64_t v) {
 // the missing values of the first round, again (one round trip)
 template <bool PREV>
 __device__ __forceinline__ void lb_reload(const DecodeParams& p, int64_t blk, int jt, LookBack& lb) {
-    const unsigned lane = threadIdx.x & 63;
+    const unsigned lane = ltid() & 63;
     if ((int)lane < jt && (lb.in_v & kFlagMask) == 0) lb.in_v = lb_load(&p.tagg[(blk << kBlkShift) + lane]);
     if (PREV && blk >= 1 && (int)lane < kBlk && (lb.prev_v & kFlagMask) == 0)
         lb.prev_v = lb_load(&p.tagg[((blk - 1) << kBlkShift) + lane]);
@@ -1016,7 +1120,7 @@ __device__ __forceinline__ void lb_reload(const DecodeParams& p, int64_t blk, in
 
 template <bool PREV>
 __device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
-    const unsigned lane = threadIdx.x & 63;
+    const unsigned lane = ltid() & 63;
     const int64_t blk = t >> kBlkShift;
     const int jt = (int)(t & (kBlk - 1));
     if (lane == 0)
@@ -1032,7 +1136,7 @@ __device__ __forceinline__ void lookback_issue(const DecodeParams& p, int64_t t,
 // Block b - 1's aggregate from its tiles, when its state is still empty and
 // every tile's aggregate has arrived (lane 0 holds block b - 1's state).
 __device__ __forceinline__ bool lb_prev_from_tiles(LookBack& lb, uint64_t& agg) {
-    const unsigned lane = threadIdx.x & 63;
+    const unsigned lane = ltid() & 63;
     const uint64_t v0 = __shfl(lb.blk_v, 0);
     if ((v0 & kFlagMask) != 0 || __ballot((lb.prev_v & kFlagMask) == 0) != 0) return false;
     agg = wave_sum_u64(lb.prev_v & kValueMask);
@@ -1046,7 +1150,7 @@ __device__ __forceinline__ bool lb_prev_from_tiles(LookBack& lb, uint64_t& agg) 
 // still missing are loaded again.
 template <bool PREV>
 __device__ __forceinline__ void lookback_mid(const DecodeParams& p, int64_t t, uint64_t A, LookBack& lb) {
-    const unsigned lane = threadIdx.x & 63;
+    const unsigned lane = ltid() & 63;
     const int64_t blk = t >> kBlkShift;
     const int jt = (int)(t & (kBlk - 1));
     if (__ballot((lb.in_v & kFlagMask) == 0) == 0) {
@@ -1062,7 +1166,7 @@ __device__ __forceinline__ void lookback_mid(const DecodeParams& p, int64_t t, u
 // Completes the look-back; returns the exclusive prefix of tile t.
 template <bool PREV>
 __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64_t t, uint64_t A, LookBack lb) {
-    const unsigned lane = threadIdx.x & 63;
+    const unsigned lane = ltid() & 63;
     const int64_t blk = t >> kBlkShift;
     const int jt = (int)(t & (kBlk - 1));
     bool fail = false;
@@ -1174,7 +1278,7 @@ template <int CODEC, typename IDX, int MODE, typename SRC>
 __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     using C = Cfg<CODEC>;
     constexpr int P = C::P;
-    const unsigned tid = threadIdx.x, wv = tid >> 6;
+    const unsigned tid = ltid(), wv = tid >> 6;
     const int64_t n_all = src.n_tiles();
     unsigned* const ctr = src.counter();
 
@@ -1184,6 +1288,11 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     int col = -1;
     const void* table_src = nullptr;      // the table in LDS (FSST-8 symbols, 12-bit lengths)
     int64_t ca = 0, cb = 0;               // the column's decode range
+    int64_t t_first = 0, t_last = -1;     // its tiles with work (divisions once per column)
+    // loaded during the previous tile for tile id pf_v (same column): its
+    // coarse groups and, FSST-8, wave 0's bytes of the window before its first code
+    int64_t pf_v = -1, pf_g0 = 0, pf_g1 = 0;
+    uint32_t pf_byte = 0;
     if constexpr (CODEC == kFsst8 && !SRC::kBatch) {
         fsst_build_table(s, src.params(0));
         table_src = (const void*)1;
@@ -1219,10 +1328,12 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             __syncthreads();
             ca = uniform64(s.hdr[0]);
             cb = uniform64(s.hdr[1]);
+            t_first = first_tile(p, ca, cb);
+            t_last = last_tile(p, ca, cb);
         }
         const int64_t t = v - src.first(col);
-        const bool after = t > last_tile(p, ca, cb);
-        if (after || t < first_tile(p, ca, cb)) {
+        const bool after = t > t_last;
+        if (after || t < t_first) {
             // a tile outside the decode range: no codes, no strings.  Past the
             // tile that holds the range's end, no later tile of the column looks
             // at it; before the one holding its start, the look-back of the tiles
@@ -1249,12 +1360,18 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         const __amdgpu_buffer_rsrc_t r_tok = make_rsrc(
             kIsOnpair<CODEC> ? (const void*)p.tok16 : (const void*)p.codes, kIsOnpair<CODEC> ? 65536u * 16u : 0u);
 
+        // the coarse groups of this tile and the next (uniform loads, usually
+        // made during the previous tile), the codes, then the first block of
+        // the tile's code offsets: all in flight together, the offsets waited
+        // for only after the length scan
+        const bool pf = pf_v == v;
+        const int64_t gcur = pf ? pf_g0 : uniform64(p.coarse[t]);
+        const int64_t gnext = pf ? pf_g1 : ((t + 1 < p.n_tiles) ? uniform64(p.coarse[t + 1]) : 0);
         Lane<CODEC> L;
         codes_load<CODEC>(p, g, 0, L.w);
+        OffRegs<CODEC, IDX> orr;
+        offsets_prefetch<CODEC, IDX>(p, min(max(gcur, (int64_t)0) << p.g_shift, p.n_strings), orr);
         if (tid == 0) {
-            s.gix[0] = p.coarse[t];
-            s.gix[1] = (t + 1 < p.n_tiles) ? p.coarse[t + 1] : 0;
-            s.emin = INT64_MAX;
             if constexpr (MODE == kModeExpand) {
                 s.cur2[0] = (int64_t)p.tagg[t];
                 s.cur2[1] = (int64_t)p.tagg[t + 1];
@@ -1262,7 +1379,9 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         }
         if constexpr (CODEC == kFsst8) {
             if (wv == 0) {
-                const uint32_t ci = fsst_carry_in(p.codes, min(max(ca, (int64_t)0), p.n_codes), g.a);
+                const int64_t ca_c = min(max(ca, (int64_t)0), p.n_codes);
+                const uint32_t first = pf ? pf_byte : fsst_window_byte(p.codes, ca_c, g.a);
+                const uint32_t ci = fsst_carry_in_from(p.codes, ca_c, g.a, first);
                 if (tid == 0) s.cin = ci;
             }
         }
@@ -1272,13 +1391,15 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         const uint32_t cin = carry;
 
         const uint32_t tot = lengths<CODEC>(s, p, g, 0, L, carry, true, r_len, r_tok);
+        offsets_stage<CODEC, IDX>(s, orr);      // read after later barriers
         if constexpr (MODE == kModeTotals) {
             // the sidecar build: every check of the decode, the tile's total, no output
             if (tid == 0) {
                 p.tagg[t] = tot;
                 s.next_id = (int32_t)atomicAdd(ctr, 1u);
             }
-            tile_offsets<CODEC, IDX, false>(s, p, g, t, 0, tot, cin, ca, uniform64(s.gix[0]), uniform64(s.gix[1]));
+            __syncthreads();            // the staged offsets
+            tile_offsets<CODEC, IDX, false>(s, p, g, t, 0, tot, cin, ca, gcur, gnext);
             v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
             __syncthreads();            // this tile's LDS is free for the next
             continue;
@@ -1317,6 +1438,26 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         if (tid == 0) s.next_id = (int32_t)atomicAdd(ctr, 1u);
         __syncthreads();
         const int64_t cursor = uniform64(s.cursor);
+        // the next tile's coarse groups and first window, loaded now (they
+        // arrive during this tile's drain and offsets)
+        {
+            const int64_t vn = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
+            pf_v = -1;
+            if (vn < n_all && src.column(vn, col) == col) {
+                const int64_t tn = vn - src.first(col);
+                if (tn >= t_first && tn <= t_last) {
+                    pf_v = vn;
+                    pf_g0 = uniform64(p.coarse[tn]);
+                    pf_g1 = (tn + 1 < p.n_tiles) ? uniform64(p.coarse[tn + 1]) : 0;
+                    if constexpr (CODEC == kFsst8) {
+                        if (wv == 0) {
+                            const Geom gn = make_geom<CODEC>(p, tn, ca, cb);
+                            pf_byte = fsst_window_byte(p.codes, min(max(ca, (int64_t)0), p.n_codes), gn.a);
+                        }
+                    }
+                }
+            }
+        }
         if (cursor >= 0) {
             const int nwin = (int)uniform32(s.nwin);
             for (int win = 0; win < nwin; win++) {
@@ -1331,8 +1472,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 __syncthreads();
                 drain(s, p, cursor, win);
             }
-            tile_offsets<CODEC, IDX, true>(s, p, g, t, cursor, tot, cin, ca, uniform64(s.gix[0]),
-                                           uniform64(s.gix[1]));
+            tile_offsets<CODEC, IDX, true>(s, p, g, t, cursor, tot, cin, ca, gcur, gnext);
             if (tid == 0) {
                 const int64_t endv = cursor + (int64_t)tot;
                 if (sizeof(IDX) == 4 && endv > (int64_t)INT32_MAX) record_error(p.err, kRankOverflow, FD_EOVERFLOW);
@@ -1356,7 +1496,7 @@ __global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode(DecodeParams p
     // the last workgroup to finish publishes the status
     if (MODE != kModeTotals) {
         __threadfence();
-        if (threadIdx.x == 0) {
+        if (ltid() == 0) {
             const unsigned prev = atomicAdd(&p.counters[1], 1u);
             if (prev == gridDim.x - 1) {
                 __threadfence();
@@ -1382,16 +1522,16 @@ __global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode_batch(const De
 __global__ void __launch_bounds__(256) k_batch_status(const unsigned long long* errs, int32_t n_cols,
                                                       int32_t* status, int32_t* status2) {
     __shared__ int s_first;
-    if (threadIdx.x == 0) s_first = n_cols;
+    if (ltid() == 0) s_first = n_cols;
     __syncthreads();
-    for (int c = threadIdx.x; c < n_cols; c += blockDim.x) {
+    for (int c = ltid(); c < n_cols; c += blockDim.x) {
         const unsigned long long e = errs[c];
         const int st = (e == ~0ull) ? FD_OK : (int)(e & 15ull);
         if (status) status[c] = st;
         if (st != FD_OK) atomicMin(&s_first, c);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (ltid() == 0) {
         int st = FD_OK;
         if (s_first < n_cols) {
             const unsigned long long e = errs[s_first];
@@ -1404,7 +1544,7 @@ __global__ void __launch_bounds__(256) k_batch_status(const unsigned long long* 
 
 // Workspace reset of a batch: n words zeroed, then the n_cols error words set to "none".
 __global__ void k_batch_reset(unsigned long long* z, int64_t n, unsigned long long* errs, int32_t n_cols) {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + ltid();
     for (int64_t k = i0; k < n; k += (int64_t)gridDim.x * blockDim.x) z[k] = 0;
     for (int64_t k = i0; k < n_cols; k += (int64_t)gridDim.x * blockDim.x) errs[k] = ~0ull;
 }
@@ -1413,7 +1553,7 @@ __global__ void k_batch_reset(unsigned long long* z, int64_t n, unsigned long lo
 // workspace reset, cursor scan (three-phase mode), OnPair dictionary repack
 // --------------------------------------------------------------------------
 __global__ void k_reset(unsigned long long* err, unsigned* counters, unsigned long long* z, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + ltid();
     if (i == 0) {
         if (err) *err = ~0ull;
         counters[0] = 0;
@@ -1430,7 +1570,7 @@ __global__ void __launch_bounds__(1024) k_scan_totals(unsigned long long* v, int
                                                       int32_t* status2) {
     __shared__ uint64_t s_w[16];
     __shared__ uint64_t s_carry;
-    const unsigned tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const unsigned tid = ltid(), lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_carry = 0;
     __syncthreads();
     for (int64_t base = 0; base < n; base += 1024) {
@@ -1470,7 +1610,7 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
                                                          int* bad_flag) {
     __shared__ uint32_t s_w[4];
     __shared__ uint64_t s_red[4];
-    const unsigned tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const unsigned tid = ltid(), lane = tid & 63, w = tid >> 6;
     const int32_t c0 = (int32_t)blockIdx.x * 256;
     bool bad = false;
     uint64_t before = 0;
@@ -1519,7 +1659,7 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
 // OnPair-16 token lengths as nibbles in LDS (32 KiB): 16 lengths (bytes of
 // 0..16) become 8 bytes, code 2k in the low nibble of byte k, 16 stored as 0.
 __device__ __forceinline__ void nib_table_load(uint8_t* s_nib, const uint8_t* tok_len) {
-    for (unsigned i = threadIdx.x; i < 65536 / 16; i += blockDim.x) {
+    for (unsigned i = ltid(); i < 65536 / 16; i += blockDim.x) {
         const uint4 a = ((const uint4*)tok_len)[i];
         const uint32_t x[4] = {a.x, a.y, a.z, a.w};
         uint32_t h[4];
@@ -1549,7 +1689,7 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
     __shared__ uint8_t s_len[256];
     __shared__ alignas(16) uint8_t s_len12[kPacked12<CODEC> ? 4096 : 16];
     __shared__ alignas(16) uint8_t s_nib[CODEC == kOnpair16 ? 32768 : 16];
-    const unsigned tid = threadIdx.x, lane = tid & 63;
+    const unsigned tid = ltid(), lane = tid & 63;
     if constexpr (kPacked12<CODEC>) {             // 12-bit codes: their 4,096 lengths
         for (unsigned i = tid; i < 4096 / 16; i += kWG) ((uint4*)s_len12)[i] = ((const uint4*)p.tok_len)[i];
         __syncthreads();
@@ -1687,7 +1827,7 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
     __shared__ uint32_t s_wpar[kNWave];
     __shared__ uint64_t s_wsum[kNWave];
     __shared__ int64_t s_nb[2];
-    const unsigned tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned tid = ltid(), lane = tid & 63, wv = tid >> 6;
     __shared__ uint32_t s_cin;
     const void* table = nullptr;                  // the dictionary whose lengths are in LDS
     int col = 0, hdr_col = -1;
@@ -1890,7 +2030,7 @@ __device__ __forceinline__ void coarse_column(const DecodeParams& p) {
     const int64_t cb = min(max((int64_t)co[n], (int64_t)0), p.n_codes);
     const int64_t t_max = min(cb / T + 1, nt - 1);
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j - (int64_t)lane <= J; j += step) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + ltid(); j - (int64_t)lane <= J; j += step) {
         int64_t t_lo = 0, len = 0;
         if (j <= J) {
             const int64_t c0 = (int64_t)co[min(j << sh, n)];
@@ -1936,7 +2076,7 @@ __global__ void __launch_bounds__(256) k_coarse_batch(const DecodeParams* __rest
 constexpr int kScanBlock = 1024;
 __global__ void __launch_bounds__(256) k_block_sums(const unsigned long long* v, int64_t n, unsigned long long* bsum) {
     __shared__ uint64_t s_w[kNWave];
-    const unsigned tid = threadIdx.x;
+    const unsigned tid = ltid();
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
     uint64_t sum = 0;
 #pragma unroll
@@ -1958,7 +2098,7 @@ __global__ void __launch_bounds__(256) k_block_sums(const unsigned long long* v,
 __global__ void __launch_bounds__(256) k_block_scan(unsigned long long* v, int64_t n, const unsigned long long* bsum) {
     __shared__ uint64_t s_w[kNWave];
     constexpr int R = kScanBlock / 256;
-    const unsigned tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const unsigned tid = ltid(), lane = lane_id(), w = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * R;   // R consecutive entries per thread
     uint64_t x[R], tsum = 0;
 #pragma unroll
@@ -2019,7 +2159,7 @@ __global__ void __launch_bounds__(256) k_take_sizes(const int64_t* rows, int64_t
                                                     int64_t n_strings, int64_t n_codes, unsigned long long* bsum,
                                                     unsigned long long* err) {
     __shared__ uint64_t s_w[kNWave];
-    const unsigned tid = threadIdx.x, w = tid >> 6;
+    const unsigned tid = ltid(), w = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTakeRows;
     uint64_t sum = 0;
 #pragma unroll
@@ -2050,7 +2190,7 @@ __global__ void __launch_bounds__(256) k_take_offsets(const int64_t* rows, int64
                                                       IDX* new_off, int64_t* src, unsigned long long* err) {
     __shared__ uint64_t s_w[kNWave];
     constexpr int R = kTakeRows / 256;
-    const unsigned tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const unsigned tid = ltid(), lane = lane_id(), w = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTakeRows;
     int64_t a[R], len[R];
     uint64_t tsum = 0;
@@ -2099,7 +2239,7 @@ __global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_
                                                    const IDX* new_off, const int64_t* src, uint8_t* dst) {
     __shared__ int64_t s_off[kTakeRows + 1];
     __shared__ int64_t s_src[kTakeRows];
-    const unsigned tid = threadIdx.x;
+    const unsigned tid = ltid();
     const int64_t base = (int64_t)blockIdx.x * rows_per_wg;
     const int nr = (int)min((int64_t)rows_per_wg, n_rows - base);
     for (int j = tid; j <= nr; j += 256) {
