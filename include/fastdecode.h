@@ -221,6 +221,23 @@ fd_status fd_decode_ex(const fd_dict *dict, const void *codes, int64_t n_codes, 
                        void *workspace, size_t workspace_bytes, int32_t *status, unsigned flags,
                        const fd_tuning *tuning, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fd_decode_ex
+ * without a workspace argument.  Its scratch (tile totals, look-back states,
+ * the coarse string index, counters and the error word) is a 4 MiB array the
+ * library holds in device memory on each GPU it runs on, until the process
+ * ends; nothing is allocated during the call.  A column needs about 16 bytes
+ * per tile of it (a tile is tile_codes codes), so a column of up to about
+ * 2.1 billion FSST-8 codes or 1.06 billion OnPair codes fits; a larger one
+ * returns FD_EINVAL before the device is touched.  dict must be a prepared
+ * dictionary; other arguments and statuses as fd_decode_ex.  Every call on one
+ * GPU uses that GPU's one array: calls that overlap on a GPU (other streams,
+ * other host threads) race and must be ordered by the caller. */
+fd_status fd_decode_noalloc(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets,
+                            int index_bits, int64_t n_strings, void *out_offsets, uint8_t *out_bytes,
+                            int64_t out_capacity, int32_t *status, unsigned flags, const fd_tuning *tuning,
+                            void *hip_stream);
+
 /* ------------------------------------------------------------------------- */
 /* Persisted output positions (sidecar)                                       */
 /* ------------------------------------------------------------------------- */

@@ -118,6 +118,8 @@ def lib():
     L.fd_decode.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, P]
     L.fd_decode_ex.restype = ctypes.c_int
     L.fd_decode_ex.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, ctypes.POINTER(Tuning), P]
+    L.fd_decode_noalloc.restype = ctypes.c_int
+    L.fd_decode_noalloc.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, U, ctypes.POINTER(Tuning), P]
     L.fd_sidecar_layout.restype = ctypes.c_int
     L.fd_sidecar_layout.argtypes = [ctypes.c_int, I64, I64, ctypes.POINTER(Tuning), ctypes.POINTER(I32),
                                     ctypes.POINTER(I64)]
@@ -287,6 +289,17 @@ def decode_into(d: Dict, codes, code_off, out_off, out_bytes, workspace, status=
                               _ptr(out_bytes), out_bytes.numel() if out_bytes is not None else 0, _ptr(workspace),
                               workspace.numel(), _ptr(status), ASYNC if async_ else 0, _tuning(tuning),
                               _stream_handle(stream))
+
+
+def decode_noalloc_into(d: Dict, codes, code_off, out_off, out_bytes, status=None, async_=False, tuning=None,
+                        stream=None, n_codes=None) -> int:
+    """fd_decode_noalloc (no workspace: the library's static device scratch);
+    returns the fd_status (FD_OK when enqueued with async_=True)."""
+    return lib().fd_decode_noalloc(d.handle, _ptr(codes),
+                                   int(codes_in(d.codec, codes) if n_codes is None else n_codes), _ptr(code_off),
+                                   _index_bits(code_off), code_off.numel() - 1, _ptr(out_off), _ptr(out_bytes),
+                                   out_bytes.numel() if out_bytes is not None else 0, _ptr(status),
+                                   ASYNC if async_ else 0, _tuning(tuning), _stream_handle(stream))
 
 
 def decode(d: Dict, codes, code_off, tuning=None, stream=None):

@@ -235,7 +235,8 @@ fd_status run_decode(const Args& a) {
     }
     Plan pl;
     if (!plan_for(a.codec, a.n_codes, a.n_strings, a.tuning, &pl)) return FD_EINVAL;
-    if (a.ws_bytes < pl.bytes) return FD_EINVAL;
+    // a prepared dictionary needs no room for the one-shot repack
+    if (a.ws_bytes < (a.dict ? pl.off_dict : pl.bytes)) return FD_EINVAL;
     if (a.sidecar_op && a.sidecar_n != pl.n_tiles + 1) return FD_EINVAL;   // another tiling's sidecar
 
     uint8_t* ws = (uint8_t*)a.ws;
@@ -333,6 +334,26 @@ fd_status run_decode(const Args& a) {
     int32_t hs = 0;
     if (hipMemcpy(&hs, p.status2, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail();
     return (fd_status)hs;
+}
+
+// ---- the no-allocation entry point: its scratch is a file-scope device
+// array (each GPU the library runs on holds its own copy until the process
+// ends), found once per device by hipGetSymbolAddress ----
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];
+
+// The device address of this device's scratch array (nullptr on failure).
+void* static_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -567,6 +588,31 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     int32_t hs = 0;
     if (hipMemcpy(&hs, p.status2, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail();
     return (fd_status)hs;
+}
+
+fd_status fd_decode_noalloc(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets,
+                            int index_bits, int64_t n_strings, void* out_offsets, uint8_t* out_bytes,
+                            int64_t out_capacity, int32_t* status, unsigned flags, const fd_tuning* tuning,
+                            void* hip_stream) {
+    if (!dict) return FD_EINVAL;
+    // the size check comes first: a column whose tiles do not fit the static
+    // scratch is rejected before the device is touched
+    Plan pl;
+    if (!plan_for(dict->codec, n_codes, n_strings, tuning, &pl)) return FD_EINVAL;
+    if (pl.off_dict > kStaticScratchBytes) return FD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return FD_EHIP;
+    void* ws = static_scratch(dev);
+    if (!ws) return FD_EHIP;
+    Args a;
+    memset(&a, 0, sizeof(a));
+    a.codec = dict->codec;
+    a.dict = dict;
+    a.codes = codes; a.n_codes = n_codes; a.code_off = code_offsets; a.index_bits = index_bits;
+    a.n_strings = n_strings; a.out_off = out_offsets; a.out = out_bytes; a.out_cap = out_capacity;
+    a.ws = ws; a.ws_bytes = kStaticScratchBytes; a.status = status; a.flags = flags; a.tuning = tuning;
+    a.stream = (hipStream_t)hip_stream;
+    return run_decode(a);
 }
 
 fd_status fd_decode(const fd_dict* dict, const void* codes, int64_t n_codes, const void* code_offsets, int index_bits,
