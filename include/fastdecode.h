@@ -381,6 +381,19 @@ fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const f
 fd_status batch_decode(const fd_column *cols, int32_t n_cols, const fd_tuning *tuning, void *workspace,
                        size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
 
+/* The FD_GRAPH cache keeps at most 16 graphs, least recently used first out.
+ * A cached graph is replayed only for a batch equal to the recorded one in
+ * every column's dictionary (compared by a per-handle id, not its address),
+ * codec, buffers and sizes, and in workspace, status pointer and tuning;
+ * fd_dict_destroy drops (after waiting for the device) every cached graph
+ * that reads the destroyed dictionary.
+ * Testing hooks: fd_debug_graph_hash_bits keeps only that many bits (0..64)
+ * of the cache's hash, so that different batches collide and only the full
+ * comparison tells them apart; fd_debug_graph_count is the number of cached
+ * graphs. */
+fd_status fd_debug_graph_hash_bits(int32_t bits);
+int32_t fd_debug_graph_count(void);
+
 /* ------------------------------------------------------------------------- */
 /* Served decode (continuous batching)                                         */
 /* ------------------------------------------------------------------------- */

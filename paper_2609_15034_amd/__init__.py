@@ -118,6 +118,10 @@ def lib():
     L.fd_decode.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, P]
     L.fd_decode_ex.restype = ctypes.c_int
     L.fd_decode_ex.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, S, P, U, ctypes.POINTER(Tuning), P]
+    L.fd_debug_graph_hash_bits.restype = ctypes.c_int
+    L.fd_debug_graph_hash_bits.argtypes = [I32]
+    L.fd_debug_graph_count.restype = ctypes.c_int32
+    L.fd_debug_graph_count.argtypes = []
     L.fd_decode_noalloc.restype = ctypes.c_int
     L.fd_decode_noalloc.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, U, ctypes.POINTER(Tuning), P]
     L.fd_sidecar_layout.restype = ctypes.c_int
@@ -439,6 +443,19 @@ def batch_workspace_size(cols, tuning=None) -> int:
     if st:
         raise DecodeError(st, "fd_batch_workspace_size")
     return int(out.value)
+
+
+def debug_graph_hash_bits(bits: int) -> None:
+    """Testing hook: keep only `bits` bits of the graph cache's hash (0 makes
+    every key collide, so only the full key comparison tells batches apart)."""
+    st = lib().fd_debug_graph_hash_bits(int(bits))
+    if st:
+        raise DecodeError(st, "fd_debug_graph_hash_bits")
+
+
+def debug_graph_count() -> int:
+    """Testing hook: the number of cached batch graphs."""
+    return int(lib().fd_debug_graph_count())
 
 
 def batch_decode(cols, workspace, status=None, tuning=None, async_=False, graph=False, stream=None) -> int:

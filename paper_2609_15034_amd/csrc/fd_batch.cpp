@@ -260,7 +260,20 @@ struct Staging {
 };
 
 // ---- caches: autotuned choice per batch shape, graphs per exact batch ----
+// A graph is reused only for a batch equal to the one it was recorded for in
+// every field the recording depends on: each column's dictionary (by its
+// unique id, never its address), codec, buffers and sizes, the workspace,
+// status pointer, tiling, mode, grid and device.  The hash only narrows the
+// search; the full key is compared.
+struct GraphKey {
+    std::vector<uint64_t> words;
+    uint64_t hash = 0;
+    bool operator==(const GraphKey& o) const { return hash == o.hash && words == o.words; }
+};
+
 struct GraphEntry {
+    GraphKey key;
+    int device = 0;
     hipGraphExec_t exec = nullptr;
     uint8_t* pinned = nullptr;
 };
@@ -269,8 +282,9 @@ std::mutex g_bmu;
 Staging g_stage[64][kRing];
 int g_stage_next[64];
 std::unordered_map<uint64_t, int> g_tuned;                  // shape -> scale (percent)
-std::list<std::pair<uint64_t, GraphEntry>> g_graphs;        // most recent first
+std::list<GraphEntry> g_graphs;                             // most recent first
 constexpr size_t kMaxGraphs = 16;
+int g_hash_bits = 64;                                       // testing: fewer bits force collisions
 
 uint64_t mix(uint64_t h, uint64_t v) {
     h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
@@ -291,19 +305,43 @@ uint64_t shape_key(const fd_column* cols, int32_t n, int dev) {
     return h;
 }
 
-uint64_t exact_key(const fd_column* cols, int32_t n, const void* ws, size_t ws_bytes, const int32_t* status,
-                   int64_t sb_fixed, int scale, int grid, int dev) {
-    uint64_t h = mix(0x9a9a, (uint64_t)n);
-    const uint64_t* w = (const uint64_t*)cols;
-    const size_t nw = (size_t)n * sizeof(fd_column) / 8;
-    for (size_t i = 0; i < nw; i++) h = mix(h, w[i]);
-    h = mix(h, (uint64_t)(uintptr_t)ws);
-    h = mix(h, (uint64_t)ws_bytes);
-    h = mix(h, (uint64_t)(uintptr_t)status);
-    h = mix(h, (uint64_t)sb_fixed);
-    h = mix(h, (uint64_t)scale);
-    h = mix(h, (uint64_t)grid);
-    return mix(h, (uint64_t)dev);
+GraphKey exact_key(const fd_column* cols, int32_t n, const void* ws, size_t ws_bytes, const int32_t* status,
+                   int64_t tc_fixed, int scale, int grid, int dev) {
+    GraphKey k;
+    std::vector<uint64_t>& w = k.words;
+    w.reserve(8 + (size_t)n * 10);
+    w.push_back((uint64_t)n);
+    w.push_back((uint64_t)dev);
+    w.push_back((uint64_t)(uintptr_t)ws);
+    w.push_back((uint64_t)ws_bytes);
+    w.push_back((uint64_t)(uintptr_t)status);
+    w.push_back((uint64_t)tc_fixed);
+    w.push_back((uint64_t)scale);
+    w.push_back((uint64_t)(int64_t)grid);
+    for (int32_t c = 0; c < n; c++) {
+        const fd_column& col = cols[c];
+        w.push_back(col.dict->id);
+        w.push_back((uint64_t)col.dict->codec);
+        w.push_back((uint64_t)(uintptr_t)col.codes);
+        w.push_back((uint64_t)col.n_codes);
+        w.push_back((uint64_t)(uintptr_t)col.code_offsets);
+        w.push_back((uint64_t)(int64_t)col.index_bits);
+        w.push_back((uint64_t)col.n_strings);
+        w.push_back((uint64_t)(uintptr_t)col.out_offsets);
+        w.push_back((uint64_t)(uintptr_t)col.out_bytes);
+        w.push_back((uint64_t)col.out_capacity);
+    }
+    uint64_t h = 0x9a9a;
+    for (uint64_t x : w) h = mix(h, x);
+    k.hash = g_hash_bits >= 64 ? h : (g_hash_bits <= 0 ? 0 : (h & ((1ull << g_hash_bits) - 1)));
+    return k;
+}
+
+void destroy_graph(GraphEntry& ge) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.pinned) (void)hipHostFree(ge.pinned);
+    ge.exec = nullptr;
+    ge.pinned = nullptr;
 }
 
 // Plan and enqueue one batch decode (no graph), staging the table in pinned memory.
@@ -373,7 +411,49 @@ fd_status read_status(uint8_t* ws, hipStream_t st) {
 
 }  // namespace
 
+namespace fd {
+
+void batch_forget_dict(uint64_t dict_id, int device) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    bool synced = false;
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        bool uses = false;
+        const std::vector<uint64_t>& w = it->key.words;
+        for (size_t i = 8; i < w.size(); i += 10)       // per column: the dictionary id first
+            if (w[i] == dict_id) { uses = true; break; }
+        if (uses) {
+            if (!synced) {
+                // a replay of it may still run: wait before freeing what it reads
+                int cur = 0;
+                (void)hipGetDevice(&cur);
+                if (cur != device) (void)hipSetDevice(device);
+                (void)hipDeviceSynchronize();
+                if (cur != device) (void)hipSetDevice(cur);
+                synced = true;
+            }
+            destroy_graph(*it);
+            it = g_graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+}  // namespace fd
+
 extern "C" {
+
+fd_status fd_debug_graph_hash_bits(int32_t bits) {
+    if (bits < 0 || bits > 64) return FD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_bmu);
+    g_hash_bits = bits;
+    return FD_OK;
+}
+
+int32_t fd_debug_graph_count(void) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    return (int32_t)g_graphs.size();
+}
 
 fd_status fd_batch_workspace_size(const fd_column* cols, int32_t n_cols, const fd_tuning* tuning, size_t* bytes) {
     if (!bytes || n_cols < 0 || n_cols > kMaxCols || (n_cols > 0 && !cols)) return FD_EINVAL;
@@ -437,18 +517,20 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
         if (workspace_bytes < pl.bytes) return FD_EINVAL;
 
         if (flags & FD_GRAPH) {
-            const uint64_t key =
+            GraphKey key =
                 exact_key(cols, n_cols, workspace, workspace_bytes, status, sb_fixed, mode * 1000 + scale, grid, dev);
             GraphEntry* ge = nullptr;
             for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
-                if (it->first == key) {
+                if (it->key == key) {
                     g_graphs.splice(g_graphs.begin(), g_graphs, it);
-                    ge = &g_graphs.front().second;
+                    ge = &g_graphs.front();
                     break;
                 }
             }
             if (!ge) {
                 GraphEntry ne;
+                ne.key = std::move(key);
+                ne.device = dev;
                 if (hipHostMalloc((void**)&ne.pinned, pl.table_bytes, hipHostMallocDefault) != hipSuccess)
                     return FD_ENOMEM;
                 fill_table(cols, n_cols, pl, ws, ne.pinned);
@@ -464,18 +546,15 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
                 if (graph) (void)hipGraphDestroy(graph);
                 if (cs) (void)hipStreamDestroy(cs);
                 if (!ok) {
-                    if (ne.exec) (void)hipGraphExecDestroy(ne.exec);
-                    (void)hipHostFree(ne.pinned);
+                    destroy_graph(ne);
                     return FD_EHIP;
                 }
-                g_graphs.emplace_front(key, ne);
-                ge = &g_graphs.front().second;
+                g_graphs.push_front(std::move(ne));
+                ge = &g_graphs.front();
                 while (g_graphs.size() > kMaxGraphs) {
                     // a graph launched earlier may still run: wait before freeing what it reads
                     (void)hipDeviceSynchronize();
-                    GraphEntry& old = g_graphs.back().second;
-                    (void)hipGraphExecDestroy(old.exec);
-                    (void)hipHostFree(old.pinned);
+                    destroy_graph(g_graphs.back());
                     g_graphs.pop_back();
                 }
             }

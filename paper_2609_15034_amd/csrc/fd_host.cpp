@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 
@@ -336,6 +337,8 @@ fd_status run_decode(const Args& a) {
     return (fd_status)hs;
 }
 
+std::atomic<uint64_t> g_dict_ids{0};     // dictionary handle ids
+
 // ---- the no-allocation entry point: its scratch is a file-scope device
 // array (each GPU the library runs on holds its own copy until the process
 // ends), found once per device by hipGetSymbolAddress ----
@@ -637,6 +640,7 @@ fd_status fd_dict_create(fd_codec codec, const uint8_t* dict_bytes, const uint8_
     memset(d, 0, sizeof(*d));
     d->codec = codec;
     d->n = n_tokens;
+    d->id = g_dict_ids.fetch_add(1) + 1;
     if (hipGetDevice(&d->device) != hipSuccess) { delete d; return FD_EHIP; }
     // scratch: err word + bad flag
     const size_t hdr = 256;
@@ -725,6 +729,9 @@ fd_status fd_dict_destroy(fd_dict* dict) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != dict->device) (void)hipSetDevice(dict->device);
+    // cached batch graphs that read this dictionary go first: a handle created
+    // later at the same address must never replay them
+    batch_forget_dict(dict->id, dict->device);
     hipError_t e = hipFree(dict->mem);
     if (cur != dict->device) (void)hipSetDevice(cur);
     delete dict;

@@ -147,6 +147,9 @@ hipError_t launch_coarse_one(int index_bits, const DecodeParams& p, hipStream_t 
 hipError_t launch_coarse_batch(int index_bits, const DecodeParams* cols, int32_t n_cols, int64_t max_samples,
                                hipStream_t st);
 int dev_cus();   // compute units of the current device
+// Batch graph cache: drop (after synchronizing the device) every cached graph
+// whose columns use the dictionary with this id; called by fd_dict_destroy.
+void batch_forget_dict(uint64_t dict_id, int device);
 int resident_grid(int codec, int index_bits, int mode);
 int resident_grid_batch(int codec, int index_bits, int mode);
 
@@ -157,6 +160,7 @@ struct fd_dict {
     fd_codec codec;
     int32_t n;
     int device;
+    uint64_t id;            // unique per handle over the process's life (graph cache keys)
     void* mem;              // single device allocation owned by the handle
     const uint8_t* bytes;   // FSST-8: packed symbols (copy)
     const uint8_t* lens;    // FSST-8: lengths (copy)

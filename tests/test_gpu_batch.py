@@ -215,3 +215,70 @@ def test_batch_many_small_columns(datagen_mod, mode):
     assert rc == 0
     for c, x in zip(cols, st[:-1]):
         c.check(int(x))
+
+
+# --------------------------------------------------------------------------- #
+# the graph cache: full keys, dictionaries by identity
+# --------------------------------------------------------------------------- #
+def test_graph_cache_colliding_hashes(datagen_mod):
+    """With the cache's hash cut to 0 bits every batch collides: replays of two
+    different batches (other columns, other dictionaries, each with its own
+    workspace and status) must still each run their own graph, told apart by
+    the full key."""
+    import torch
+    import paper_2609_15034_amd as fd
+    a = [Col("fsst8", *cols_of(datagen_mod.fsst_small(seed=71, n_strings=800)))]
+    b = [Col("onpair16", *cols_of(datagen_mod.onpair_urls(seed=72, target_bytes=128 << 10,
+                                                          sample_bytes=128 << 10)))]
+    tu = {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0}
+    runs = []
+    for cols in (a, b):
+        tups = [c.tup() for c in cols]
+        ws = torch.empty(fd.batch_workspace_size(tups, tu), dtype=torch.uint8, device="cuda")
+        status = torch.full((len(cols) + 1,), -1, dtype=torch.int32, device="cuda")
+        runs.append((cols, tups, ws, status))
+    fd.debug_graph_hash_bits(0)
+    try:
+        for rep in range(3):                        # recorded on the first pass, replayed after
+            for cols, tups, ws, status in runs:
+                for c in cols:
+                    c.clear()
+                status.fill_(-1)
+                assert fd.batch_decode(tups, ws, status=status, tuning=tu, graph=True, async_=True) == fd.OK
+                torch.cuda.synchronize()
+                st = status.cpu().numpy()
+                for c, s_ in zip(cols, st[:-1]):
+                    c.check(int(s_))
+        assert fd.debug_graph_count() >= 2
+    finally:
+        fd.debug_graph_hash_bits(64)
+
+
+def test_graph_cache_forgets_destroyed_dictionaries(datagen_mod):
+    """A graph recorded for a dictionary is dropped when the dictionary is
+    destroyed; a new dictionary (possibly at the recycled address, with other
+    symbols) decodes its own column correctly through the same buffers."""
+    import gc
+    import torch
+    import paper_2609_15034_amd as fd
+    c1 = datagen_mod.fsst_small(seed=81, n_strings=600)
+    c2 = datagen_mod.fsst_small(seed=82, n_strings=600)    # another table, other codes
+    col = Col("fsst8", *cols_of(c1))
+    tu = {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0}
+    rc, st, _, _ = run_batch([col], tuning=tu, graph=True)
+    col.check(int(st[0]))
+    n_before = fd.debug_graph_count()
+    del col.d
+    gc.collect()
+    assert fd.debug_graph_count() < n_before                # the graph that read it is gone
+    # the second column in new buffers, with a dictionary created afterwards
+    col2 = Col("fsst8", *cols_of(c2))
+    for _ in range(2):
+        col2.clear()
+        rc, st, _, _ = run_batch([col2], tuning=tu, graph=True)
+        col2.check(int(st[0]))
+    torch.cuda.synchronize()
+
+
+def cols_of(c):
+    return c.codes, c.code_off, c.dict_bytes, c.dict_lens
