@@ -395,6 +395,41 @@ fd_status fd_debug_graph_hash_bits(int32_t bits);
 int32_t fd_debug_graph_count(void);
 
 /* ------------------------------------------------------------------------- */
+/* Kernel timing                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* The kernels one decode enqueues, by role (the hot path's stages of the
+ * paper's Design section, Decode Stages, as launched here). */
+typedef enum fd_prof_kind {
+    FD_PROF_RESET = 0,     /* k_reset: workspace words, tile words, status */
+    FD_PROF_COARSE = 1,    /* k_coarse: the coarse string index per tile of codes */
+    FD_PROF_TOTALS = 2,    /* tile totals (three phases; sidecar build) */
+    FD_PROF_SCAN = 3,      /* the scan of tile totals into tile cursors */
+    FD_PROF_DECODE = 4,    /* k_decode: expand, single pass, or sidecar decode */
+    FD_PROF_PREPARE = 5,   /* one-shot dictionary repack; fd_decode_take's row compaction */
+    FD_PROF_KINDS = 6
+} fd_prof_kind;
+
+/* fd_profile_begin opens a profile on the current device: from then on, every
+ * launch of a kind in kind_mask (bit 1 << fd_prof_kind) made by fsst_decode,
+ * onpair_decode, fd_decode(_ex), fd_sidecar_build, fd_decode_sidecar or
+ * fd_decode_take on that device is bracketed by two HIP events recorded on
+ * the launch's own stream.  The events, 2 * max_launches of them
+ * (1..1,048,576), are created here, so the timed calls allocate nothing;
+ * launches past the pool are counted as dropped.  batch_decode and the server
+ * are not timed.  FD_EINVAL for an empty or unknown mask, a bad size or a
+ * profile already open; FD_EHIP if the events cannot be created.
+ *
+ * fd_profile_end waits for the recorded events and writes, for each of the
+ * FD_PROF_KINDS kinds (arrays of that length, each may be NULL), the summed
+ * duration in ms, the number of launches timed, and the shortest and longest
+ * launch; *dropped (may be NULL) gets the launches not timed.  It closes the
+ * profile and frees the events.  FD_EINVAL if no profile is open.
+ * Not for use while a stream capture records the calls. */
+fd_status fd_profile_begin(uint32_t kind_mask, int32_t max_launches);
+fd_status fd_profile_end(double *total_ms, int64_t *launches, double *min_ms, double *max_ms, int64_t *dropped);
+
+/* ------------------------------------------------------------------------- */
 /* Served decode (continuous batching)                                         */
 /* ------------------------------------------------------------------------- */
 

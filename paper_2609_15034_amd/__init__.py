@@ -122,6 +122,10 @@ def lib():
     L.fd_debug_graph_hash_bits.argtypes = [I32]
     L.fd_debug_graph_count.restype = ctypes.c_int32
     L.fd_debug_graph_count.argtypes = []
+    L.fd_profile_begin.restype = ctypes.c_int
+    L.fd_profile_begin.argtypes = [ctypes.c_uint32, ctypes.c_int32]
+    L.fd_profile_end.restype = ctypes.c_int
+    L.fd_profile_end.argtypes = [P, P, P, P, P]
     L.fd_decode_noalloc.restype = ctypes.c_int
     L.fd_decode_noalloc.argtypes = [P, P, I64, P, ctypes.c_int, I64, P, P, I64, P, U, ctypes.POINTER(Tuning), P]
     L.fd_sidecar_layout.restype = ctypes.c_int
@@ -456,6 +460,40 @@ def debug_graph_hash_bits(bits: int) -> None:
 def debug_graph_count() -> int:
     """Testing hook: the number of cached batch graphs."""
     return int(lib().fd_debug_graph_count())
+
+
+PROF_KINDS = ("reset", "coarse", "totals", "scan", "decode", "prepare")   # fd_prof_kind order
+
+
+def profile_begin(kinds=PROF_KINDS, max_launches: int = 4096) -> None:
+    """fd_profile_begin: time every launch of the named kinds (HIP events on
+    the launch's stream) until profile_end."""
+    mask = 0
+    for k in kinds:
+        mask |= 1 << PROF_KINDS.index(k)
+    st = lib().fd_profile_begin(mask, int(max_launches))
+    if st:
+        raise DecodeError(st, "fd_profile_begin")
+
+
+def profile_end() -> dict:
+    """fd_profile_end: {kind: {"launches", "total_ms", "mean_us", "min_us",
+    "max_us"}} for the kinds launched, plus "dropped"."""
+    n = len(PROF_KINDS)
+    tot, mn, mx = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    dropped = ctypes.c_int64(0)
+    st = lib().fd_profile_end(ctypes.cast(tot, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p),
+                              ctypes.cast(mn, ctypes.c_void_p), ctypes.cast(mx, ctypes.c_void_p),
+                              ctypes.cast(ctypes.pointer(dropped), ctypes.c_void_p))
+    if st:
+        raise DecodeError(st, "fd_profile_end")
+    out = {"dropped": int(dropped.value)}
+    for i, k in enumerate(PROF_KINDS):
+        if cnt[i]:
+            out[k] = {"launches": int(cnt[i]), "total_ms": tot[i], "mean_us": tot[i] * 1e3 / cnt[i],
+                      "min_us": mn[i] * 1e3, "max_us": mx[i] * 1e3}
+    return out
 
 
 def batch_decode(cols, workspace, status=None, tuning=None, async_=False, graph=False, stream=None) -> int:

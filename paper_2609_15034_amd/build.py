@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfastdecode.so")
 ARCH = os.environ.get("FD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fd_kernels.hip", "fd_host.cpp", "fd_batch.cpp", "fd_server.cpp"]
+SOURCES = ["fd_kernels.hip", "fd_host.cpp", "fd_batch.cpp", "fd_server.cpp", "fd_profile.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

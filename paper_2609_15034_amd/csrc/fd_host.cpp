@@ -265,12 +265,15 @@ fd_status run_decode(const Args& a) {
     hipStream_t st = a.stream;
     // tile words, block states and the coarse index are contiguous: one zeroing covers them
     const int64_t nz = (int64_t)((pl.off_scan - pl.off_tiles) / 8);
-    if (launch_reset(p.err, p.counters, (unsigned long long*)(ws + pl.off_tiles), nz, st) != hipSuccess)
+    if (timed(FD_PROF_RESET, st, [&] { return launch_reset(p.err, p.counters, (unsigned long long*)(ws + pl.off_tiles), nz, st); }) !=
+        hipSuccess)
         return hip_fail();
     if (a.sidecar_op == kSidecarBuild) {
         // the totals pass writes the entries of the tiles with codes; the rest and the last start at zero
         p.tagg = (unsigned long long*)a.sidecar;
-        if (launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + 1, st) != hipSuccess) return hip_fail();
+        if (timed(FD_PROF_RESET, st, [&] { return launch_reset(p.err, p.counters, p.tagg, pl.n_tiles + 1, st); }) !=
+            hipSuccess)
+            return hip_fail();
     } else if (a.sidecar_op == kSidecarDecode) {
         p.tagg = (unsigned long long*)a.sidecar;     // read only (entries t and t + 1 per tile)
     }
@@ -295,7 +298,9 @@ fd_status run_decode(const Args& a) {
         } else {
             uint4* t16 = (uint4*)(ws + pl.off_dict);
             uint8_t* tl = ws + pl.off_dict + kTok16Bytes;
-            if (launch_onpair_prepare(a.dict_bytes, a.dict_lens, a.n_dict, t16, tl, p.err, nullptr, st) != hipSuccess)
+            if (timed(FD_PROF_PREPARE, st, [&] {
+                    return launch_onpair_prepare(a.dict_bytes, a.dict_lens, a.n_dict, t16, tl, p.err, nullptr, st);
+                }) != hipSuccess)
                 return hip_fail();
             p.tok16 = t16;
             p.tok_len = tl;
@@ -304,30 +309,45 @@ fd_status run_decode(const Args& a) {
 
     const int codec = (int)a.codec;
     int grid_req = a.tuning ? a.tuning->grid : 0;
-    if (launch_coarse_one(a.index_bits, p, st) != hipSuccess) return hip_fail();
+    if (timed(FD_PROF_COARSE, st, [&] { return launch_coarse_one(a.index_bits, p, st); }) != hipSuccess)
+        return hip_fail();
     if (a.sidecar_op == kSidecarBuild) {
         int g1 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeTotals);
         if ((int64_t)g1 > pl.n_tiles) g1 = (int)pl.n_tiles;
-        if (launch_decode(codec, a.index_bits, kModeTotals, p, g1, st) != hipSuccess) return hip_fail();
-        if (launch_scan_totals(p.tagg, pl.n_tiles + 1, p.err, a.status, p.status2, st) != hipSuccess)
+        if (timed(FD_PROF_TOTALS, st, [&] { return launch_decode(codec, a.index_bits, kModeTotals, p, g1, st); }) !=
+            hipSuccess)
+            return hip_fail();
+        if (timed(FD_PROF_SCAN, st,
+                  [&] { return launch_scan_totals(p.tagg, pl.n_tiles + 1, p.err, a.status, p.status2, st); }) !=
+            hipSuccess)
             return hip_fail();
     } else if (a.sidecar_op == kSidecarDecode) {
         int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
         if ((int64_t)g2 > pl.n_tiles) g2 = (int)pl.n_tiles;
-        if (launch_decode(codec, a.index_bits, kModeExpand, p, g2, st) != hipSuccess) return hip_fail();
+        if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec, a.index_bits, kModeExpand, p, g2, st); }) !=
+            hipSuccess)
+            return hip_fail();
     } else if (mode_sel == 0) {
         int grid = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeLookback);
         if ((int64_t)grid > pl.n_tiles) grid = (int)pl.n_tiles;
-        if (launch_decode(codec, a.index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();
+        if (timed(FD_PROF_DECODE, st,
+                  [&] { return launch_decode(codec, a.index_bits, kModeLookback, p, grid, st); }) != hipSuccess)
+            return hip_fail();
     } else {
         // tile totals streamed, scanned into cursors, then the expand phase
         // (which validates and checks every tile's total against its cursors)
-        if (launch_tile_totals(codec, a.index_bits, p, dev_cus(), st) != hipSuccess) return hip_fail();
-        if (launch_scan_multi(p.tagg, pl.n_tiles + 1, (unsigned long long*)(ws + pl.off_scan), st) != hipSuccess)
+        if (timed(FD_PROF_TOTALS, st, [&] { return launch_tile_totals(codec, a.index_bits, p, dev_cus(), st); }) !=
+            hipSuccess)
+            return hip_fail();
+        if (timed(FD_PROF_SCAN, st, [&] {
+                return launch_scan_multi(p.tagg, pl.n_tiles + 1, (unsigned long long*)(ws + pl.off_scan), st);
+            }) != hipSuccess)
             return hip_fail();
         int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
         if ((int64_t)g2 > pl.n_tiles) g2 = (int)pl.n_tiles;
-        if (launch_decode(codec, a.index_bits, kModeExpand, p, g2, st) != hipSuccess) return hip_fail();
+        if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec, a.index_bits, kModeExpand, p, g2, st); }) !=
+            hipSuccess)
+            return hip_fail();
     }
 
     if (a.flags & FD_ASYNC) return FD_OK;
@@ -533,7 +553,9 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     unsigned* counters = (unsigned*)(ws + kOffCounters);
     unsigned long long* tagg = (unsigned long long*)(ws + tp.dec.off_tiles);
     // tile words, block states and the coarse index of the compacted column
-    if (launch_reset(err, counters, tagg, (int64_t)((tp.dec.off_scan - tp.dec.off_tiles) / 8), st) != hipSuccess)
+    if (timed(FD_PROF_RESET, st, [&] {
+            return launch_reset(err, counters, tagg, (int64_t)((tp.dec.off_scan - tp.dec.off_tiles) / 8), st);
+        }) != hipSuccess)
         return hip_fail();
     // compaction: the selected strings' codes, whole, one after another
     uint8_t* ccodes = ws + tp.off_codes;
@@ -542,9 +564,11 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
     int rows_per_wg = 16;
     while (rows_per_wg < 1024 && (double)(2 * rows_per_wg) * mean <= 4096.0) rows_per_wg *= 2;
-    if (launch_take_compact((int)dict->codec, index_bits, rows, n_rows, code_offsets, n_strings, n_codes,
-                            (const uint8_t*)codes, (unsigned long long*)(ws + tp.off_bsum), max_codes, coff,
-                            (int64_t*)(ws + tp.off_src), ccodes, rows_per_wg, err, st) != hipSuccess)
+    if (timed(FD_PROF_PREPARE, st, [&] {
+            return launch_take_compact((int)dict->codec, index_bits, rows, n_rows, code_offsets, n_strings, n_codes,
+                                       (const uint8_t*)codes, (unsigned long long*)(ws + tp.off_bsum), max_codes,
+                                       coff, (int64_t*)(ws + tp.off_src), ccodes, rows_per_wg, err, st);
+        }) != hipSuccess)
         return hip_fail();
     // the compacted column through the decode kernels
     DecodeParams p;
@@ -582,10 +606,12 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
         p.tok_len = dict->tok_len;
     }
     const int codec2 = (int)tp.codec2;
-    if (launch_coarse_one(index_bits, p, st) != hipSuccess) return hip_fail();
+    if (timed(FD_PROF_COARSE, st, [&] { return launch_coarse_one(index_bits, p, st); }) != hipSuccess) return hip_fail();
     int grid = (tuning && tuning->grid) ? tuning->grid : resident_grid(codec2, index_bits, kModeLookback);
     if ((int64_t)grid > tp.dec.n_tiles) grid = (int)tp.dec.n_tiles;
-    if (launch_decode(codec2, index_bits, kModeLookback, p, grid, st) != hipSuccess) return hip_fail();
+    if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec2, index_bits, kModeLookback, p, grid, st); }) !=
+        hipSuccess)
+        return hip_fail();
     if (flags & FD_ASYNC) return FD_OK;
     if (hipStreamSynchronize(st) != hipSuccess) return hip_fail();
     int32_t hs = 0;

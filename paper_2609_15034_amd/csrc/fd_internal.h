@@ -153,6 +153,22 @@ void batch_forget_dict(uint64_t dict_id, int device);
 int resident_grid(int codec, int index_bits, int mode);
 int resident_grid_batch(int codec, int index_bits, int mode);
 
+// Kernel timing while a profile is open (fd_profile_begin): prof_begin records
+// a start event on `st` for a launch of `kind` (an fd_prof_kind) and returns
+// its slot, or -1 when the kind is not selected or no profile is open;
+// prof_end records the slot's end event.
+int prof_begin(int kind, hipStream_t st);
+void prof_end(int slot, hipStream_t st);
+
+// A launch bracketed by prof_begin / prof_end.
+template <class F>
+hipError_t timed(int kind, hipStream_t st, F&& launch) {
+    const int slot = prof_begin(kind, st);
+    const hipError_t e = launch();
+    prof_end(slot, st);
+    return e;
+}
+
 }  // namespace fd
 
 // A prepared dictionary (device-resident, immutable after creation).

@@ -162,3 +162,15 @@ def test_take_host_checks(fdlib):
     fake, ws = P(1 << 20), P(1 << 21)
     assert L.fd_decode_take(None, fake, 10, fake, 64, 1, fake, 1, 10, fake, fake, 10, ws, 1 << 20, None, 0, None,
                             None) == fd.EINVAL
+
+
+def test_profile_host_checks(fdlib):
+    """fd_profile_begin rejects an empty or unknown kind mask and bad pool
+    sizes; fd_profile_end with no open profile is an error (no device calls)."""
+    L = fdlib.lib()
+    assert L.fd_profile_begin(0, 16) == fdlib.EINVAL
+    assert L.fd_profile_begin(1 << 6, 16) == fdlib.EINVAL
+    assert L.fd_profile_begin(1, 0) == fdlib.EINVAL
+    assert L.fd_profile_begin(1, (1 << 20) + 1) == fdlib.EINVAL
+    assert L.fd_profile_end(None, None, None, None, None) == fdlib.EINVAL
+    assert fdlib.PROF_KINDS[4] == "decode" and len(fdlib.PROF_KINDS) == 6
