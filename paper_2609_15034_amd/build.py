@@ -27,6 +27,9 @@ def flags(extra=()):
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
             # no packed FP32 instructions anywhere (the path has no floating point)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # single-lane atomics stay single-lane: the optimizer's wave-wide
+            # rewrite reads the result back at once, which waits for the atomic
+            "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable", *extra]
 
 

@@ -171,6 +171,16 @@ __device__ __forceinline__ void lds_put_clipped(uint8_t* stage, int q, uint64_t 
     }
 }
 
+// Loads through global (not generic) addresses: a generic load also counts
+// against the LDS wait counter, so every later wait for an LDS access would
+// wait for it too.
+#define FD_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ u32x4 gload16_nt(uintptr_t a) { return __builtin_nontemporal_load((const FD_GLOBAL u32x4*)a); }
+__device__ __forceinline__ uint32_t gload4_nt(uintptr_t a) {
+    return __builtin_nontemporal_load((const FD_GLOBAL uint32_t*)a);
+}
+__device__ __forceinline__ uint32_t gload1(uintptr_t a) { return *(const FD_GLOBAL uint8_t*)a; }
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
@@ -266,7 +276,6 @@ template <int CODEC> struct SmemT {
     uint32_t wlast[kNWave];               // total of each wave's last lane
     uint32_t wpar[kNWave];
     int64_t hdr[2];                       // the column's decode range [code_offsets[0], code_offsets[n])
-    int64_t cur2[2];                      // stored cursors of this tile and the next (expand mode)
     int64_t pfirst[2][kNWave];            // offsets: per-wave first index past the tile, double-buffered
     uint32_t vote[2][kNWave];             // offsets: per-wave "first string found" flags
     uint32_t cin;                         // FSST-8: escape parity entering the tile
@@ -402,15 +411,15 @@ __device__ __forceinline__ void codes_load_at(const DecodeParams& p, const Geom&
             uint32_t x = 0, y = 0, z = 0;
             if (k < g.nchunk) {
                 if (ca + 12 <= hi && (ca & 3u) == 0) {
-                    x = __builtin_nontemporal_load((const uint32_t*)ca);
-                    y = __builtin_nontemporal_load((const uint32_t*)(ca + 4));
-                    z = __builtin_nontemporal_load((const uint32_t*)(ca + 8));
+                    x = gload4_nt(ca);
+                    y = gload4_nt(ca + 4);
+                    z = gload4_nt(ca + 8);
                 } else {
                     uint32_t d[3] = {0, 0, 0};
 #pragma unroll
                     for (int j = 0; j < 12; j++) {
                         const uintptr_t a = ca + j;
-                        if (a >= lo && a < hi) d[j >> 2] |= (uint32_t)(*(const uint8_t*)a) << (8 * (j & 3));
+                        if (a >= lo && a < hi) d[j >> 2] |= gload1(a) << (8 * (j & 3));
                     }
                     x = d[0]; y = d[1]; z = d[2];
                 }
@@ -435,13 +444,13 @@ __device__ __forceinline__ void codes_load_at(const DecodeParams& p, const Geom&
         w[c][0] = w[c][1] = w[c][2] = w[c][3] = 0;
         if (k < g.nchunk) {
             if (ca >= lo && ca + 16 <= hi) {
-                const u32x4 v = __builtin_nontemporal_load((const u32x4*)ca);
+                const u32x4 v = gload16_nt(ca);
                 w[c][0] = v.x; w[c][1] = v.y; w[c][2] = v.z; w[c][3] = v.w;
             } else {
 #pragma unroll
                 for (int j = 0; j < 16; j++) {
                     const uintptr_t x = ca + j;
-                    if (x >= lo && x < hi) w[c][j >> 2] |= (uint32_t)(*(const uint8_t*)x) << (8 * (j & 3));
+                    if (x >= lo && x < hi) w[c][j >> 2] |= gload1(x) << (8 * (j & 3));
                 }
             }
         }
@@ -1281,7 +1290,9 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     const unsigned tid = ltid(), wv = tid >> 6;
     const int64_t n_all = src.n_tiles();
     unsigned* const ctr = src.counter();
-
+    // Tiles come from a global counter, in increasing order (the look-back
+    // needs it; in the other modes it spreads the workgroups of a CU over
+    // different steps of their tiles, which measured faster than fixed shares).
     if (tid == 0) s.next_id = (int32_t)atomicAdd(ctr, 1u);
     __syncthreads();
     int64_t v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
@@ -1290,9 +1301,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     int64_t ca = 0, cb = 0;               // the column's decode range
     int64_t t_first = 0, t_last = -1;     // its tiles with work (divisions once per column)
     // loaded during the previous tile for tile id pf_v (same column): its
-    // coarse groups and, FSST-8, wave 0's bytes of the window before its first code
-    int64_t pf_v = -1, pf_g0 = 0, pf_g1 = 0;
+    // coarse groups, its stored cursor and the next tile's (expand mode) and,
+    // FSST-8, wave 0's bytes of the window before its first code.  Kept as
+    // loaded (per-lane registers) until the tile starts, so that nothing
+    // waits for them earlier.
+    int64_t pf_v = -1, pf_g0 = 0, pf_g1 = 0, pf_c0 = 0, pf_c1 = 0;
     uint32_t pf_byte = 0;
+    uint32_t pf_w[P][4];                  // and its codes (their loads overlap this tile's drain and offsets)
     if constexpr (CODEC == kFsst8 && !SRC::kBatch) {
         fsst_build_table(s, src.params(0));
         table_src = (const void*)1;
@@ -1365,18 +1380,25 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         // the tile's code offsets: all in flight together, the offsets waited
         // for only after the length scan
         const bool pf = pf_v == v;
-        const int64_t gcur = pf ? pf_g0 : uniform64(p.coarse[t]);
-        const int64_t gnext = pf ? pf_g1 : ((t + 1 < p.n_tiles) ? uniform64(p.coarse[t + 1]) : 0);
+        const int64_t gcur = uniform64(pf ? pf_g0 : p.coarse[t]);
+        const int64_t gnext = uniform64(pf ? pf_g1 : ((t + 1 < p.n_tiles) ? p.coarse[t + 1] : 0));
+        // expand mode: the stored cursors of this tile and the next (used at the cursor step)
+        int64_t cur0 = 0, cur1 = 0;
+        if constexpr (MODE == kModeExpand) {
+            cur0 = pf ? pf_c0 : (int64_t)p.tagg[t];
+            cur1 = pf ? pf_c1 : (int64_t)p.tagg[t + 1];
+        }
         Lane<CODEC> L;
-        codes_load<CODEC>(p, g, 0, L.w);
+        if (pf) {
+#pragma unroll
+            for (int c = 0; c < P; c++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) L.w[c][i] = pf_w[c][i];
+        } else {
+            codes_load<CODEC>(p, g, 0, L.w);
+        }
         OffRegs<CODEC, IDX> orr;
         offsets_prefetch<CODEC, IDX>(p, min(max(gcur, (int64_t)0) << p.g_shift, p.n_strings), orr);
-        if (tid == 0) {
-            if constexpr (MODE == kModeExpand) {
-                s.cur2[0] = (int64_t)p.tagg[t];
-                s.cur2[1] = (int64_t)p.tagg[t + 1];
-            }
-        }
         if constexpr (CODEC == kFsst8) {
             if (wv == 0) {
                 const int64_t ca_c = min(max(ca, (int64_t)0), p.n_codes);
@@ -1389,6 +1411,13 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         uint32_t carry = 0;
         if constexpr (CODEC == kFsst8) carry = uniform32(s.cin);
         const uint32_t cin = carry;
+        // the id after this tile, published at the cursor step.  Without a
+        // look-back it is requested now, so that the atomic's round trip
+        // overlaps the length scan and the assembly; the single pass requests
+        // it at the cursor step (tiles then start in about the order of their
+        // ids, which its look-back wants)
+        uint32_t nid = 0;
+        if (MODE != kModeLookback && tid == 0) nid = atomicAdd(ctr, 1u);
 
         const uint32_t tot = lengths<CODEC>(s, p, g, 0, L, carry, true, r_len, r_tok);
         offsets_stage<CODEC, IDX>(s, orr);      // read after later barriers
@@ -1396,7 +1425,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             // the sidecar build: every check of the decode, the tile's total, no output
             if (tid == 0) {
                 p.tagg[t] = tot;
-                s.next_id = (int32_t)atomicAdd(ctr, 1u);
+                s.next_id = (int32_t)nid;
             }
             __syncthreads();            // the staged offsets
             tile_offsets<CODEC, IDX, false>(s, p, g, t, 0, tot, cin, ca, gcur, gnext);
@@ -1422,7 +1451,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             }
         } else {
             if (tid == 0) {
-                int64_t cur = s.cur2[0], nxt = s.cur2[1];
+                int64_t cur = cur0, nxt = cur1;
                 if constexpr (SRC::kBatch) {
                     // a batch group's cursors are scanned over all its columns:
                     // relative to the column's first tile
@@ -1433,9 +1462,8 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 s.cursor = checked_cursor(p, t, cur, nxt, tot);
             }
         }
-        // the next tile, requested once this one's cursor is known (tiles then
-        // start in about the order of their ids, which the look-back wants)
-        if (tid == 0) s.next_id = (int32_t)atomicAdd(ctr, 1u);
+        // the next tile's id
+        if (tid == 0) s.next_id = (int32_t)(MODE == kModeLookback ? atomicAdd(ctr, 1u) : nid);
         __syncthreads();
         const int64_t cursor = uniform64(s.cursor);
         // the next tile's coarse groups and first window, loaded now (they
@@ -1447,13 +1475,16 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 const int64_t tn = vn - src.first(col);
                 if (tn >= t_first && tn <= t_last) {
                     pf_v = vn;
-                    pf_g0 = uniform64(p.coarse[tn]);
-                    pf_g1 = (tn + 1 < p.n_tiles) ? uniform64(p.coarse[tn + 1]) : 0;
+                    pf_g0 = p.coarse[tn];
+                    pf_g1 = (tn + 1 < p.n_tiles) ? p.coarse[tn + 1] : 0;
+                    if constexpr (MODE == kModeExpand) {
+                        pf_c0 = (int64_t)p.tagg[tn];
+                        pf_c1 = (int64_t)p.tagg[tn + 1];
+                    }
+                    const Geom gn = make_geom<CODEC>(p, tn, ca, cb);
+                    codes_load<CODEC>(p, gn, 0, pf_w);
                     if constexpr (CODEC == kFsst8) {
-                        if (wv == 0) {
-                            const Geom gn = make_geom<CODEC>(p, tn, ca, cb);
-                            pf_byte = fsst_window_byte(p.codes, min(max(ca, (int64_t)0), p.n_codes), gn.a);
-                        }
+                        if (wv == 0) pf_byte = fsst_window_byte(p.codes, min(max(ca, (int64_t)0), p.n_codes), gn.a);
                     }
                 }
             }
