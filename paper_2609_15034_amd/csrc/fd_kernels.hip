@@ -128,49 +128,6 @@ __device__ __forceinline__ void wave_record_error(unsigned long long* err, uint6
     }
 }
 
-// unaligned LDS stores (gfx950 supports unaligned DS access)
-__device__ __forceinline__ void lds_put16(uint8_t* p, u32x4 v) { __builtin_memcpy(p, &v, 16); }
-__device__ __forceinline__ void lds_put8(uint8_t* p, uint64_t v) { __builtin_memcpy(p, &v, 8); }
-__device__ __forceinline__ void lds_put4(uint8_t* p, uint32_t v) { __builtin_memcpy(p, &v, 4); }
-__device__ __forceinline__ void lds_put2(uint8_t* p, uint32_t v) {
-    const uint16_t h = (uint16_t)v;
-    __builtin_memcpy(p, &h, 2);
-}
-
-// exact write of l (0..8) bytes of v
-__device__ __forceinline__ void lds_put_exact8(uint8_t* p, uint64_t v, uint32_t l) {
-    if (l == 8) {
-        lds_put8(p, v);
-        return;
-    }
-    uint32_t o = 0;
-    if (l & 4) { lds_put4(p, (uint32_t)v); v >>= 32; o = 4; }
-    if (l & 2) { lds_put2(p + o, (uint32_t)v); v >>= 16; o += 2; }
-    if (l & 1) { p[o] = (uint8_t)v; }
-}
-
-// exact write of l (0..16) bytes of v
-__device__ __forceinline__ void lds_put_exact16(uint8_t* p, u32x4 v, uint32_t l) {
-    if (l == 16) {
-        lds_put16(p, v);
-        return;
-    }
-    uint64_t lo = ((uint64_t)v.y << 32) | v.x;
-    const uint64_t hi = ((uint64_t)v.w << 32) | v.z;
-    if (l & 8) { lds_put8(p, lo); p += 8; lo = hi; }
-    lds_put_exact8(p, lo, l & 7);
-}
-
-// byte-wise write of the part of [q, q+l) inside [0, lim); v = bytes lo..hi
-__device__ __forceinline__ void lds_put_clipped(uint8_t* stage, int q, uint64_t lo, uint64_t hi, uint32_t l, int lim) {
-    for (uint32_t m = 0; m < l; m++) {
-        const int y = q + (int)m;
-        if (y >= 0 && y < lim) stage[y] = (uint8_t)lo;
-        lo = (lo >> 8) | (hi << 56);
-        hi >>= 8;
-    }
-}
-
 // Loads through global (not generic) addresses: a generic load also counts
 // against the LDS wait counter, so every later wait for an LDS access would
 // wait for it too.
@@ -264,7 +221,9 @@ __host__ __device__ __forceinline__ int64_t packed12_bytes(int64_t n) { return (
 
 template <int CODEC> struct SmemT {
     static constexpr int P = Cfg<CODEC>::P, CPC = Cfg<CODEC>::CPC;
-    uint8_t stage[Cfg<CODEC>::WIN + 16];  // staging window (+16: slack for the drain's 16-byte reads)
+    // staging window, zero before the assembly (+32: the last entries' ORs
+    // reach up to 24 bytes past their start; the drain's 16-byte reads)
+    alignas(16) uint8_t stage[Cfg<CODEC>::WIN + 32];
     uint8_t pre8[kWG * P * CPC];          // per code: prefix inside its chunk | escape bit
     uint32_t lane_pre[kWG];               // per lane: exclusive prefix inside the tile
     uint16_t cbase[kWG * P];              // per chunk: prefix inside its lane
@@ -472,7 +431,7 @@ template <int CODEC> struct Lane {
     uint32_t tot;          // decoded bytes of the lane
     uint32_t lane_pre;     // exclusive prefix of the lane inside the super-pass
     uint32_t lenp[P][Cfg<CODEC>::CPC / 4];   // per-code lengths, packed bytes
-    u32x4 tok[kIsOnpair<CODEC> ? Cfg<CODEC>::CPL : 1];   // OnPair token entries
+    u32x4 tok[kIsOnpair<CODEC> ? Cfg<CODEC>::CPC : 1];   // OnPair token entries of the chunk being assembled
 };
 
 // Load the FSST-8 table into LDS (once per workgroup).  Lengths 0 / above 8
@@ -753,33 +712,27 @@ struct U128 {
     uint64_t lo, hi;
 };
 
-// v << (8 * o) truncated to 128 bits, o in 0..15
-__device__ __forceinline__ U128 shl_bytes(U128 v, uint32_t o) {
-    const uint32_t sh = 8u * o;
-    U128 r;
-    if (sh == 0) {
-        r = v;
-    } else if (sh < 64) {
-        r.lo = v.lo << sh;
-        r.hi = (v.hi << sh) | (v.lo >> (64u - sh));
-    } else {
-        r.lo = 0;
-        r.hi = v.lo << (sh - 64u);
-    }
-    return r;
+// OR the 16 bytes (lo, hi) into the staging window at byte offset q: three
+// 64-bit LDS ORs at the aligned words q & ~7 .. (q & ~7) + 16, the last two
+// only where they carry bytes.  Aligned atomics cost a fraction of a store at
+// a byte-granular address, and ORing into zeroed memory leaves every other
+// byte as it is, so entries and lanes need no order among themselves.
+__device__ __forceinline__ void lds_or16(uint8_t* stage, int q, uint64_t lo, uint64_t hi) {
+    const uint32_t o8 = 8u * ((uint32_t)q & 7u), rs = 63u - o8;
+    const uint64_t r0 = lo << o8;
+    const uint64_t r1 = (hi << o8) | ((lo >> 1) >> rs);      // (two shifts: o8 = 0 needs no select)
+    const uint64_t r2 = (hi >> 1) >> rs;
+    unsigned long long* d = (unsigned long long*)&stage[q & ~7];
+    __hip_atomic_fetch_or(d, (unsigned long long)r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (r1) __hip_atomic_fetch_or(d + 1, (unsigned long long)r1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (r2) __hip_atomic_fetch_or(d + 2, (unsigned long long)r2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Every token (FSST-8: every pair of tokens) is written as a whole 16-byte
-// entry at its offset; the lane's next entry overwrites the excess (the
-// copy-and-advance idea of OnPair's CPU loop).  The excess of a lane's last
-// entries lands in the first 16 bytes of the next lane, which each lane also
-// builds in registers (`head`, its entries are zero past their lengths) and
-// writes back once every lane is done (fixup).  No write is ever narrower than
-// 16 bytes: LDS stores at byte-granular addresses cost several times an aligned
-// one whatever their width.
+// Every token (FSST-8: every pair of tokens) is ORed as a whole 16-byte
+// entry, zero past its length, into the zeroed window at its offset.
 template <typename S>
 __device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], uint32_t lit, const uint32_t (&lenp)[4],
-                                                int& q, int q0, U128& head) {
+                                                int& q) {
     // the table reads run one pair ahead of the writes (source order keeps
     // them ahead: the compiler cannot tell the staging and the table apart)
     uint64_t n0 = s.fsst_tab[w[0] & 0xffu], n1 = s.fsst_tab[(w[0] >> 8) & 0xffu];
@@ -800,58 +753,45 @@ __device__ __forceinline__ void fsst_chunk_emit(S& s, const uint32_t (&w)[4], ui
         // the pair: v0 | v1 << 8 * l0 over 128 bits, l0 in 0..8; each shift is
         // split in two of at most 32 bits, so l0 = 0 and l0 = 8 need no select
         const uint32_t sl = 4u * l0, sr = 32u - sl;
-        U128 pr;
-        pr.lo = v0 | ((v1 << sl) << sl);
-        pr.hi = (v1 >> sr) >> sr;
-        const u32x4 v = {(uint32_t)pr.lo, (uint32_t)(pr.lo >> 32), (uint32_t)pr.hi, (uint32_t)(pr.hi >> 32)};
-        lds_put16(&s.stage[q], v);
-        const uint32_t qr = (uint32_t)(q - q0);
-        if (qr < 16u) {
-            const U128 sh = shl_bytes(pr, qr);
-            head.lo |= sh.lo;
-            head.hi |= sh.hi;
-        }
+        lds_or16(s.stage, q, v0 | ((v1 << sl) << sl), (v1 >> sr) >> sr);
         q += (int)(l0 + l1);
         if ((j & 3) == 2) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
+// (codes outside the tile were gathered as zero entries)
 template <typename S>
-__device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const uint32_t (&lenp)[2], int& q, int q0,
-                                                  U128& head) {
+__device__ __forceinline__ void onpair_chunk_emit(S& s, const u32x4* tok, const uint32_t (&lenp)[2], int& q) {
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const uint32_t l = (lenp[j >> 2] >> (8 * (j & 3))) & 0xffu;
         const u32x4 v = tok[j];
-        lds_put16(&s.stage[q], v);
-        const uint32_t qr = (uint32_t)(q - q0);
-        if (qr < 16u && l != 0) {
-            const U128 t = {((uint64_t)v.y << 32) | v.x, ((uint64_t)v.w << 32) | v.z};
-            const U128 sh = shl_bytes(t, qr);
-            head.lo |= sh.lo;
-            head.hi |= sh.hi;
-        }
+        lds_or16(s.stage, q, ((uint64_t)v.y << 32) | v.x, ((uint64_t)v.w << 32) | v.z);
         q += (int)l;
         if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
 template <int CODEC, typename S>
-__device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, U128& head,
-                                         const __amdgpu_buffer_rsrc_t& r_tok) {
+__device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, const __amdgpu_buffer_rsrc_t& r_tok) {
     using C = Cfg<CODEC>;
     constexpr uint32_t K = C::WIN - C::CPL * C::W;
     if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
     if constexpr (kIsOnpair<CODEC>) {
-        if (c == 0) {          // the lane's token entries, gathered for its window
+        // the chunk's token entries (one chunk at a time: the entries of all
+        // the lane's chunks at once would not fit the registers); codes
+        // outside the tile read past the entries, which the buffer load's
+        // range check returns as zero
 #pragma unroll
-            for (int cc = 0; cc < C::P; cc++)
+        for (int cc = 0; cc < C::P; cc++)
+            if (cc == c) {
 #pragma unroll
                 for (int j = 0; j < 8; j++) {
                     const uint32_t cj = (L.w[cc][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                    L.tok[cc * 8 + j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, cj << 4, 0, 0);
+                    const uint32_t off = ((L.valid >> (cc * 8 + j)) & 1u) ? cj << 4 : 65536u * 16u;
+                    L.tok[j] = __builtin_amdgcn_raw_buffer_load_b128(r_tok, off, 0, 0);
                 }
-        }
+            }
     }
     // the chunk starts after the lane's earlier chunks
     uint32_t cbase = 0;
@@ -879,24 +819,16 @@ __device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, U
         }
         asm volatile("" : "+v"(w[i]));
     }
-    if constexpr (CODEC == kFsst8) fsst_chunk_emit(s, w, lit, lenp, q, lane0, head);
-    else onpair_chunk_emit(s, &L.tok[c * 8], lenp, q, lane0, head);
+    if constexpr (CODEC == kFsst8) fsst_chunk_emit(s, w, lit, lenp, q);
+    else onpair_chunk_emit(s, L.tok, lenp, q);
 }
 
-// After every lane of the workgroup has assembled window `win`: each lane's
-// first 16 bytes, overwritten by the excess of the lane before, are written
-// back from `head`.  The first lane of a window has nothing to repair (and is
-// the only lane that can start with codes outside the range).
-template <int CODEC, typename S>
-__device__ __forceinline__ void fixup(S& s, const Lane<CODEC>& L, int win, const U128& head) {
-    using C = Cfg<CODEC>;
-    constexpr uint32_t K = C::WIN - C::CPL * C::W;
-    if ((int)(L.lane_pre / K) != win || L.tot == 0) return;
-    const int lane0 = (int)(L.lane_pre - s.wbase[win]);
-    if (lane0 == 0) return;
-    const u32x4 v = {(uint32_t)head.lo, (uint32_t)(head.lo >> 32), (uint32_t)head.hi, (uint32_t)(head.hi >> 32)};
-    if (L.tot >= 16) lds_put16(&s.stage[lane0], v);
-    else lds_put_exact16(&s.stage[lane0], v, L.tot);
+// Zero the staging window before an assembly (whole 16-byte words, every
+// thread a share).
+template <typename S>
+__device__ __forceinline__ void stage_zero(S& s) {
+    constexpr int n = (int)sizeof(s.stage) / 16;
+    for (int i = (int)ltid(); i < n; i += kWG) *(u32x4*)&s.stage[16 * i] = u32x4{0, 0, 0, 0};
 }
 
 // Drain window `win` (super-pass output bytes [wbase[win], wbase[win+1]))
@@ -1233,8 +1165,8 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
 }
 
 // Waves per SIMD the decode kernels are compiled for: four FSST-8 workgroups
-// per CU (128 VGPRs); OnPair-16 keeps its 64 registers of gathered token
-// entries and runs three.
+// per CU (128 VGPRs); the OnPair kernels run three (their 32 KiB staging
+// window leaves room in the LDS for three workgroups).
 template <int CODEC> constexpr int kMinWaves = CODEC == kFsst8 ? 4 : 3;
 
 // Whether the look-back sums the previous block's tiles (measured: FSST-8
@@ -1407,6 +1339,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                 if (tid == 0) s.cin = ci;
             }
         }
+        if constexpr (MODE != kModeTotals) stage_zero(s);     // the previous tile's drain is done
         __syncthreads();
         uint32_t carry = 0;
         if constexpr (CODEC == kFsst8) carry = uniform32(s.cin);
@@ -1434,16 +1367,15 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             continue;
         }
         LookBack lb{};
-        U128 head{0, 0};                // the lane's first 16 output bytes in the window being assembled
         if constexpr (MODE == kModeLookback) {
             if (wv == 0) lookback_issue<kPrevTiles<CODEC>>(p, t, tot, lb);
         }
-        assemble<CODEC>(s, L, 0, 0, head, r_tok);
+        assemble<CODEC>(s, L, 0, 0, r_tok);
         if constexpr (MODE == kModeLookback) {
             if (wv == 0) lookback_mid<kPrevTiles<CODEC>>(p, t, tot, lb);
         }
 #pragma unroll
-        for (int cc = 1; cc < P; cc++) assemble<CODEC>(s, L, 0, cc, head, r_tok);
+        for (int cc = 1; cc < P; cc++) assemble<CODEC>(s, L, 0, cc, r_tok);
         if constexpr (MODE == kModeLookback) {
             if (wv == 0) {
                 const uint64_t ex = lookback_finish<kPrevTiles<CODEC>>(p, t, tot, lb);
@@ -1492,15 +1424,15 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         if (cursor >= 0) {
             const int nwin = (int)uniform32(s.nwin);
             for (int win = 0; win < nwin; win++) {
+                // window 0 was assembled before the cursor step's barrier
                 if (win > 0) {
+                    __syncthreads();            // the previous window's drain is done
+                    stage_zero(s);
                     __syncthreads();
-                    head = U128{0, 0};
 #pragma unroll
-                    for (int cc = 0; cc < P; cc++) assemble<CODEC>(s, L, win, cc, head, r_tok);
+                    for (int cc = 0; cc < P; cc++) assemble<CODEC>(s, L, win, cc, r_tok);
                     __syncthreads();
                 }
-                fixup<CODEC>(s, L, win, head);
-                __syncthreads();
                 drain(s, p, cursor, win);
             }
             tile_offsets<CODEC, IDX, true>(s, p, g, t, cursor, tot, cin, ca, gcur, gnext);
