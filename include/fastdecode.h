@@ -87,7 +87,10 @@ typedef enum fd_status {
     FD_EOFFSETS = 7,   /* code_offsets decreasing, negative or past n_codes       */
     FD_EHIP = 8,       /* a HIP runtime call failed                               */
     FD_ENOMEM = 9,     /* allocation failed / request exceeds a memory budget     */
-    FD_ESIDECAR = 10   /* fd_decode_sidecar: stored positions differ from the codes */
+    FD_ESIDECAR = 10,  /* fd_decode_sidecar: stored positions differ from the codes */
+    FD_ETIMEOUT = 11,  /* server: a wait or a queued request's deadline passed     */
+    FD_ECANCELED = 12, /* server: the request was cancelled before it ran         */
+    FD_EBUSY = 13      /* server: the request already runs or ran (not cancelled)  */
 } fd_status;
 
 typedef enum fd_codec { FD_FSST8 = 1, FD_ONPAIR16 = 2, FD_ONPAIR12 = 3 } fd_codec;
@@ -449,11 +452,15 @@ typedef struct fd_server_config {
     int64_t max_inflight_bytes;   /* HBM budget of admitted requests; 0 = 16 GiB */
     int32_t n_slots;              /* batches on the device at once (1..64); 0 = 4 */
     int32_t max_batch;            /* requests per batch (1..65536); 0 = 64 */
+    int64_t queue_timeout_us;     /* a request still waiting for admission this long
+                                     after its submission completes with FD_ETIMEOUT
+                                     without running; 0 = no deadline */
 } fd_server_config;
 
 typedef struct fd_server_stats {
     int64_t submitted, admitted, completed, batches, queued;
     int64_t inflight_bytes, max_inflight_bytes;
+    int64_t canceled, timed_out;  /* completed without running */
 } fd_server_stats;
 
 /* cfg may be NULL (all defaults).  The server owns its streams, events,
@@ -466,6 +473,18 @@ fd_status fd_server_submit(fd_server *server, const fd_column *request, uint64_t
  * submission to the host seeing its batch complete).  Each ticket is waited
  * for once. */
 fd_status fd_server_wait(fd_server *server, uint64_t ticket, int32_t *status, double *latency_us);
+/* fd_server_wait with a time limit: FD_ETIMEOUT if the request has not
+ * completed within timeout_us microseconds (the ticket stays valid, to be
+ * waited for again); a negative timeout waits without limit.  FD_EINVAL for
+ * an unknown or already waited ticket. */
+fd_status fd_server_wait_for(fd_server *server, uint64_t ticket, int64_t timeout_us, int32_t *status,
+                             double *latency_us);
+/* Cancel a request that is still waiting for admission: FD_OK, and the
+ * request completes with status FD_ECANCELED (its outputs untouched; wait for
+ * its ticket as usual).  FD_EBUSY if it was already admitted or has
+ * completed (it then completes normally), FD_EINVAL for an unknown or already
+ * waited ticket. */
+fd_status fd_server_cancel(fd_server *server, uint64_t ticket);
 fd_status fd_server_get_stats(fd_server *server, fd_server_stats *out);
 /* Completes every queued request, then frees the server. */
 fd_status fd_server_destroy(fd_server *server);

@@ -39,9 +39,10 @@ def codes_in(codec, codes) -> int:
 ASYNC = 1
 GRAPH = 2
 
-OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS, EHIP, ENOMEM, ESIDECAR = range(11)
+(OK, EINVAL, EBADCODE, EESCAPE, ECAPACITY, EOVERFLOW, EBADDICT, EOFFSETS, EHIP, ENOMEM, ESIDECAR, ETIMEOUT, ECANCELED,
+ EBUSY) = range(14)
 STATUS_NAMES = ["FD_OK", "FD_EINVAL", "FD_EBADCODE", "FD_EESCAPE", "FD_ECAPACITY", "FD_EOVERFLOW", "FD_EBADDICT",
-                "FD_EOFFSETS", "FD_EHIP", "FD_ENOMEM", "FD_ESIDECAR"]
+                "FD_EOFFSETS", "FD_EHIP", "FD_ENOMEM", "FD_ESIDECAR", "FD_ETIMEOUT", "FD_ECANCELED", "FD_EBUSY"]
 
 
 class LibraryNotBuilt(RuntimeError):
@@ -69,14 +70,16 @@ class Column(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    """fd_server_config: HBM budget (bytes), stream slots, requests per batch (0 = default)."""
-    _fields_ = [("max_inflight_bytes", ctypes.c_int64), ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+    """fd_server_config: HBM budget (bytes), stream slots, requests per batch (0 = default), queue
+    deadline in microseconds (0 = none)."""
+    _fields_ = [("max_inflight_bytes", ctypes.c_int64), ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("queue_timeout_us", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("queued", ctypes.c_int64), ("inflight_bytes", ctypes.c_int64),
-                ("max_inflight_bytes", ctypes.c_int64)]
+                ("max_inflight_bytes", ctypes.c_int64), ("canceled", ctypes.c_int64), ("timed_out", ctypes.c_int64)]
 
 
 _lib = None
@@ -151,6 +154,10 @@ def lib():
     L.fd_server_submit.argtypes = [P, ctypes.POINTER(Column), ctypes.POINTER(ctypes.c_uint64)]
     L.fd_server_wait.restype = ctypes.c_int
     L.fd_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
+    L.fd_server_wait_for.restype = ctypes.c_int
+    L.fd_server_wait_for.argtypes = [P, ctypes.c_uint64, I64, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
+    L.fd_server_cancel.restype = ctypes.c_int
+    L.fd_server_cancel.argtypes = [P, ctypes.c_uint64]
     L.fd_server_get_stats.restype = ctypes.c_int
     L.fd_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     L.fd_server_destroy.restype = ctypes.c_int
@@ -516,9 +523,9 @@ class Server:
     ``submit`` takes a column tuple (Dict, codes, code_off, out_off, out_bytes)
     whose tensors must stay alive until ``wait`` returns for its ticket."""
 
-    def __init__(self, max_inflight_bytes: int = 0, n_slots: int = 0, max_batch: int = 0):
+    def __init__(self, max_inflight_bytes: int = 0, n_slots: int = 0, max_batch: int = 0, queue_timeout_us: int = 0):
         self._h = ctypes.c_void_p(0)
-        cfg = ServerConfig(int(max_inflight_bytes), int(n_slots), int(max_batch))
+        cfg = ServerConfig(int(max_inflight_bytes), int(n_slots), int(max_batch), int(queue_timeout_us))
         st = lib().fd_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
         if st:
             raise DecodeError(st, "fd_server_create")
@@ -539,14 +546,28 @@ class Server:
             raise DecodeError(st, "fd_server_submit")
         return int(t.value)
 
-    def wait(self, ticket: int):
-        """(fd_status, latency in microseconds) of a request."""
+    def wait(self, ticket: int, timeout_us: int | None = None):
+        """(fd_status, latency in microseconds) of a request; with a timeout,
+        None if it has not completed by then (wait for the ticket again)."""
         s = ctypes.c_int32(-1)
         lat = ctypes.c_double(0.0)
-        st = lib().fd_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(s), ctypes.byref(lat))
+        st = lib().fd_server_wait_for(self._h, ctypes.c_uint64(ticket), -1 if timeout_us is None else int(timeout_us),
+                                      ctypes.byref(s), ctypes.byref(lat))
+        if st == ETIMEOUT:
+            return None
         if st:
-            raise DecodeError(st, "fd_server_wait")
+            raise DecodeError(st, "fd_server_wait_for")
         return int(s.value), float(lat.value)
+
+    def cancel(self, ticket: int) -> bool:
+        """fd_server_cancel: True if the request was still queued (it then
+        completes with ECANCELED), False if it already runs or ran."""
+        st = lib().fd_server_cancel(self._h, ctypes.c_uint64(ticket))
+        if st == EBUSY:
+            return False
+        if st:
+            raise DecodeError(st, "fd_server_cancel")
+        return True
 
     def stats(self) -> dict:
         out = ServerStats()

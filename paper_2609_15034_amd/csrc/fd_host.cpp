@@ -396,6 +396,9 @@ const char* fd_status_str(int status) {
         case FD_EHIP: return "FD_EHIP";
         case FD_ENOMEM: return "FD_ENOMEM";
         case FD_ESIDECAR: return "FD_ESIDECAR";
+        case FD_ETIMEOUT: return "FD_ETIMEOUT";
+        case FD_ECANCELED: return "FD_ECANCELED";
+        case FD_EBUSY: return "FD_EBUSY";
         default: return "FD_UNKNOWN";
     }
 }

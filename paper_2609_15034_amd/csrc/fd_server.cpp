@@ -83,7 +83,36 @@ struct fd_server {
     void run();
     bool launch(Slot& s, std::unique_lock<std::mutex>& lk);
     void complete(Slot& s, std::unique_lock<std::mutex>& lk);
+    void finish_unrun(const Request& r, int32_t status);
+    void expire(Clock::time_point now);
 };
+
+// A request that completes without running (cancelled, or its queue deadline
+// passed): its status, and its latency up to now.
+void fd_server::finish_unrun(const Request& r, int32_t status) {
+    Done& d = done[r.ticket];
+    d.status = status;
+    d.latency_us = std::chrono::duration<double, std::micro>(Clock::now() - r.t_submit).count();
+    d.done = true;
+    stats.completed += 1;
+    if (status == FD_ECANCELED) stats.canceled += 1;
+    else stats.timed_out += 1;
+    cv_done.notify_all();
+}
+
+// Queued requests past their deadline complete with FD_ETIMEOUT.
+void fd_server::expire(Clock::time_point now) {
+    if (cfg.queue_timeout_us <= 0 || queue.empty()) return;
+    const auto limit = std::chrono::microseconds(cfg.queue_timeout_us);
+    for (auto it = queue.begin(); it != queue.end();) {
+        if (now - it->t_submit >= limit) {
+            finish_unrun(*it, FD_ETIMEOUT);
+            it = queue.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
 
 bool fd_server::launch(Slot& s, std::unique_lock<std::mutex>& lk) {
     // admit in arrival order within the budget and the batch limit
@@ -169,14 +198,16 @@ void fd_server::run() {
                 any_busy = true;
             }
         }
+        expire(Clock::now());
         for (Slot& s : slots) {
             if (!s.busy && !queue.empty()) {
                 if (launch(s, lk)) any_busy = true;
             }
         }
         if (stop && queue.empty() && !any_busy) break;
-        if (any_busy) {
-            // poll the events of running batches without holding the lock
+        if (any_busy || (cfg.queue_timeout_us > 0 && !queue.empty())) {
+            // poll the events of running batches (and the queue's deadlines)
+            // without holding the lock
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
@@ -192,7 +223,8 @@ fd_status fd_server_create(const fd_server_config* cfg, fd_server** out) {
     if (!out) return FD_EINVAL;
     *out = nullptr;
     fd_server_config c = cfg ? *cfg : fd_server_config{};
-    if (c.max_inflight_bytes < 0 || c.n_slots < 0 || c.max_batch < 0 || c.n_slots > 64 || c.max_batch > 65536)
+    if (c.max_inflight_bytes < 0 || c.n_slots < 0 || c.max_batch < 0 || c.n_slots > 64 || c.max_batch > 65536 ||
+        c.queue_timeout_us < 0)
         return FD_EINVAL;
     if (c.max_inflight_bytes == 0) c.max_inflight_bytes = (int64_t)16 << 30;
     if (c.n_slots == 0) c.n_slots = 4;
@@ -256,17 +288,40 @@ fd_status fd_server_submit(fd_server* s, const fd_column* req, uint64_t* ticket)
     return FD_OK;
 }
 
-fd_status fd_server_wait(fd_server* s, uint64_t ticket, int32_t* status, double* latency_us) {
+fd_status fd_server_wait_for(fd_server* s, uint64_t ticket, int64_t timeout_us, int32_t* status,
+                             double* latency_us) {
     if (!s) return FD_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->done.find(ticket);
-    if (it == s->done.end()) return FD_EINVAL;
-    s->cv_done.wait(lk, [&] { return s->done[ticket].done; });
+    if (s->done.find(ticket) == s->done.end()) return FD_EINVAL;
+    const auto ready = [&] { return s->done[ticket].done; };
+    if (timeout_us < 0) {
+        s->cv_done.wait(lk, ready);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+        return FD_ETIMEOUT;
+    }
     const Done d = s->done[ticket];
     s->done.erase(ticket);
     if (status) *status = d.status;
     if (latency_us) *latency_us = d.latency_us;
     return FD_OK;
+}
+
+fd_status fd_server_wait(fd_server* s, uint64_t ticket, int32_t* status, double* latency_us) {
+    return fd_server_wait_for(s, ticket, -1, status, latency_us);
+}
+
+fd_status fd_server_cancel(fd_server* s, uint64_t ticket) {
+    if (!s) return FD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->done.find(ticket) == s->done.end()) return FD_EINVAL;
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+        if (it->ticket == ticket) {
+            s->finish_unrun(*it, FD_ECANCELED);
+            s->queue.erase(it);
+            return FD_OK;
+        }
+    }
+    return FD_EBUSY;
 }
 
 fd_status fd_server_get_stats(fd_server* s, fd_server_stats* out) {

@@ -174,3 +174,12 @@ def test_profile_host_checks(fdlib):
     assert L.fd_profile_begin(1, (1 << 20) + 1) == fdlib.EINVAL
     assert L.fd_profile_end(None, None, None, None, None) == fdlib.EINVAL
     assert fdlib.PROF_KINDS[4] == "decode" and len(fdlib.PROF_KINDS) == 6
+
+
+def test_server_status_names(fdlib):
+    fd = fdlib
+    assert [fd.status_str(k) for k in (fd.ETIMEOUT, fd.ECANCELED, fd.EBUSY)] == ["FD_ETIMEOUT", "FD_ECANCELED",
+                                                                              "FD_EBUSY"]
+    L = fd.lib()
+    assert L.fd_server_cancel(None, 1) == fd.EINVAL
+    assert L.fd_server_wait_for(None, 1, 0, None, None) == fd.EINVAL

@@ -131,3 +131,71 @@ def test_server_rejects_bad_requests(pool):
         assert L.fd_server_submit(srv._h, arr, ctypes.byref(t)) == fd.EINVAL
         ticket = srv.submit(r.tup())
         assert srv.wait(ticket)[0] == 0
+
+
+def check_untouched(r):
+    """A request that never ran: its outputs hold their canary values."""
+    assert np.all(r.out.cpu().numpy() == 0xA5)
+    assert np.all(r.off.cpu().numpy() == -7)
+
+
+def check_decoded(r, st):
+    assert st == 0
+    c = r.chunk
+    assert np.array_equal(r.out.cpu().numpy()[:c.decoded_bytes], c.text)
+    assert np.array_equal(r.off.cpu().numpy().astype(np.int64), c.text_off)
+
+
+def test_wait_with_timeout_and_cancel(pool):
+    """One slot, one request per batch: a request queued behind many is not
+    done after a 1 us wait (FD_ETIMEOUT, the ticket stays valid), and queued
+    requests can be cancelled (FD_ECANCELED, outputs untouched); the others
+    decode exactly."""
+    import paper_2609_15034_amd as fd
+    dicts = make_dicts(pool)
+    big = max(range(len(pool.chunks)), key=lambda i: pool.chunks[i].decoded_bytes)
+    reqs = [Req(pool.chunks[big], dicts[pool.chunk_dict[big]]) for _ in range(24)]
+    with fd.Server(n_slots=1, max_batch=1) as srv:
+        tickets = [srv.submit(r.tup()) for r in reqs]
+        assert srv.wait(tickets[-1], timeout_us=1) is None        # 23 requests ahead of it
+        cancelled = [srv.cancel(t) for t in tickets[-6:]]
+        res = [srv.wait(t) for t in tickets]
+        with pytest.raises(fd.DecodeError):
+            srv.wait(tickets[0])                                  # each ticket is waited for once
+        with pytest.raises(fd.DecodeError):
+            srv.cancel(tickets[0])
+        stats = srv.stats()
+    assert cancelled[-1]                                          # the last one was still queued
+    n_cancelled = 0
+    for r, (st, lat), was in zip(reqs, res, [False] * 18 + cancelled):
+        if was:
+            assert st == fd.ECANCELED
+            check_untouched(r)
+            n_cancelled += 1
+        else:
+            check_decoded(r, st)
+    assert stats["canceled"] == n_cancelled and stats["completed"] == len(reqs)
+    assert stats["admitted"] == len(reqs) - n_cancelled
+
+
+def test_queue_deadline(pool):
+    """With a 1 us queue deadline and one slot, requests that wait for
+    admission complete with FD_ETIMEOUT without running; the admitted ones
+    decode exactly."""
+    import paper_2609_15034_amd as fd
+    dicts = make_dicts(pool)
+    big = max(range(len(pool.chunks)), key=lambda i: pool.chunks[i].decoded_bytes)
+    reqs = [Req(pool.chunks[big], dicts[pool.chunk_dict[big]]) for _ in range(16)]
+    with fd.Server(n_slots=1, max_batch=1, queue_timeout_us=1) as srv:
+        tickets = [srv.submit(r.tup()) for r in reqs]
+        res = [srv.wait(t) for t in tickets]
+        stats = srv.stats()
+    n_timed_out = 0
+    for r, (st, _) in zip(reqs, res):
+        if st == fd.ETIMEOUT:
+            check_untouched(r)
+            n_timed_out += 1
+        else:
+            check_decoded(r, st)
+    assert n_timed_out >= 1 and stats["timed_out"] == n_timed_out
+    assert stats["admitted"] + n_timed_out == len(reqs)
