@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <list>
+#include <map>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -210,10 +211,46 @@ void fill_table(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* 
     }
 }
 
+// Streams for the groups of a batch beyond the first, per (device, calling
+// stream): each group's kernels run on a stream of their own, forked from and
+// joined back into the caller's stream, so that a group's workgroups start as
+// soon as the previous group's last ones leave the CUs, instead of after its
+// whole launch.  At most kMaxAux calling streams get a set; batches on others
+// run their groups one after another on the calling stream.
+struct AuxSet {
+    hipStream_t s[kMaxGroups - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMaxGroups - 1] = {};
+};
+constexpr size_t kMaxAux = 64;
+std::map<std::pair<int, hipStream_t>, AuxSet> g_aux;
+
+AuxSet* aux_for(int dev, hipStream_t st) {
+    const auto key = std::make_pair(dev, st);
+    auto it = g_aux.find(key);
+    if (it != g_aux.end()) return &it->second;
+    if (g_aux.size() >= kMaxAux) return nullptr;
+    AuxSet a;
+    bool ok = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kMaxGroups - 1 && ok; i++) {
+        ok = hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        if (a.fork) (void)hipEventDestroy(a.fork);
+        for (int i = 0; i < kMaxGroups - 1; i++) {
+            if (a.s[i]) (void)hipStreamDestroy(a.s[i]);
+            if (a.join[i]) (void)hipEventDestroy(a.join[i]);
+        }
+        return nullptr;
+    }
+    return &(g_aux[key] = a);
+}
+
 // Enqueue a planned batch whose table image is in pinned memory `host`;
 // `copied` (optional) is recorded once the image has been copied.
 hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_t* ws, const uint8_t* host,
-                   int32_t* status, hipStream_t st, hipEvent_t copied = nullptr) {
+                   int32_t* status, hipStream_t st, int dev, hipEvent_t copied = nullptr) {
     hipError_t e = hipMemcpyAsync(ws + pl.off_table, host, pl.table_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     if (copied && (e = hipEventRecord(copied, st)) != hipSuccess) return e;
@@ -222,28 +259,47 @@ hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
     if (e != hipSuccess) return e;
     const DecodeParams* dp = (const DecodeParams*)(ws + pl.off_table);
     const int64_t* ft = (const int64_t*)(ws + pl.off_table + (size_t)n * sizeof(DecodeParams));
-    int k = 0;
-    for (int gi = 0; gi < kMaxGroups; gi++) {
+    // the groups' places in the table, and their launch order: the most
+    // tiles first (the smaller groups then fill the larger one's tail)
+    int first_col[kMaxGroups], first_ft[kMaxGroups], order[kMaxGroups], ng = 0;
+    for (int gi = 0, k = 0, f = 0; gi < kMaxGroups; gi++) {
         const Group& g = pl.groups[gi];
+        first_col[gi] = k;
+        first_ft[gi] = f;
         if (g.cols.empty()) continue;
+        k += (int)g.cols.size();
+        f += (int)g.cols.size() + 1;
+        order[ng++] = gi;
+    }
+    std::stable_sort(order, order + ng, [&](int a, int b) { return pl.groups[a].total > pl.groups[b].total; });
+    AuxSet* aux = ng > 1 ? aux_for(dev, st) : nullptr;
+    if (aux && (e = hipEventRecord(aux->fork, st)) != hipSuccess) return e;
+    for (int o = 0; o < ng; o++) {
+        const int gi = order[o];
+        const Group& g = pl.groups[gi];
+        hipStream_t gs = (aux && o > 0) ? aux->s[o - 1] : st;
+        if (gs != st && (e = hipStreamWaitEvent(gs, aux->fork, 0)) != hipSuccess) return e;
         unsigned* ctr = (unsigned*)(ws + 8 * gi);
         const int32_t nc = (int32_t)g.cols.size();
-        e = launch_coarse_batch(g.index_bits, dp + k, nc, g.max_samples, st);
+        const DecodeParams* gdp = dp + first_col[gi];
+        const int64_t* gft = ft + first_ft[gi];
+        e = launch_coarse_batch(g.index_bits, gdp, nc, g.max_samples, gs);
         if (e != hipSuccess) return e;
         if (pl.mode == 1) {
             unsigned long long* sum = (unsigned long long*)(ws + g.off_sum);
-            e = launch_tile_totals_batch(g.codec, g.index_bits, dp + k, ft, nc, g.total, sum, dev_cus(), st);
+            e = launch_tile_totals_batch(g.codec, g.index_bits, gdp, gft, nc, g.total, sum, dev_cus(), gs);
             if (e != hipSuccess) return e;
-            e = launch_scan_multi(sum, g.total + 1, (unsigned long long*)(ws + g.off_gsum), st);
+            e = launch_scan_multi(sum, g.total + 1, (unsigned long long*)(ws + g.off_gsum), gs);
             if (e != hipSuccess) return e;
-            e = launch_decode_batch(g.codec, g.index_bits, kModeExpand, dp + k, ft, nc, g.total, ctr, g.grid, st);
+            e = launch_decode_batch(g.codec, g.index_bits, kModeExpand, gdp, gft, nc, g.total, ctr, g.grid, gs);
         } else {
-            e = launch_decode_batch(g.codec, g.index_bits, kModeLookback, dp + k, ft, nc, g.total, ctr, g.grid, st);
+            e = launch_decode_batch(g.codec, g.index_bits, kModeLookback, gdp, gft, nc, g.total, ctr, g.grid, gs);
         }
         if (e != hipSuccess) return e;
-        k += (int)g.cols.size();
-        ft += g.cols.size() + 1;
+        if (gs != st && (e = hipEventRecord(aux->join[o - 1], gs)) != hipSuccess) return e;
     }
+    for (int o = 1; aux && o < ng; o++)
+        if ((e = hipStreamWaitEvent(st, aux->join[o - 1], 0)) != hipSuccess) return e;
     (void)cols;
     return launch_batch_status(errs, n, status, (int32_t*)(ws + kBOffStatus), st);
 }
@@ -283,6 +339,7 @@ Staging g_stage[64][kRing];
 int g_stage_next[64];
 std::unordered_map<uint64_t, int> g_tuned;                  // shape -> scale (percent)
 std::list<GraphEntry> g_graphs;                             // most recent first
+hipStream_t g_capture[64];                                  // per device: the stream graphs are recorded on
 constexpr size_t kMaxGraphs = 16;
 int g_hash_bits = 64;                                       // testing: fewer bits force collisions
 
@@ -363,7 +420,7 @@ fd_status run_once(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
     }
     if (!sg.done && hipEventCreateWithFlags(&sg.done, hipEventDisableTiming) != hipSuccess) return FD_EHIP;
     fill_table(cols, n, pl, ws, sg.buf);
-    if (enqueue(cols, n, pl, ws, sg.buf, status, st, sg.done) != hipSuccess) return FD_EHIP;
+    if (enqueue(cols, n, pl, ws, sg.buf, status, st, dev, sg.done) != hipSuccess) return FD_EHIP;
     sg.pending = true;
     return FD_OK;
 }
@@ -534,17 +591,18 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
                 if (hipHostMalloc((void**)&ne.pinned, pl.table_bytes, hipHostMallocDefault) != hipSuccess)
                     return FD_ENOMEM;
                 fill_table(cols, n_cols, pl, ws, ne.pinned);
-                hipStream_t cs = nullptr;
+                // recorded on the device's capture stream (kept: its group
+                // streams are cached per calling stream)
+                hipStream_t& cs = g_capture[dev];
                 hipGraph_t graph = nullptr;
-                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+                bool ok = cs || hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
                 ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
                 if (ok) {
-                    const bool enq = enqueue(cols, n_cols, pl, ws, ne.pinned, status, cs) == hipSuccess;
+                    const bool enq = enqueue(cols, n_cols, pl, ws, ne.pinned, status, cs, dev) == hipSuccess;
                     ok = hipStreamEndCapture(cs, &graph) == hipSuccess && enq;
                 }
                 ok = ok && hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0) == hipSuccess;
                 if (graph) (void)hipGraphDestroy(graph);
-                if (cs) (void)hipStreamDestroy(cs);
                 if (!ok) {
                     destroy_graph(ne);
                     return FD_EHIP;
