@@ -365,11 +365,11 @@ fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const f
  * out_offsets of different columns must not overlap.
  *   cols, n_cols      host array of column descriptions (0 <= n_cols <= 65536);
  *                     the description is read during the call only.
- *   tuning            NULL: a built-in autotuner times both modes at three
- *                     tile sizes on this batch the first time a batch of its
- *                     shape is seen and caches the winner; else mode (0 or 1)
- *                     applies to the batch and strings_per_tile / grid to
- *                     every column / group (0 = automatic).
+ *   tuning            NULL: the autotuner's choice for the batch's shape
+ *                     (fd_batch_autotune; found by timing the first time a
+ *                     shape is seen, then cached); else mode (0 or 1) applies
+ *                     to the batch and tile_codes / grid to every column /
+ *                     group (0 = automatic).
  *   status            device int32[n_cols + 1] or NULL (required with
  *                     FD_ASYNC): status[c] = the status of column c,
  *                     status[n_cols] = the first non-OK status in column order.
@@ -383,6 +383,38 @@ fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const f
  * enqueued.  Calls sharing a workspace must be ordered. */
 fd_status batch_decode(const fd_column *cols, int32_t n_cols, const fd_tuning *tuning, void *workspace,
                        size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
+
+/* The autotuner behind batch_decode(tuning = NULL) (the paper's performance
+ * model and launch-parameter study, Design and Microbenchmarks).  Candidates:
+ * mode 0 / 1, tiles of 100, 50 and 25% of the largest, and all or three
+ * quarters of the workgroups that fit on the device.  A residency model
+ * prunes them first: with R = the workgroups resident at once (set by the
+ * kernel's registers and LDS), a smaller tile size is tried only while the
+ * larger one leaves some codec group with fewer than 2 R tiles, and fewer
+ * workgroups only for mode 0 on groups of at least 2 R tiles.  The rest are
+ * timed on the batch (a warm-up and two timed runs each) and the fastest is
+ * kept per batch shape (per column: codec, offset width, log2 of its strings
+ * and codes) and device type.  With the environment variable
+ * FD_AUTOTUNE_CACHE naming a file, choices are appended to it and read back
+ * by later processes.
+ *
+ * fd_batch_autotune returns the choice for a batch (timing it if its shape is
+ * new, which decodes the batch into its outputs several times; the workspace
+ * is that of fd_batch_workspace_size(tuning = NULL)) and waits for the
+ * stream.  source: 0 timed now, 1 cached in this process, 2 read from the
+ * file.  fd_debug_autotune_forget clears the process's cache (the file is
+ * read again on the next lookup). */
+typedef struct fd_batch_choice {
+    int32_t mode;                 /* 0 or 1 */
+    int32_t tile_scale_pct;       /* tile size, % of the codec's largest */
+    int32_t grid_pct;             /* % of the resident workgroups launched */
+    int32_t source;
+    int32_t candidates_timed;     /* 0 unless timed now */
+} fd_batch_choice;
+
+fd_status fd_batch_autotune(const fd_column *cols, int32_t n_cols, void *workspace, size_t workspace_bytes,
+                            void *hip_stream, fd_batch_choice *out);
+fd_status fd_debug_autotune_forget(void);
 
 /* The FD_GRAPH cache keeps at most 16 graphs, least recently used first out.
  * A cached graph is replayed only for a batch equal to the recorded one in

@@ -69,6 +69,12 @@ class Column(ctypes.Structure):
                 ("out_offsets", ctypes.c_void_p), ("out_bytes", ctypes.c_void_p), ("out_capacity", ctypes.c_int64)]
 
 
+class BatchChoice(ctypes.Structure):
+    """fd_batch_choice: the batch autotuner's choice."""
+    _fields_ = [("mode", ctypes.c_int32), ("tile_scale_pct", ctypes.c_int32), ("grid_pct", ctypes.c_int32),
+                ("source", ctypes.c_int32), ("candidates_timed", ctypes.c_int32)]
+
+
 class ServerConfig(ctypes.Structure):
     """fd_server_config: HBM budget (bytes), stream slots, requests per batch (0 = default), queue
     deadline in microseconds (0 = none)."""
@@ -125,6 +131,10 @@ def lib():
     L.fd_debug_graph_hash_bits.argtypes = [I32]
     L.fd_debug_graph_count.restype = ctypes.c_int32
     L.fd_debug_graph_count.argtypes = []
+    L.fd_batch_autotune.restype = ctypes.c_int
+    L.fd_batch_autotune.argtypes = [ctypes.POINTER(Column), I32, P, S, P, ctypes.POINTER(BatchChoice)]
+    L.fd_debug_autotune_forget.restype = ctypes.c_int
+    L.fd_debug_autotune_forget.argtypes = []
     L.fd_profile_begin.restype = ctypes.c_int
     L.fd_profile_begin.argtypes = [ctypes.c_uint32, ctypes.c_int32]
     L.fd_profile_end.restype = ctypes.c_int
@@ -454,6 +464,25 @@ def batch_workspace_size(cols, tuning=None) -> int:
     if st:
         raise DecodeError(st, "fd_batch_workspace_size")
     return int(out.value)
+
+
+def batch_autotune(cols, workspace, stream=None) -> dict:
+    """fd_batch_autotune: the autotuner's choice for a batch of column tuples
+    (timed now if its shape is new)."""
+    arr = make_columns(cols)
+    out = BatchChoice()
+    st = lib().fd_batch_autotune(arr, len(cols), _ptr(workspace), workspace.numel(), _stream_handle(stream),
+                                 ctypes.byref(out))
+    if st:
+        raise DecodeError(st, "fd_batch_autotune")
+    return {k: int(getattr(out, k)) for k, _ in BatchChoice._fields_}
+
+
+def debug_autotune_forget() -> None:
+    """Testing hook: clear the process's autotuner cache."""
+    st = lib().fd_debug_autotune_forget()
+    if st:
+        raise DecodeError(st, "fd_debug_autotune_forget")
 
 
 def debug_graph_hash_bits(bits: int) -> None:

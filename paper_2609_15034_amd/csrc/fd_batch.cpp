@@ -13,6 +13,8 @@
 // turns the error words into per-column statuses.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -91,7 +93,7 @@ bool column_ok(const fd_column& c) {
 // column's codes per tile, else `scale` percent of the largest tile (rounded
 // to whole chunks).
 bool make_plan(const fd_column* cols, int32_t n, int64_t tc_fixed, int scale, int grid_req, int mode,
-               BatchPlan* pl) {
+               BatchPlan* pl, int grid_pct = 100) {
     pl->mode = mode;
     pl->tcodes.assign(n, 0);
     pl->n_tiles.assign(n, 0);
@@ -152,7 +154,10 @@ bool make_plan(const fd_column* cols, int32_t n, int64_t tc_fixed, int scale, in
     pl->bytes = align_up(pl->off_table + tb, 256);
     for (Group& g : pl->groups) {
         if (g.cols.empty()) continue;
-        int grid = grid_req ? grid_req : resident_grid_batch(g.codec, g.index_bits, mode == 1 ? kModeExpand : kModeLookback);
+        int grid = grid_req ? grid_req
+                            : (int)((int64_t)resident_grid_batch(g.codec, g.index_bits,
+                                                                 mode == 1 ? kModeExpand : kModeLookback) *
+                                    grid_pct / 100);
         if ((int64_t)grid > g.total) grid = (int)g.total;
         g.grid = grid < 1 ? 1 : grid;
     }
@@ -337,7 +342,13 @@ struct GraphEntry {
 std::mutex g_bmu;
 Staging g_stage[64][kRing];
 int g_stage_next[64];
-std::unordered_map<uint64_t, int> g_tuned;                  // shape -> scale (percent)
+// the autotuner's choice for a batch shape
+struct Choice {
+    int mode = 0, scale = 100, grid_pct = 100;
+    bool from_file = false;
+};
+std::unordered_map<uint64_t, Choice> g_tuned;               // shape (and device) -> choice
+bool g_tuned_file_read = false;                             // the persisted choices, read once
 std::list<GraphEntry> g_graphs;                             // most recent first
 hipStream_t g_capture[64];                                  // per device: the stream graphs are recorded on
 constexpr size_t kMaxGraphs = 16;
@@ -425,38 +436,146 @@ fd_status run_once(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
     return FD_OK;
 }
 
-// Autotune: time every candidate (mode, scale) on this batch, keep the fastest.
+// Autotune.  Candidates: mode (look-back or three phases) x tile size (100,
+// 50, 25% of the largest) x resident workgroups (all, or three quarters: the
+// look-back's waits on other tiles can favour fewer workgroups per CU).  A
+// residency model prunes them before any is timed (the paper's performance
+// model: a launch keeps R = CUs x workgroups-per-CU tiles in flight, set by
+// the kernel's registers and LDS): a smaller tile size is tried only while
+// the larger one leaves some group with fewer than 2 R tiles (too few to
+// fill the device twice over), and fewer workgroups only for the look-back
+// and only on groups of at least 2 R tiles.  Each survivor runs once to warm
+// up and twice timed; the fastest is kept.
 fd_status autotune(const fd_column* cols, int32_t n, uint8_t* ws, size_t ws_bytes, hipStream_t st, int dev,
-                   int* best_mode, int* best_scale) {
+                   Choice* best_out, int* n_timed) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return FD_EHIP;
     float best = 1e30f;
-    *best_mode = 0;
-    *best_scale = kScales[0];
+    Choice best_c;
     fd_status rc = FD_OK;
-    for (int i = 0; i < 2 * kNumScales && rc == FD_OK; i++) {
-        const int mode = i / kNumScales, scale = kScales[i % kNumScales];
-        BatchPlan pl;
-        if (!make_plan(cols, n, 0, scale, 0, mode, &pl) || pl.bytes > ws_bytes) continue;
-        float ms_sum = 0.f;
-        for (int rep = 0; rep < 3 && rc == FD_OK; rep++) {      // one warm-up, two timed
-            if (hipEventRecord(a, st) != hipSuccess) { rc = FD_EHIP; break; }
-            rc = run_once(cols, n, pl, ws, nullptr, st, dev);
-            if (rc != FD_OK) break;
-            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) { rc = FD_EHIP; break; }
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, a, b) != hipSuccess) { rc = FD_EHIP; break; }
-            if (rep > 0) ms_sum += ms;
-        }
-        if (rc == FD_OK && ms_sum < best) {
-            best = ms_sum;
-            *best_mode = mode;
-            *best_scale = scale;
+    *n_timed = 0;
+    for (int mode = 0; mode < 2 && rc == FD_OK; mode++) {
+        bool larger_fills = false;          // the previous (larger) tile size gave every group >= 2 R tiles
+        for (int si = 0; si < kNumScales && rc == FD_OK; si++) {
+            const int scale = kScales[si];
+            BatchPlan pl;
+            if (!make_plan(cols, n, 0, scale, 0, mode, &pl) || pl.bytes > ws_bytes) continue;
+            if (si > 0 && larger_fills) break;
+            bool fills = true, big = false;
+            for (const Group& g : pl.groups) {
+                if (g.cols.empty()) continue;
+                const int64_t R = resident_grid_batch(g.codec, g.index_bits, mode == 1 ? kModeExpand : kModeLookback);
+                fills = fills && g.total >= 2 * R;
+                big = big || g.total >= 2 * R;
+            }
+            larger_fills = fills;
+            for (int gp : {100, 75}) {
+                if (gp != 100 && (mode != 0 || !big)) continue;
+                BatchPlan pg;
+                if (!make_plan(cols, n, 0, scale, 0, mode, &pg, gp)) continue;
+                float ms_sum = 0.f;
+                for (int rep = 0; rep < 3 && rc == FD_OK; rep++) {
+                    if (hipEventRecord(a, st) != hipSuccess) { rc = FD_EHIP; break; }
+                    rc = run_once(cols, n, pg, ws, nullptr, st, dev);
+                    if (rc != FD_OK) break;
+                    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                        rc = FD_EHIP;
+                        break;
+                    }
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) { rc = FD_EHIP; break; }
+                    if (rep > 0) ms_sum += ms;
+                }
+                *n_timed += 1;
+                if (rc == FD_OK && ms_sum < best) {
+                    best = ms_sum;
+                    best_c.mode = mode;
+                    best_c.scale = scale;
+                    best_c.grid_pct = gp;
+                }
+            }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    *best_out = best_c;
     return rc;
+}
+
+// The persisted choices: with FD_AUTOTUNE_CACHE naming a file, the choices
+// found by timing are appended to it, one line each
+//   fastdecode-autotune 1 <key, 16 hex digits> <mode> <tile %> <workgroup %>
+// and read back by later processes; the key hashes the batch shape and the
+// device's architecture name and CU count (not its ordinal).
+uint64_t device_key(int dev) {
+    static uint64_t keys[64];
+    if (!keys[dev]) {
+        hipDeviceProp_t prop;
+        uint64_t h = 0xd1ce;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            for (const char* c = prop.gcnArchName; *c; c++) h = mix(h, (uint64_t)(unsigned char)*c);
+            h = mix(h, (uint64_t)prop.multiProcessorCount);
+        }
+        keys[dev] = h | 1;
+    }
+    return keys[dev];
+}
+
+uint64_t persist_key(const fd_column* cols, int32_t n, int dev) {
+    return mix(shape_key(cols, n, 0), device_key(dev));
+}
+
+void read_tuned_file() {
+    g_tuned_file_read = true;
+    const char* path = getenv("FD_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char tag[32];
+    int ver = 0, mode = 0, scale = 0, gp = 0;
+    unsigned long long key = 0;
+    while (fscanf(f, "%31s %d %llx %d %d %d", tag, &ver, &key, &mode, &scale, &gp) == 6) {
+        if (strcmp(tag, "fastdecode-autotune") != 0 || ver != 1) continue;
+        const bool ok_scale = std::find(std::begin(kScales), std::end(kScales), scale) != std::end(kScales);
+        if ((mode != 0 && mode != 1) || !ok_scale || (gp != 100 && gp != 75)) continue;
+        Choice c;
+        c.mode = mode;
+        c.scale = scale;
+        c.grid_pct = gp;
+        c.from_file = true;
+        g_tuned[(uint64_t)key] = c;
+    }
+    fclose(f);
+}
+
+void write_tuned(uint64_t key, const Choice& c) {
+    const char* path = getenv("FD_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "fastdecode-autotune 1 %016llx %d %d %d\n", (unsigned long long)key, c.mode, c.scale, c.grid_pct);
+    fclose(f);
+}
+
+// The choice for a batch: cached (in memory, or from the file), else timed.
+// `source`: 0 timed now, 1 from this process's cache, 2 read from the file.
+fd_status choose(const fd_column* cols, int32_t n, uint8_t* ws, size_t ws_bytes, hipStream_t st, int dev, Choice* c,
+                 int* source, int* n_timed) {
+    if (!g_tuned_file_read) read_tuned_file();
+    const uint64_t key = persist_key(cols, n, dev);
+    *n_timed = 0;
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        *c = it->second;
+        *source = c->from_file ? 2 : 1;
+        return FD_OK;
+    }
+    const fd_status rc = autotune(cols, n, ws, ws_bytes, st, dev, c, n_timed);
+    if (rc != FD_OK) return rc;
+    g_tuned[key] = *c;
+    write_tuned(key, *c);
+    *source = 0;
+    return FD_OK;
 }
 
 fd_status read_status(uint8_t* ws, hipStream_t st) {
@@ -512,6 +631,42 @@ int32_t fd_debug_graph_count(void) {
     return (int32_t)g_graphs.size();
 }
 
+fd_status fd_batch_autotune(const fd_column* cols, int32_t n_cols, void* workspace, size_t workspace_bytes,
+                            void* hip_stream, fd_batch_choice* out) {
+    try {
+        if (!out || n_cols <= 0 || n_cols > kMaxCols || !cols) return FD_EINVAL;
+        if (!workspace || ((uintptr_t)workspace & 255)) return FD_EINVAL;
+        for (int32_t c = 0; c < n_cols; c++)
+            if (!column_ok(cols[c])) return FD_EINVAL;
+        size_t need = 0;
+        if (fd_batch_workspace_size(cols, n_cols, nullptr, &need) != FD_OK || workspace_bytes < need) return FD_EINVAL;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return FD_EHIP;
+        std::lock_guard<std::mutex> lk(g_bmu);
+        Choice c;
+        int source = 0, n_timed = 0;
+        const fd_status rc = choose(cols, n_cols, (uint8_t*)workspace, workspace_bytes, (hipStream_t)hip_stream, dev,
+                                    &c, &source, &n_timed);
+        if (rc != FD_OK) return rc;
+        if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return FD_EHIP;
+        out->mode = c.mode;
+        out->tile_scale_pct = c.scale;
+        out->grid_pct = c.grid_pct;
+        out->source = source;
+        out->candidates_timed = n_timed;
+        return FD_OK;
+    } catch (...) {
+        return FD_ENOMEM;
+    }
+}
+
+fd_status fd_debug_autotune_forget(void) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    g_tuned.clear();
+    g_tuned_file_read = false;
+    return FD_OK;
+}
+
 fd_status fd_batch_workspace_size(const fd_column* cols, int32_t n_cols, const fd_tuning* tuning, size_t* bytes) {
     if (!bytes || n_cols < 0 || n_cols > kMaxCols || (n_cols > 0 && !cols)) return FD_EINVAL;
     for (int32_t c = 0; c < n_cols; c++)
@@ -556,26 +711,24 @@ fd_status batch_decode(const fd_column* cols, int32_t n_cols, const fd_tuning* t
         // the tile-size choice
         int64_t sb_fixed = tuning ? tuning->tile_codes : 0;
         int grid = tuning ? tuning->grid : 0;
-        int scale = 100, mode = tuning ? tuning->mode : 0;
+        int scale = 100, mode = tuning ? tuning->mode : 0, grid_pct = 100;
         if (!tuning) {
-            const uint64_t sk = shape_key(cols, n_cols, dev);
-            auto it = g_tuned.find(sk);
-            if (it != g_tuned.end()) {
-                mode = it->second / 1000;
-                scale = it->second % 1000;
-            } else {
-                const fd_status rc = autotune(cols, n_cols, ws, workspace_bytes, st, dev, &mode, &scale);
-                if (rc != FD_OK) return rc;
-                g_tuned[sk] = mode * 1000 + scale;
-            }
+            Choice c;
+            int source = 0, n_timed = 0;
+            const fd_status rc = choose(cols, n_cols, ws, workspace_bytes, st, dev, &c, &source, &n_timed);
+            if (rc != FD_OK) return rc;
+            mode = c.mode;
+            scale = c.scale;
+            grid_pct = c.grid_pct;
         }
         BatchPlan pl;
-        if (!make_plan(cols, n_cols, sb_fixed, scale, grid, mode, &pl)) return FD_EINVAL;
+        if (!make_plan(cols, n_cols, sb_fixed, scale, grid, mode, &pl, grid_pct)) return FD_EINVAL;
         if (workspace_bytes < pl.bytes) return FD_EINVAL;
 
         if (flags & FD_GRAPH) {
             GraphKey key =
-                exact_key(cols, n_cols, workspace, workspace_bytes, status, sb_fixed, mode * 1000 + scale, grid, dev);
+                exact_key(cols, n_cols, workspace, workspace_bytes, status, sb_fixed, mode * 1000 + scale,
+                          grid ? grid : -grid_pct, dev);
             GraphEntry* ge = nullptr;
             for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
                 if (it->key == key) {
