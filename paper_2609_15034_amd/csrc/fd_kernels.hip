@@ -609,14 +609,17 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
         F &= L.valid;
         // the parity entering the tile, at its first code
         if (tid == 0) F |= tile_entry_mask(g.a - q0, carry);
-        if (g.a > g.pos0) carry = 0;
         const bool all_ff = (F == 0xffffffffu);
         const uint32_t trail = __clz(~F);                       // 255s at the top of the lane
         const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
         const uint64_t m = M & ((1ull << lane) - 1ull);
         if (lane == 0) s.wpar[wv] = M ? (1u | ((uint32_t)((T >> (63 - __clzll(M))) & 1ull) << 1)) : 0u;
         __syncthreads();
-        uint32_t cw = carry, cout = carry;
+        // the parity entering the tile (written to s.cin by wave 0 before the
+        // barrier); applied at the first code already when the tile starts
+        // inside a chunk
+        const uint32_t c0 = g.a > g.pos0 ? 0u : uniform32(s.cin);
+        uint32_t cw = c0, cout = c0;
 #pragma unroll
         for (int i = 0; i < kNWave; i++) {
             const uint32_t v = s.wpar[i];
@@ -683,10 +686,20 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
     }
     L.lane_pre = basew + incl - tot;
     s.lane_pre[tid] = L.lane_pre;
-    // staging windows: window of a lane = lane_pre / K; first lanes record bases.
-    // The previous lane's prefix is this one's minus its total.
+    // staging windows: window of a lane = lane_pre / K; first lanes record
+    // bases (window 0 starts at 0).  A tile whose output fits one window (the
+    // usual case) needs no barrier here: its window count and end are read
+    // after the cursor step's barrier.
+    constexpr uint32_t K = C::WIN - C::CPL * C::W;   // a lane writes at most CPL * W bytes
+    if (uniform32(total) < K) {
+        if (tid == 0) {
+            s.nwin = 1;
+            s.wbase[0] = 0;
+            s.wbase[1] = total;
+        }
+        return uniform32(total);
+    }
     {
-        constexpr uint32_t K = C::WIN - C::CPL * C::W;   // a lane writes at most CPL * W bytes
         const uint32_t wl = L.lane_pre / K;
         const uint32_t tprev = __shfl_up(tot, 1u);
         const uint32_t pprev = lane ? L.lane_pre - tprev : (wv ? basew - s.wlast[wv - 1] : 0u);
@@ -800,7 +813,7 @@ __device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, c
 #pragma unroll
         for (int i = 0; i < C::CPC / 4; i++)
             if (cc < c) cbase = __builtin_amdgcn_sad_u8(L.lenp[cc][i], 0u, cbase);
-    const int lane0 = (int)(L.lane_pre - s.wbase[win]);
+    const int lane0 = (int)(L.lane_pre - (win == 0 ? 0u : s.wbase[win]));
     int q = lane0 + (int)cbase;
     // opaque copies: keeps the compiler from hoisting every per-code predicate
     // out of the window loop (they would all stay live)
@@ -1331,19 +1344,23 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         }
         OffRegs<CODEC, IDX> orr;
         offsets_prefetch<CODEC, IDX>(p, min(max(gcur, (int64_t)0) << p.g_shift, p.n_strings), orr);
+        uint32_t s_cin_local = 0;
         if constexpr (CODEC == kFsst8) {
             if (wv == 0) {
                 const int64_t ca_c = min(max(ca, (int64_t)0), p.n_codes);
                 const uint32_t first = pf ? pf_byte : fsst_window_byte(p.codes, ca_c, g.a);
-                const uint32_t ci = fsst_carry_in_from(p.codes, ca_c, g.a, first);
-                if (tid == 0) s.cin = ci;
+                s_cin_local = fsst_carry_in_from(p.codes, ca_c, g.a, first);
+                if (tid == 0) s.cin = s_cin_local;
             }
         }
-        if constexpr (MODE != kModeTotals) stage_zero(s);     // the previous tile's drain is done
-        __syncthreads();
+        // (the previous tile's drain is done: its last barrier)
+        if constexpr (MODE != kModeTotals) stage_zero(s);
+        // FSST-8: the entry parity, computed by wave 0 and shared through s.cin
+        // at the length scan's first barrier
         uint32_t carry = 0;
-        if constexpr (CODEC == kFsst8) carry = uniform32(s.cin);
-        const uint32_t cin = carry;
+        if constexpr (CODEC == kFsst8) {
+            if (wv == 0) carry = s_cin_local;
+        }
         // the id after this tile, published at the cursor step.  Without a
         // look-back it is requested now, so that the atomic's round trip
         // overlaps the length scan and the assembly; the single pass requests
@@ -1353,6 +1370,8 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         if (MODE != kModeLookback && tid == 0) nid = atomicAdd(ctr, 1u);
 
         const uint32_t tot = lengths<CODEC>(s, p, g, 0, L, carry, true, r_len, r_tok);
+        uint32_t cin = 0;
+        if constexpr (CODEC == kFsst8) cin = uniform32(s.cin);    // (written before the scan's barriers)
         offsets_stage<CODEC, IDX>(s, orr);      // read after later barriers
         if constexpr (MODE == kModeTotals) {
             // the sidecar build: every check of the decode, the tile's total, no output

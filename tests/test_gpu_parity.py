@@ -350,3 +350,49 @@ def test_bad_offsets_anywhere(datagen_mod, mode, tc):
         if np.all(np.diff(off) >= 0):
             continue
         assert_parity("fsst8", c.codes, off, c.dict_bytes, c.dict_lens, tuning=tu(mode, tc))
+
+
+# --------------------------------------------------------------------------- #
+# tiles whose output spans several staging windows (long tokens at full tile
+# sizes), next to tiles of one window, with escapes
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("long_share", [1.0, 0.5])
+def test_fsst_multi_window_tiles(mode, long_share):
+    """254 eight-byte symbols and code 254 of one byte: at the full tile of
+    8,176 codes a tile decodes to up to 64 KiB, several 16 KiB windows;
+    long_share < 1 mixes in short codes and escapes, so neighbouring tiles
+    take one window or several."""
+    rng = np.random.default_rng(int(long_share * 10) + 17 * mode)
+    syms = [bytes(rng.integers(0, 256, 8, dtype=np.uint8)) for _ in range(254)] + [b"\x07"]
+    db, dl = pack(syms)
+    n = 300_000
+    codes = rng.integers(0, 254, n).astype(np.uint8)
+    short = rng.random(n) > long_share
+    codes[short] = 254
+    esc = np.flatnonzero(rng.random(n - 1) < 0.02 * (1.0 - long_share))
+    codes[esc] = 255                               # an escape; its literal is the next byte
+    cuts = np.sort(rng.choice(np.arange(1, n), 2000, replace=False))
+    codes[cuts - 1] = 254                          # no string ends on an escape
+    codes[-1] = 254
+    code_off = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    exp = assert_parity("fsst8", codes, code_off, db, dl, tuning=tu(mode))
+    assert exp.status == 0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_onpair_multi_window_tiles(mode):
+    """Sixteen-byte tokens: a full OnPair tile of 4,088 codes decodes to 64
+    KiB, two or three 32 KiB windows; one-byte tokens in half the tiles'
+    stretches give tiles of one window next to them."""
+    rng = np.random.default_rng(23 + mode)
+    toks = [bytes(rng.integers(0, 256, 16, dtype=np.uint8)) for _ in range(1000)] + [bytes([b]) for b in range(256)]
+    db, dl = pack(toks)
+    n = 200_000
+    codes = rng.integers(0, 1000, n).astype(np.uint16)
+    stretch = (np.arange(n) // 3000) % 2 == 1
+    codes[stretch] = 1000 + rng.integers(0, 256, int(stretch.sum())).astype(np.uint16)
+    cuts = np.sort(rng.choice(np.arange(1, n), 5000, replace=False))
+    code_off = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    exp = assert_parity("onpair16", codes, code_off, db, dl, tuning=tu(mode))
+    assert exp.status == 0
