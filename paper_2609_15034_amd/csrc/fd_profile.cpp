@@ -4,6 +4,7 @@
 // so no allocation happens between the launches being timed.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -14,7 +15,7 @@ namespace {
 
 struct ProfState {
     std::mutex m;
-    bool on = false;
+    std::atomic<bool> on{false};
     unsigned mask = 0;
     int device = -1;
     std::vector<hipEvent_t> ev;      // 2 per slot: start, end
@@ -39,7 +40,7 @@ void destroy_events(ProfState& s) {
 
 int prof_begin(int kind, hipStream_t st) {
     ProfState& s = prof();
-    if (!s.on) return -1;                        // unsynchronised peek; the flag is set before timed work
+    if (!s.on.load(std::memory_order_relaxed)) return -1;   // the common case: no profile open
     std::lock_guard<std::mutex> g(s.m);
     if (!s.on || !(s.mask & (1u << kind))) return -1;
     int dev = -1;
