@@ -32,9 +32,11 @@ using namespace fd;
 
 namespace {
 
-constexpr size_t kBHdr = 256;          // group tile counters (8 bytes each) and the status word
-constexpr size_t kBOffStatus = 128;
 constexpr int kMaxGroups = 6;          // (codec, offset width) pairs
+constexpr size_t kBOffStatus = 128;    // the status word
+constexpr size_t kBOffCounters = 256;  // a counter block (tile queues) per group
+constexpr size_t kBHdr = kBOffCounters + kMaxGroups * kCounterBlockBytes;
+static_assert(kBHdr % 256 == 0, "the column states start 256-byte aligned");
 constexpr int32_t kMaxCols = 65536;
 
 // Candidate tile sizes of the autotuner: fractions (percent) of the largest
@@ -284,7 +286,7 @@ hipError_t enqueue(const fd_column* cols, int32_t n, const BatchPlan& pl, uint8_
         const Group& g = pl.groups[gi];
         hipStream_t gs = (aux && o > 0) ? aux->s[o - 1] : st;
         if (gs != st && (e = hipStreamWaitEvent(gs, aux->fork, 0)) != hipSuccess) return e;
-        unsigned* ctr = (unsigned*)(ws + 8 * gi);
+        unsigned* ctr = (unsigned*)(ws + kBOffCounters + kCounterBlockBytes * gi);
         const int32_t nc = (int32_t)g.cols.size();
         const DecodeParams* gdp = dp + first_col[gi];
         const int64_t* gft = ft + first_ft[gi];

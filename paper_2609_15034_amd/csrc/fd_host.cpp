@@ -98,11 +98,13 @@ int resident_grid_batch(int codec, int index_bits, int mode) {
 
 namespace {
 
-constexpr size_t kHdr = 256;                 // err, counters, status words
+// workspace header: the error word, status words, then the counter block
 constexpr size_t kOffErr = 0;
-constexpr size_t kOffCounters = 8;
 constexpr size_t kOffStatus = 16;
 constexpr size_t kOffBadFlag = 20;
+constexpr size_t kOffCounters = 256;
+constexpr size_t kHdr = kOffCounters + kCounterBlockBytes;
+static_assert(kHdr % 256 == 0, "the tile words start 256-byte aligned");
 constexpr size_t kTok16Bytes = 65536 * 16;
 constexpr size_t kTokLenBytes = 65536;
 

@@ -35,6 +35,19 @@ constexpr int kBlk = 1 << kBlkShift;
 constexpr int kModeLookback = 0;    // single pass, decoupled look-back for tile cursors
 constexpr int kModeTotals = 1;      // three-phase: tile totals only
 constexpr int kModeExpand = 2;      // three-phase / sidecar: expand with stored tile cursors (checked)
+// Tile queues.  Workgroups take tiles from counters in device memory.  One
+// counter takes about 12 ns per device-scope atomic on the same address, a
+// limit the decode of a 1 GiB column (about 10^5 tiles) reaches, so a decode
+// that needs no order splits its tiles into kQueues contiguous ranges, each
+// with its own counter in its own 256-byte line; workgroup b starts on range
+// b % kQueues (the workgroups of one XCD, as the dispatcher deals them out)
+// and moves on to the next ranges when its own runs out.  The single pass
+// keeps one queue: its look-back needs the tiles taken in order.
+// A counter block: word 0 counts finished workgroups, queue q's counter is
+// word kQueueStride * (q + 1).
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 64;
+constexpr size_t kCounterBlockBytes = 4 * (size_t)kQueueStride * (kQueues + 1);
 
 // tile state words (look-back): 2 flag bits + 62 value bits
 constexpr uint64_t kFlagAgg = 1ull << 62;
@@ -78,7 +91,7 @@ struct DecodeParams {
     int32_t off_pref;              // code offsets a tile prefetches from its coarse sample on
     // workspace
     unsigned long long* err;
-    unsigned* counters;            // [0] tile counter, [1] finished workgroups
+    unsigned* counters;            // a counter block (kCounterBlockBytes): tile queues, finished workgroups
     unsigned long long* tagg;      // per tile: aggregate (look-back) / total / cursor (three phases, sidecar:
                                    // n_tiles + 1 int64 entries, the last the decoded total)
     unsigned long long* bstate;    // per block of kBlk tiles: look-back state

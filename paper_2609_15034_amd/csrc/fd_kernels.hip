@@ -1226,7 +1226,35 @@ struct ColumnBatch {
 };
 
 // --------------------------------------------------------------------------
-// the decode loop of one workgroup: tiles from the counter until it runs out
+// The tile queues of a launch (thread 0 of a workgroup uses them): tiles
+// [0, n_all) split into nq contiguous ranges, range q taken in order through
+// its counter.  take() issues the atomic on the current range; resolve()
+// turns its result into a tile id, moving on to the next ranges while the
+// current one is used up, and returns n_all once every range is.  Each tile
+// is taken exactly once, and a workgroup stops only after it has found every
+// range used up.
+// --------------------------------------------------------------------------
+struct TileQueue {
+    unsigned* base;       // counter block
+    int64_t n_all;
+    int nq, q, left;
+    __device__ TileQueue(unsigned* b, int64_t n, int queues)
+        : base(b), n_all(n), nq(queues), q((int)(blockIdx.x % (unsigned)queues)), left(queues) {}
+    __device__ int64_t lo(int k) const { return (int64_t)k * n_all / nq; }
+    __device__ unsigned take() const { return atomicAdd(&base[kQueueStride * (q + 1)], 1u); }
+    __device__ int64_t resolve(unsigned raw) {
+        for (;;) {
+            const int64_t t = lo(q) + (int64_t)raw;
+            if (t < lo(q + 1)) return t;
+            if (--left == 0) return n_all;
+            q = (q + 1 == nq) ? 0 : q + 1;
+            raw = take();
+        }
+    }
+};
+
+// --------------------------------------------------------------------------
+// the decode loop of one workgroup: tiles from the queues until they run out
 // --------------------------------------------------------------------------
 template <int CODEC, typename IDX, int MODE, typename SRC>
 __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
@@ -1234,11 +1262,11 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     constexpr int P = C::P;
     const unsigned tid = ltid(), wv = tid >> 6;
     const int64_t n_all = src.n_tiles();
-    unsigned* const ctr = src.counter();
-    // Tiles come from a global counter, in increasing order (the look-back
-    // needs it; in the other modes it spreads the workgroups of a CU over
-    // different steps of their tiles, which measured faster than fixed shares).
-    if (tid == 0) s.next_id = (int32_t)atomicAdd(ctr, 1u);
+    // Tiles come from counters (dynamic shares measured faster than fixed
+    // ones: they spread the workgroups of a CU over different steps of their
+    // tiles).  The look-back needs them taken in increasing order: one queue.
+    TileQueue tq(src.counter(), n_all, MODE == kModeLookback ? 1 : kQueues);
+    if (tid == 0) s.next_id = (int32_t)tq.resolve(tq.take());
     __syncthreads();
     int64_t v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
     int col = -1;
@@ -1306,7 +1334,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                         if ((t & (kBlk - 1)) == kBlk - 1) lb_publish(&p.bstate[t >> kBlkShift], kFlagIncl);
                     }
                 }
-                s.next_id = (int32_t)atomicAdd(ctr, 1u);
+                s.next_id = (int32_t)tq.resolve(tq.take());
             }
             __syncthreads();
             v = (int64_t)(uint32_t)uniform32((uint32_t)s.next_id);
@@ -1367,7 +1395,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
         // it at the cursor step (tiles then start in about the order of their
         // ids, which its look-back wants)
         uint32_t nid = 0;
-        if (MODE != kModeLookback && tid == 0) nid = atomicAdd(ctr, 1u);
+        if (MODE != kModeLookback && tid == 0) nid = tq.take();
 
         const uint32_t tot = lengths<CODEC>(s, p, g, 0, L, carry, true, r_len, r_tok);
         uint32_t cin = 0;
@@ -1377,7 +1405,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             // the sidecar build: every check of the decode, the tile's total, no output
             if (tid == 0) {
                 p.tagg[t] = tot;
-                s.next_id = (int32_t)nid;
+                s.next_id = (int32_t)tq.resolve(nid);
             }
             __syncthreads();            // the staged offsets
             tile_offsets<CODEC, IDX, false>(s, p, g, t, 0, tot, cin, ca, gcur, gnext);
@@ -1414,7 +1442,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             }
         }
         // the next tile's id
-        if (tid == 0) s.next_id = (int32_t)(MODE == kModeLookback ? atomicAdd(ctr, 1u) : nid);
+        if (tid == 0) s.next_id = (int32_t)tq.resolve(MODE == kModeLookback ? tq.take() : nid);
         __syncthreads();
         const int64_t cursor = uniform64(s.cursor);
         // the next tile's coarse groups and first window, loaded now (they
@@ -1479,7 +1507,7 @@ __global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode(DecodeParams p
     if (MODE != kModeTotals) {
         __threadfence();
         if (ltid() == 0) {
-            const unsigned prev = atomicAdd(&p.counters[1], 1u);
+            const unsigned prev = atomicAdd(&p.counters[0], 1u);
             if (prev == gridDim.x - 1) {
                 __threadfence();
                 const unsigned long long e = __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1538,8 +1566,7 @@ __global__ void k_reset(unsigned long long* err, unsigned* counters, unsigned lo
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + ltid();
     if (i == 0) {
         if (err) *err = ~0ull;
-        counters[0] = 0;
-        counters[1] = 0;
+        for (int q = 0; q <= kQueues; q++) counters[q * kQueueStride] = 0;
     }
     for (int64_t k = i; k < n; k += (int64_t)gridDim.x * blockDim.x) z[k] = 0;
 }
