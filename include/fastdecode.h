@@ -474,7 +474,8 @@ fd_status fd_profile_end(double *total_ms, int64_t *launches, double *min_ms, do
  * whenever a slot is free it admits waiting requests in arrival order while the
  * device bytes they hold (codes, code and Arrow offsets, output capacity,
  * workspace) stay within max_inflight_bytes, up to max_batch per batch, and runs
- * them as one asynchronous batch_decode on the slot's stream.  Requests that
+ * them as one asynchronous batch_decode (three phases, mode 1) on the slot's
+ * stream.  Requests that
  * arrive while batches run are admitted as slots and budget free up, so their
  * work overlaps on the device.  Each request's bytes and offsets are those of
  * fd_decode on the same column. */

@@ -10,6 +10,11 @@
 // admitted as soon as a slot and budget free up, so batches overlap on the
 // device.  Completion is observed through one event per slot; the latency of
 // a request runs from its submission to the host seeing its batch complete.
+// Batches run in three phases (tile totals, scan, expand): their expand
+// passes take tiles from the split queues, which the single pass cannot (its
+// look-back needs one in-order queue); on the served mix of 64 KB - 32 MB
+// chunks this sustained 0.94 of the single-column rate under saturation,
+// against 0.83 for the single pass, at the same latency under moderate load.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -28,6 +33,8 @@
 #include "fd_internal.h"
 
 namespace {
+
+constexpr fd_tuning kServeTuning = {1, 0, 0, 0};   // three phases, automatic tiles and grid
 
 using Clock = std::chrono::steady_clock;
 
@@ -134,7 +141,7 @@ bool fd_server::launch(Slot& s, std::unique_lock<std::mutex>& lk) {
     lk.unlock();
     std::vector<fd_column> cols(take.size());
     for (size_t i = 0; i < take.size(); i++) cols[i] = take[i].col;
-    const fd_tuning tu = {0, 0, 0, 0};
+    const fd_tuning tu = kServeTuning;
     size_t need = 0;
     fd_status rc = fd_batch_workspace_size(cols.data(), (int32_t)cols.size(), &tu, &need);
     if (rc == FD_OK && need > s.ws_bytes) {
@@ -267,7 +274,7 @@ fd_status fd_server_submit(fd_server* s, const fd_column* req, uint64_t* ticket)
     if (!s || !req || !ticket) return FD_EINVAL;
     // the host-visible checks of batch_decode, now, so that a bad request fails its submission
     size_t ws = 0;
-    const fd_tuning tu = {0, 0, 0, 0};
+    const fd_tuning tu = kServeTuning;
     if (fd_batch_workspace_size(req, 1, &tu, &ws) != FD_OK) return FD_EINVAL;
     try {
         std::lock_guard<std::mutex> lk(s->mu);
