@@ -1229,25 +1229,38 @@ struct ColumnBatch {
 // The tile queues of a launch (thread 0 of a workgroup uses them): tiles
 // [0, n_all) split into nq contiguous ranges, range q taken in order through
 // its counter.  take() issues the atomic on the current range; resolve()
-// turns its result into a tile id, moving on to the next ranges while the
-// current one is used up, and returns n_all once every range is.  Each tile
-// is taken exactly once, and a workgroup stops only after it has found every
-// range used up.
+// turns its result into a tile id.  When the current range is used up it
+// reads all the counters at once (one round trip, not one atomic per range)
+// and moves on to the first later range that still had tiles, or returns
+// n_all when none had: a counter only grows, so a range seen used up stays
+// so, and a workgroup stops only after it has seen every range used up.
+// Each tile is taken exactly once (by the atomic that returned its index).
 // --------------------------------------------------------------------------
 struct TileQueue {
     unsigned* base;       // counter block
     int64_t n_all;
-    int nq, q, left;
+    int nq, q;
     __device__ TileQueue(unsigned* b, int64_t n, int queues)
-        : base(b), n_all(n), nq(queues), q((int)(blockIdx.x % (unsigned)queues)), left(queues) {}
+        : base(b), n_all(n), nq(queues), q((int)(blockIdx.x % (unsigned)queues)) {}
     __device__ int64_t lo(int k) const { return (int64_t)k * n_all / nq; }
-    __device__ unsigned take() const { return atomicAdd(&base[kQueueStride * (q + 1)], 1u); }
+    __device__ unsigned* ctr(int k) const { return &base[kQueueStride * (k + 1)]; }
+    __device__ unsigned take() const { return atomicAdd(ctr(q), 1u); }
     __device__ int64_t resolve(unsigned raw) {
         for (;;) {
             const int64_t t = lo(q) + (int64_t)raw;
             if (t < lo(q + 1)) return t;
-            if (--left == 0) return n_all;
-            q = (q + 1 == nq) ? 0 : q + 1;
+            if (nq == 1) return n_all;
+            unsigned c[kQueues];
+#pragma unroll
+            for (int k = 0; k < kQueues; k++)
+                c[k] = k < nq ? __hip_atomic_load(ctr(k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            int next = -1;
+            for (int i = 1; i < nq && next < 0; i++) {
+                const int k = (q + i) % nq;
+                if (lo(k) + (int64_t)c[k] < lo(k + 1)) next = k;
+            }
+            if (next < 0) return n_all;
+            q = next;
             raw = take();
         }
     }
