@@ -205,7 +205,10 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                     multiple of 16 (FSST-8) or 8 (OnPair) up to that.
  *                     n_tiles = ceil(n_codes / tile_codes), at least 1.
  *   grid              workgroups to launch; automatic = all that can be
- *                     resident on the device (they pull tiles from a counter).
+ *                     resident on the device.  Workgroups pull tiles from
+ *                     counters: mode 1 splits the tiles into eight contiguous
+ *                     ranges with a counter each, mode 0 takes them in order
+ *                     from one.
  * The decoded result does not depend on the tuning. */
 typedef struct fd_tuning {
     int32_t mode;
@@ -357,8 +360,9 @@ fd_status fd_batch_workspace_size(const fd_column *cols, int32_t n_cols, const f
 /* Decode n_cols columns of any codecs and offset widths in one stream
  * submission: columns of one codec and offset width form a group, each group
  * runs as one persistent kernel in which every workgroup takes tiles of the
- * group's columns, in column order, from one counter (each column keeps its
- * own error word), and a last kernel collects the statuses.  The tile cursors
+ * group's columns (numbered in column order) from the group's counters, as
+ * for fd_tuning's modes (each column keeps its own error word), and a last
+ * kernel collects the statuses.  The tile cursors
  * come from a look-back per column (mode 0) or from three phases per group
  * (mode 1: the group's tile totals, one scan over them, then the expand pass).
  * The byte semantics per column are those of fd_decode; out_bytes and
