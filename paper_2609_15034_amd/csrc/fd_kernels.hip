@@ -2253,12 +2253,21 @@ __global__ void __launch_bounds__(256) k_take_offsets(const int64_t* rows, int64
 
 // Pass 4: copy the selected codes, widening 12-bit codes to 16 bits.  A
 // workgroup copies the codes of rows_per_wg consecutive rows (chosen so that
-// it holds a few thousand codes at the column's mean codes per string); their
-// offsets are staged in LDS and each thread finds the row holding its group of
-// 4 consecutive codes by a binary search there.
+// it holds about 16,384 codes at the column's mean codes per string: a few
+// chunks per thread, whose loads can be in flight together); their offsets are
+// staged in LDS.  The output is cut into 16-byte chunks at its
+// own alignment (the destination is 256-byte aligned): each thread takes a
+// chunk, finds the row holding the chunk's first code by a binary search in
+// LDS, gathers the chunk's codes row by row into registers and writes them
+// with one 16-byte store.  The chunks at the two ends of a workgroup's range
+// (shared with the neighbouring workgroups) are written code by code, only
+// for the workgroup's own codes.
 template <int CIN, typename IDX>
-__global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_wg, const uint8_t* codes,
-                                                   const IDX* new_off, const int64_t* src, uint8_t* dst) {
+__global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_wg, const uint8_t* __restrict__ codes,
+                                                   const IDX* __restrict__ new_off, const int64_t* __restrict__ src,
+                                                   uint8_t* __restrict__ dst) {
+    constexpr int EO = CIN == kFsst8 ? 1 : 2;      // output bytes per code
+    constexpr int CH = 16 / EO;                    // codes per 16-byte output chunk
     __shared__ int64_t s_off[kTakeRows + 1];
     __shared__ int64_t s_src[kTakeRows];
     const unsigned tid = ltid();
@@ -2269,29 +2278,56 @@ __global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_
         if (j < nr) s_src[j] = src[base + j];
     }
     __syncthreads();
-    const int64_t o0 = s_off[0], lim = s_off[nr] - o0;
-    for (int64_t q = (int64_t)tid * 4; q < lim; q += 256 * 4) {
-        int lo = 0, hi = nr - 1;                  // the last row starting at or before q
+    const int64_t o0 = s_off[0], o1 = s_off[nr];  // this workgroup's codes [o0, o1) of the output
+    const int64_t c_end = (o1 + CH - 1) / CH;
+#pragma unroll 4
+    for (int64_t c = o0 / CH + (int64_t)tid; c < c_end; c += 256) {
+        const int64_t e0 = c * CH;
+        const int64_t a = max(e0, o0), b = min(e0 + CH, o1);
+        int lo = 0, hi = nr - 1;                  // the last row starting at or before a
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] - o0 <= q) lo = mid;
+            if (s_off[mid] <= a) lo = mid;
             else hi = mid - 1;
         }
+        // the chunk's codes row by row: slots [ka, kb) of the chunk, the row's
+        // codes from slot ks on (a row change inside a chunk is the rare case)
+        const int ka = (int)(a - e0), kb = (int)(b - e0);
         int j = lo;
-        for (int e = 0; e < 4; e++) {
-            const int64_t pq = q + e;
-            if (pq >= lim) break;
-            while (s_off[j + 1] - o0 <= pq) j++;  // past rows that end before pq (empty ones included)
-            const int64_t sc = s_src[j] + (pq - (s_off[j] - o0));
-            const int64_t o = o0 + pq;
+        int kn = (int)min(s_off[j + 1] - e0, (int64_t)CH);   // first slot past row j
+        int64_t sb = s_src[j] - (s_off[j] - e0);             // source index of slot 0 in row j
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if (k < ka || k >= kb) continue;
+            if (k >= kn) {                        // past rows that end before slot k (empty ones included)
+                do { j++; } while (s_off[j + 1] <= e0 + k);
+                kn = (int)min(s_off[j + 1] - e0, (int64_t)CH);
+                sb = s_src[j] - (s_off[j] - e0);
+            }
+            const int64_t sc = sb + k;
+            uint32_t x;
             if constexpr (CIN == kFsst8) {
-                dst[o] = codes[sc];
+                x = codes[sc];
             } else if constexpr (CIN == kOnpair16) {
-                ((uint16_t*)dst)[o] = ((const uint16_t*)codes)[sc];
+                x = ((const uint16_t*)codes)[sc];
             } else {                              // code sc: bits [12 sc, 12 sc + 12), least significant first
                 const int64_t bo = sc + (sc >> 1);
-                const uint32_t v = (uint32_t)codes[bo] | ((uint32_t)codes[bo + 1] << 8);
-                ((uint16_t*)dst)[o] = (uint16_t)((v >> ((sc & 1) * 4)) & 0xfffu);
+                const uint32_t w = (uint32_t)codes[bo] | ((uint32_t)codes[bo + 1] << 8);
+                x = (w >> ((sc & 1) * 4)) & 0xfffu;
+            }
+            v[(k * EO) >> 2] |= x << (8 * ((k * EO) & 3));
+        }
+        if (a == e0 && b == e0 + CH) {
+            *(u32x4*)(dst + e0 * EO) = u32x4{v[0], v[1], v[2], v[3]};
+        } else {
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                const int64_t e = e0 + k;
+                if (e < a || e >= b) continue;
+                const uint32_t x = (v[(k * EO) >> 2] >> (8 * ((k * EO) & 3))) & (EO == 1 ? 0xffu : 0xffffu);
+                if constexpr (EO == 1) dst[e] = (uint8_t)x;
+                else ((uint16_t*)dst)[e] = (uint16_t)x;
             }
         }
     }
