@@ -565,10 +565,13 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     // compaction: the selected strings' codes, whole, one after another
     uint8_t* ccodes = ws + tp.off_codes;
     void* coff = ws + tp.off_noff;
-    // copy workgroups of about 16,384 codes at the column's mean codes per string
+    // copy workgroups of about 16,384 FSST-8 codes or 4,096 OnPair codes at the
+    // column's mean codes per string (measured: fewer, larger workgroups pay
+    // on the long FSST-8 strings and cost on the short OnPair ones)
     const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+    const double per_wg = dict->codec == FD_FSST8 ? 16384.0 : 4096.0;
     int rows_per_wg = 16;
-    while (rows_per_wg < 1024 && (double)(2 * rows_per_wg) * mean <= 16384.0) rows_per_wg *= 2;
+    while (rows_per_wg < 1024 && (double)(2 * rows_per_wg) * mean <= per_wg) rows_per_wg *= 2;
     if (timed(FD_PROF_PREPARE, st, [&] {
             return launch_take_compact((int)dict->codec, index_bits, rows, n_rows, code_offsets, n_strings, n_codes,
                                        (const uint8_t*)codes, (unsigned long long*)(ws + tp.off_bsum), max_codes,

@@ -2253,13 +2253,13 @@ __global__ void __launch_bounds__(256) k_take_offsets(const int64_t* rows, int64
 
 // Pass 4: copy the selected codes, widening 12-bit codes to 16 bits.  A
 // workgroup copies the codes of rows_per_wg consecutive rows (chosen so that
-// it holds about 16,384 codes at the column's mean codes per string: a few
+// it holds a few thousand codes at the column's mean codes per string: a few
 // chunks per thread, whose loads can be in flight together); their offsets are
-// staged in LDS.  The output is cut into 16-byte chunks at its
-// own alignment (the destination is 256-byte aligned): each thread takes a
-// chunk, finds the row holding the chunk's first code by a binary search in
-// LDS, gathers the chunk's codes row by row into registers and writes them
-// with one 16-byte store.  The chunks at the two ends of a workgroup's range
+// staged in LDS.  The output is cut into chunks of 16 bytes (FSST-8) or 8
+// bytes (OnPair) at its own alignment (the destination is 256-byte aligned):
+// each thread takes a chunk, finds the row holding the chunk's first code by a
+// binary search in LDS, gathers the chunk's codes row by row into registers
+// and writes them with one store.  The chunks at the two ends of a workgroup's range
 // (shared with the neighbouring workgroups) are written code by code, only
 // for the workgroup's own codes.
 template <int CIN, typename IDX>
@@ -2267,7 +2267,8 @@ __global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_
                                                    const IDX* __restrict__ new_off, const int64_t* __restrict__ src,
                                                    uint8_t* __restrict__ dst) {
     constexpr int EO = CIN == kFsst8 ? 1 : 2;      // output bytes per code
-    constexpr int CH = 16 / EO;                    // codes per 16-byte output chunk
+    constexpr int CB = CIN == kFsst8 ? 16 : 8;     // bytes per output chunk (short OnPair rows: more threads)
+    constexpr int CH = CB / EO;                    // codes per output chunk
     __shared__ int64_t s_off[kTakeRows + 1];
     __shared__ int64_t s_src[kTakeRows];
     const unsigned tid = ltid();
@@ -2319,7 +2320,8 @@ __global__ void __launch_bounds__(256) k_take_copy(int64_t n_rows, int rows_per_
             v[(k * EO) >> 2] |= x << (8 * ((k * EO) & 3));
         }
         if (a == e0 && b == e0 + CH) {
-            *(u32x4*)(dst + e0 * EO) = u32x4{v[0], v[1], v[2], v[3]};
+            if constexpr (CB == 16) *(u32x4*)(dst + e0 * EO) = u32x4{v[0], v[1], v[2], v[3]};
+            else *(uint2*)(dst + e0 * EO) = make_uint2(v[0], v[1]);
         } else {
 #pragma unroll
             for (int k = 0; k < CH; k++) {
