@@ -185,7 +185,8 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
 /* Tuning                                                                     */
 /* ------------------------------------------------------------------------- */
 
-/* Launch parameters of a decode.  A zero field means "automatic".
+/* Launch parameters of a decode.  A zero tile_codes or grid means
+ * "automatic"; a NULL tuning makes every choice automatic.
  *   mode              0: one pass; each tile finds its output position by a
  *                        decoupled look-back over the totals published by
  *                        earlier tiles;
@@ -193,6 +194,9 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                        expansion), reading the code stream twice (the
  *                        "sidecar regenerated at decode time" variant the
  *                        paper measures in its design overview).
+ *                     With a NULL tuning: mode 1 when the column has at
+ *                     least twice as many tiles as workgroups resident on
+ *                     the device, else mode 0 (fewer launches).
  *   tile_codes        codes per tile.  Tiles are fixed ranges of code
  *                     positions (the paper's fixed-size batches of codes,
  *                     design overview): tile t holds the codes at positions
@@ -318,8 +322,9 @@ fd_status fd_decode_sidecar(const fd_dict *dict, const void *codes, int64_t n_co
  *               which sizes the workspace (n_codes when no row repeats);
  *               a selection with more codes reports FD_ENOMEM.  index_bits 32
  *               needs max_codes <= INT32_MAX.
- *   tuning      as fd_decode_ex (mode must be 0); the automatic tile size
- *               assumes the rows have the column's mean codes per string.
+ *   tuning      as fd_decode_ex (mode 0 or 1); the automatic tile size and,
+ *               with a NULL tuning, the automatic mode assume the rows have
+ *               the column's mean codes per string.
  * Statuses: a row outside [0, n_strings) or a selected string whose code
  * offsets are not ordered inside [0, n_codes] is FD_EOFFSETS; then FD_ENOMEM;
  * then the decode's statuses, the data errors ranked by position in the

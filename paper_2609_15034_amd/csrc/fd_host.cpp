@@ -162,7 +162,7 @@ bool take_plan_for(fd_codec codec, int64_t n_codes, int64_t n_strings, int64_t n
     if (n_codes < 0 || n_strings < 0 || n_rows < 0 || max_codes < 0) return false;
     if (n_rows > (int64_t)1 << 40 || max_codes > (int64_t)1 << 40) return false;
     if (codec != FD_FSST8 && codec != FD_ONPAIR16 && codec != FD_ONPAIR12) return false;
-    if (tu && tu->mode != 0) return false;
+    if (tu && tu->mode != 0 && tu->mode != 1) return false;
     tp->codec2 = codec == FD_ONPAIR12 ? FD_ONPAIR16 : codec;
     // tiles over the compacted buffer of max_codes codes (the tiles past the
     // selection's codes are skipped on the device); the coarse index stride
@@ -241,6 +241,13 @@ fd_status run_decode(const Args& a) {
     // a prepared dictionary needs no room for the one-shot repack
     if (a.ws_bytes < (a.dict ? pl.off_dict : pl.bytes)) return FD_EINVAL;
     if (a.sidecar_op && a.sidecar_n != pl.n_tiles + 1) return FD_EINVAL;   // another tiling's sidecar
+    // without a tuning: the three phases when the column's tiles fill the
+    // resident workgroups twice over (their expand pass takes tiles from the
+    // split queues), the single pass (fewer launches) below that
+    int mode = mode_sel;
+    if (!a.tuning && !a.sidecar_op &&
+        pl.n_tiles >= 2 * (int64_t)resident_grid((int)a.codec, a.index_bits, kModeExpand))
+        mode = 1;
 
     uint8_t* ws = (uint8_t*)a.ws;
     DecodeParams p;
@@ -329,7 +336,7 @@ fd_status run_decode(const Args& a) {
         if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec, a.index_bits, kModeExpand, p, g2, st); }) !=
             hipSuccess)
             return hip_fail();
-    } else if (mode_sel == 0) {
+    } else if (mode == 0) {
         int grid = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeLookback);
         if ((int64_t)grid > pl.n_tiles) grid = (int)pl.n_tiles;
         if (timed(FD_PROF_DECODE, st,
@@ -610,15 +617,34 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
         p.fsst_tab = dict->fsst_tab;
         p.fsst_len = dict->fsst_len;
     } else {
+        p.n_sym = dict->n;                 // codes at or past it are not tokens
         p.tok16 = dict->tok16;
         p.tok_len = dict->tok_len;
     }
     const int codec2 = (int)tp.codec2;
     if (timed(FD_PROF_COARSE, st, [&] { return launch_coarse_one(index_bits, p, st); }) != hipSuccess) return hip_fail();
-    int grid = (tuning && tuning->grid) ? tuning->grid : resident_grid(codec2, index_bits, kModeLookback);
+    // the mode: as asked, else the three phases when the selection is expected
+    // (at the column's mean codes per string) to fill the resident workgroups
+    // twice over with tiles, the single pass (fewer launches) below that
+    int mode = tuning ? tuning->mode : -1;
+    if (mode < 0) {
+        const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
+        const double tiles = mean * (double)n_rows / (double)tp.dec.T;
+        mode = tiles >= 2.0 * (double)resident_grid(codec2, index_bits, kModeExpand) ? 1 : 0;
+    }
+    if (mode == 1) {
+        if (timed(FD_PROF_TOTALS, st, [&] { return launch_tile_totals(codec2, index_bits, p, dev_cus(), st); }) !=
+            hipSuccess)
+            return hip_fail();
+        if (timed(FD_PROF_SCAN, st, [&] {
+                return launch_scan_multi(p.tagg, tp.dec.n_tiles + 1, (unsigned long long*)(ws + tp.dec.off_scan), st);
+            }) != hipSuccess)
+            return hip_fail();
+    }
+    const int kmode = mode == 1 ? kModeExpand : kModeLookback;
+    int grid = (tuning && tuning->grid) ? tuning->grid : resident_grid(codec2, index_bits, kmode);
     if ((int64_t)grid > tp.dec.n_tiles) grid = (int)tp.dec.n_tiles;
-    if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec2, index_bits, kModeLookback, p, grid, st); }) !=
-        hipSuccess)
+    if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec2, index_bits, kmode, p, grid, st); }) != hipSuccess)
         return hip_fail();
     if (flags & FD_ASYNC) return FD_OK;
     if (hipStreamSynchronize(st) != hipSuccess) return hip_fail();

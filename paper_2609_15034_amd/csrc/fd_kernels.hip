@@ -1274,7 +1274,22 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
     using C = Cfg<CODEC>;
     constexpr int P = C::P;
     const unsigned tid = ltid(), wv = tid >> 6;
-    const int64_t n_all = src.n_tiles();
+    int64_t n_all = src.n_tiles();
+    if constexpr (!SRC::kBatch) {
+        // a single column's tiles past the one holding the end of its decode
+        // range have no work (a slice of the code buffer; a selection decoded
+        // in a buffer sized for more codes): the queues cover only the tiles
+        // up to it, so that no workgroup starts on a range of empty tiles
+        const DecodeParams& p0 = src.params(0);
+        int64_t x0 = 0, x1 = 0;
+        if (tid == 0) {
+            column_range<IDX>(p0, x0, x1);
+            s.hdr[0] = x0;
+            s.hdr[1] = x1;
+        }
+        __syncthreads();
+        n_all = min(n_all, last_tile(p0, uniform64(s.hdr[0]), uniform64(s.hdr[1])) + 1);
+    }
     // Tiles come from counters (dynamic shares measured faster than fixed
     // ones: they spread the workgroups of a CU over different steps of their
     // tiles).  The look-back needs them taken in increasing order: one queue.

@@ -144,8 +144,9 @@ def test_sidecar_host_checks(fdlib):
 
 
 def test_take_host_checks(fdlib):
-    """fd_take_workspace_size grows with the code budget and rejects
-    three-phase tuning; fd_decode_take rejects a missing dictionary."""
+    """fd_take_workspace_size grows with the code budget and plans one
+    workspace for both modes (an unknown mode is rejected); fd_decode_take
+    rejects a missing dictionary."""
     fd = fdlib
     a = fd.take_workspace_size("fsst8", 10 ** 6, 10 ** 4, 100, 0)
     b = fd.take_workspace_size("fsst8", 10 ** 6, 10 ** 4, 100, 10 ** 5)
@@ -155,8 +156,11 @@ def test_take_host_checks(fdlib):
     for bad in ((10 ** 6, 10 ** 4, -1, 0), (10 ** 6, 10 ** 4, 1, -1)):
         with pytest.raises(fd.DecodeError):
             fd.take_workspace_size("fsst8", *bad)
+    # both modes plan the same workspace; there is no third mode
+    assert fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0}) == \
+        fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0})
     with pytest.raises(fd.DecodeError):
-        fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0})
+        fd.take_workspace_size("fsst8", 100, 10, 5, 100, {"mode": 2, "tile_codes": 0, "grid": 0, "reserved": 0})
     L = fd.lib()
     P = ctypes.c_void_p
     fake, ws = P(1 << 20), P(1 << 21)

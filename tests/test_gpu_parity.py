@@ -396,3 +396,16 @@ def test_onpair_multi_window_tiles(mode):
     code_off = np.concatenate([[0], cuts, [n]]).astype(np.int64)
     exp = assert_parity("onpair16", codes, code_off, db, dl, tuning=tu(mode))
     assert exp.status == 0
+
+
+def test_automatic_mode_both_sides(datagen_mod):
+    """Without a tuning the decode picks the three phases for a column with at
+    least twice as many tiles as resident workgroups (a 32 MiB log column has
+    about 2,600 tiles of 8,176 codes) and the single pass for a small one; both
+    match the oracle."""
+    big = datagen_mod.fsst_logs(seed=41, target_bytes=32 << 20)
+    assert len(big.codes) // 8176 >= 2 * 1024
+    exp = assert_parity("fsst8", big.codes, big.code_off, big.dict_bytes, big.dict_lens)
+    assert np.array_equal(exp.out_bytes, big.text)
+    small = datagen_mod.fsst_small(seed=42)
+    assert_parity("fsst8", small.codes, small.code_off, small.dict_bytes, small.dict_lens)

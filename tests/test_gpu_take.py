@@ -120,7 +120,10 @@ def test_take(cols, name, order):
 
 @pytest.mark.parametrize("tuning", [{"mode": 0, "tile_codes": 16, "grid": 0, "reserved": 0},
                                     {"mode": 0, "tile_codes": 400, "grid": 3, "reserved": 0},
-                                    {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0}])
+                                    {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 16, "grid": 0, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 400, "grid": 3, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0}])
 @pytest.mark.parametrize("name", ["fsst_logs", "onpair12_urls"])
 def test_take_tuning(cols, name, tuning):
     c = cols[name]
@@ -135,24 +138,38 @@ def test_take_unaligned_12bit(cols, misalign):
     assert assert_take(c, rows, misalign=misalign).status == 0
 
 
-def test_take_errors(cols):
+@pytest.mark.parametrize("name", ["fsst_logs", "onpair_urls", "onpair12_urls"])
+@pytest.mark.parametrize("order", ["sorted10", "random10", "repeats", "all", "ends", "one", "none"])
+def test_take_three_phases(cols, name, order):
+    """The selection decoded by the three phases (their expand pass takes
+    tiles from the split queues), at the default and at small tiles."""
+    c = cols[name]
+    rows = make_rows(c.n_strings, order, np.random.default_rng(len(order) + 3 * len(name)))
+    for tc in (0, 64):
+        tuning = {"mode": 1, "tile_codes": tc, "grid": 0, "reserved": 0}
+        assert assert_take(c, rows, tuning=tuning).status == 0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_take_errors(cols, mode):
     c = cols["fsst_logs"]
     n = c.n_strings
+    tu = {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
     rng = np.random.default_rng(4)
     rows = make_rows(n, "random10", rng)
     # rows outside the column
     for bad in (n, -1, 1 << 40):
         r2 = rows.copy()
         r2[len(r2) // 2] = bad
-        assert assert_take(c, r2, max_codes=n_codes_of(c)).status == 3 + 4     # EOFFSETS
+        assert assert_take(c, r2, max_codes=n_codes_of(c), tuning=tu).status == 3 + 4     # EOFFSETS
     # a code budget one short, and exactly enough
     need = selected_codes(c, rows)
-    assert assert_take(c, rows, max_codes=need - 1).status == 9                 # ENOMEM
-    assert assert_take(c, rows, max_codes=need).status == 0
+    assert assert_take(c, rows, max_codes=need - 1, tuning=tu).status == 9                 # ENOMEM
+    assert assert_take(c, rows, max_codes=need, tuning=tu).status == 0
     # capacity, async
-    total = int(assert_take(c, rows).out_off[-1])
-    assert assert_take(c, rows, cap=total - 1).status == 4
-    assert assert_take(c, rows, async_=True).status == 0
+    total = int(assert_take(c, rows, tuning=tu).out_off[-1])
+    assert assert_take(c, rows, cap=total - 1, tuning=tu).status == 4
+    assert assert_take(c, rows, async_=True, tuning=tu).status == 0
 
 
 def test_take_errors_in_strings(datagen_mod):
@@ -166,5 +183,16 @@ def test_take_errors_in_strings(datagen_mod):
     c2 = type(c)(**{**c.__dict__, "codes": codes})
     rows_with = np.array([3, bad_row, 7]) if bad_row not in (3, 7) else np.array([bad_row])
     rows_without = np.array([r for r in range(0, 1000, 7) if r != bad_row])
-    assert assert_take(c2, rows_with).status == 2
-    assert assert_take(c2, rows_without).status == 0
+    for mode in (0, 1):
+        tu = {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
+        assert assert_take(c2, rows_with, tuning=tu).status == 2
+        assert assert_take(c2, rows_without, tuning=tu).status == 0
+
+
+def test_take_automatic_mode_large_selection(datagen_mod):
+    """Without a tuning a selection expected to span at least twice as many
+    tiles as resident workgroups runs the three phases: every row of a 32 MiB
+    log column, in order and reversed."""
+    c = datagen_mod.fsst_logs(seed=43, target_bytes=32 << 20)
+    for rows in (np.arange(c.n_strings), np.arange(c.n_strings)[::-1].copy()):
+        assert assert_take(c, rows).status == 0
