@@ -263,8 +263,9 @@ def sidecar_rates(workload: str, steps: int = 20, seed: int | None = None) -> di
                                                           async_=True), steps, 2)
     ok = int(st.item()) == fd.OK and torch.equal(out, torch.from_numpy(col.text).to(dev)) and \
         torch.equal(out_off.to(torch.int64), torch.from_numpy(col.text_off).to(dev))
-    t_lb, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True),
-                           steps, 2)
+    lb = {"mode": 0, "tile_codes": 0, "grid": 0, "reserved": 0}      # the single pass (look-back), explicitly
+    t_lb, _ = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True,
+                                                  tuning=lb), steps, 2)
     D = col.decoded_bytes
     return {"sidecar_GBps": round(D / t_sc / 1e9, 2), "lookback_GBps": round(D / t_lb / 1e9, 2),
             "regeneration_cost": round(t_lb / t_sc - 1.0, 3), "sidecar_bytes": int(sc.numel() * 8),
