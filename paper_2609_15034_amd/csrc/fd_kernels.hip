@@ -1177,10 +1177,18 @@ __device__ __forceinline__ uint64_t lookback_finish(const DecodeParams& p, int64
     return excl;
 }
 
-// Waves per SIMD the decode kernels are compiled for: four FSST-8 workgroups
-// per CU (128 VGPRs); the OnPair kernels run three (their 32 KiB staging
-// window leaves room in the LDS for three workgroups).
-template <int CODEC> constexpr int kMinWaves = CODEC == kFsst8 ? 4 : 3;
+// The next tile's codes are loaded into registers during the current tile's
+// drain, except in the FSST-8 passes whose positions are known (expand,
+// sidecar): there the eight registers would cost a fifth workgroup per CU,
+// which measured 3-4% faster than the prefetch.  The FSST-8 single pass keeps
+// the prefetch (without it, at five workgroups, it spilled and ran 9% slower).
+template <int CODEC, int MODE> constexpr bool kPrefetchCodes = !(CODEC == kFsst8 && MODE != kModeLookback);
+// Waves per SIMD the decode kernels are compiled for: FSST-8 five workgroups
+// per CU without the code prefetch (at most 96 VGPRs; their LDS, 31.5 KiB
+// each, fits five), four with it; the OnPair kernels three (their 32 KiB
+// staging window leaves room in the LDS for three workgroups).
+template <int CODEC, int MODE>
+constexpr int kMinWaves = CODEC == kFsst8 ? (kPrefetchCodes<CODEC, MODE> ? 4 : 5) : 3;
 
 // Whether the look-back sums the previous block's tiles (measured: FSST-8
 // gains, OnPair-16, whose tiles publish later and wait mostly inside their
@@ -1390,7 +1398,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
             cur1 = pf ? pf_c1 : (int64_t)p.tagg[t + 1];
         }
         Lane<CODEC> L;
-        if (pf) {
+        if (kPrefetchCodes<CODEC, MODE> && pf) {
 #pragma unroll
             for (int c = 0; c < P; c++)
 #pragma unroll
@@ -1489,7 +1497,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
                         pf_c1 = (int64_t)p.tagg[tn + 1];
                     }
                     const Geom gn = make_geom<CODEC>(p, tn, ca, cb);
-                    codes_load<CODEC>(p, gn, 0, pf_w);
+                    if constexpr (kPrefetchCodes<CODEC, MODE>) codes_load<CODEC>(p, gn, 0, pf_w);
                     if constexpr (CODEC == kFsst8) {
                         if (wv == 0) pf_byte = fsst_window_byte(p.codes, min(max(ca, (int64_t)0), p.n_codes), gn.a);
                     }
@@ -1527,7 +1535,7 @@ __device__ __forceinline__ void decode_tiles(SmemT<CODEC>& s, const SRC& src) {
 // offset width (the statuses of a batch are collected by k_batch_status)
 // --------------------------------------------------------------------------
 template <int CODEC, typename IDX, int MODE>
-__global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode(DecodeParams p) {
+__global__ void __launch_bounds__(kWG, (kMinWaves<CODEC, MODE>)) k_decode(DecodeParams p) {
     __shared__ SmemT<CODEC> s;
     decode_tiles<CODEC, IDX, MODE>(s, OneColumn{p});
 
@@ -1548,7 +1556,7 @@ __global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode(DecodeParams p
 }
 
 template <int CODEC, typename IDX, int MODE>
-__global__ void __launch_bounds__(kWG, kMinWaves<CODEC>) k_decode_batch(const DecodeParams* __restrict__ cols,
+__global__ void __launch_bounds__(kWG, (kMinWaves<CODEC, MODE>)) k_decode_batch(const DecodeParams* __restrict__ cols,
                                                       const int64_t* __restrict__ first_tile, int32_t n_cols,
                                                       int64_t total, unsigned* ctr) {
     __shared__ SmemT<CODEC> s;
