@@ -170,6 +170,22 @@ __device__ __forceinline__ uint32_t tile_entry_mask(int64_t f, uint32_t cin) {
     return (f > 0 && f < 32 && cin) ? (1u << (uint32_t)(f - 1)) : 0u;
 }
 
+// 0x80 in each byte of x that is 255, 0 elsewhere
+__device__ __forceinline__ uint32_t ff_bytes(uint32_t x) { return ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u; }
+
+// The 255 mask of 32 codes (bit 4d + b: byte b of dword d is 255) from the
+// ff_bytes of its eight dwords: an 8-bit dot product with the weights
+// 1, 2, 4, 8 (dword 2i) and 16 .. 128 (dword 2i + 1) gathers byte i of the
+// mask, scaled by 128, in one full-rate instruction per dword.
+__device__ __forceinline__ uint32_t ff_mask32(const uint32_t m[8]) {
+    uint32_t d[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        d[i] = __builtin_amdgcn_udot4(m[2 * i + 1], 0x80402010u,
+                                      __builtin_amdgcn_udot4(m[2 * i], 0x08040201u, 0u, false), false);
+    return (d[0] >> 7) | (d[1] << 1) | (d[2] << 9) | (d[3] << 17);
+}
+
 // expand 4 bits into bit 7 of each byte of a dword
 // 4 bits -> bytes 0x01 / 0x00 (a 24-bit multiply places bit k at bit 8k)
 __device__ __forceinline__ uint32_t nib_to_bytes(uint32_t nib) { return ((nib & 0xfu) * 0x00204081u) & 0x01010101u; }
@@ -1783,54 +1799,80 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
 #pragma unroll
                 for (int q = 0; q < 4; q++) w[c][q] = wn[c][q];
             if (it + 1 < steps) codes_load_at<CODEC>(p, g, k0 + CPI, wn);
-            const int64_t q0 = g.pos0 + k0 * CPC;
-            const int64_t lo = min(max(g.a - q0, (int64_t)0), (int64_t)CPL);
-            const int64_t hi = min(max(g.b - q0, (int64_t)0), (int64_t)CPL);
-            const uint32_t mhi = hi >= 32 ? 0xffffffffu : ((1u << (uint32_t)hi) - 1u);
-            const uint32_t mlo = lo >= 32 ? 0xffffffffu : ((1u << (uint32_t)lo) - 1u);
-            const uint32_t valid = mhi & ~mlo;
+            // the lane's codes inside the tile, bits [lo, hi) of 32 (tile-relative, so 32-bit)
+            const int32_t rel = (int32_t)(k0 * CPC);
+            const int32_t lo = min(max((int32_t)(g.a - g.pos0) - rel, 0), CPL);
+            const int32_t hi = min(max((int32_t)(g.b - g.pos0) - rel, 0), CPL);
+            const uint32_t valid = (uint32_t)(~0ull << lo) & ~(uint32_t)(~0ull << hi);
             uint32_t tot = 0;
             if constexpr (CODEC == kFsst8) {
-                // bit j: code j is 255 (the top bits of 0xFF bytes gathered by one multiply)
-                uint32_t F = 0;
+                uint32_t m[P * 4];                // 0x80 in each byte that is 255
 #pragma unroll
                 for (int c = 0; c < P; c++)
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const uint32_t x = w[c][q];
-                        const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
-                        F |= (((m >> 7) * 0x00204081u) >> 21 & 0xfu) << (c * 16 + q * 4);
+                    for (int q = 0; q < 4; q++) m[c * 4 + q] = ff_bytes(w[c][q]);
+                // Common case: every code of the step is inside the tile and no
+                // two 255 are adjacent (text never holds a literal 255), the
+                // parity entering the step included.  Then every 255 is an
+                // escape and a literal is simply the code after a 255: the 255
+                // bytes shifted by one code, across dwords and from the lane below.
+                const int64_t s0 = g.pos0 + it * CPI * CPC;   // the step's first code
+                bool fast = uniform32(s0 >= g.a && s0 + CPI * CPC <= g.b ? 1u : 0u) != 0;
+                uint32_t L[P * 4];                // 0x80 in each byte that is a literal
+                uint64_t E = 0;                   // lanes whose last code is 255
+                if (fast) {
+                    E = __ballot(m[P * 4 - 1] >> 31);
+                    uint32_t prev = (uint32_t)(((E << 1) | carry) >> lane) << 31, adj = 0;
+#pragma unroll
+                    for (int d = 0; d < P * 4; d++) {
+                        L[d] = __builtin_amdgcn_alignbit(m[d], prev, 24);
+                        adj |= m[d] & L[d];       // a 255 after a 255 (or after the carry)
+                        prev = m[d];
                     }
-                F &= valid;
-                if (it == 0) {                    // the parity entering the tile, at its first code
-                    if (lane == 0) F |= tile_entry_mask(g.a - q0, carry);
-                    if (g.a > g.pos0) carry = 0;
+                    fast = __ballot(adj != 0u) == 0;
                 }
-                // the parity entering each lane: the trailing run of the nearest
-                // lower lane that is not all escapes, else the previous step's
-                const bool all_ff = (F == 0xffffffffu);
-                const uint32_t trail = __clz(~F);
-                const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
-                const uint64_t m = M & ((1ull << lane) - 1ull);
-                const uint32_t cin = m ? (uint32_t)((T >> (63 - __clzll(m))) & 1ull) : carry;
-                if (M) carry = (uint32_t)((T >> (63 - __clzll(M))) & 1ull);
-                uint32_t esc, lit;
-                classify_escapes(F, cin, esc, lit);
-                lit &= valid;
-                // literals count 1 each; they and the codes outside the tile are
-                // read as 255, whose length is 0 (as an escape's), so every other
-                // code adds its table length
-                tot = (uint32_t)__builtin_popcount(lit);
-                const uint32_t fix = ~valid | lit;
+                if (fast) {
+                    carry = (uint32_t)(E >> 63);
 #pragma unroll
-                for (int c = 0; c < P; c++)
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const uint32_t nib = (fix >> (c * 16 + q * 4)) & 0xfu;
-                        const uint32_t x = w[c][q] | (((nib * 0x00204081u) & 0x01010101u) * 0xffu);
+                    for (int d = 0; d < P * 4; d++) {
+                        // literals count 1 each and read as 255 (length 0, as escapes)
+                        const uint32_t x = w[d >> 2][d & 3] | L[d] | (L[d] - (L[d] >> 7));
+                        tot += (uint32_t)__builtin_popcount(L[d]);
                         tot += (uint32_t)s_len[x & 0xffu] + (uint32_t)s_len[(x >> 8) & 0xffu] +
                                (uint32_t)s_len[(x >> 16) & 0xffu] + (uint32_t)s_len[x >> 24];
                     }
+                } else {
+                    uint32_t F = ff_mask32(m) & valid;   // bit j: code j is 255
+                    if (it == 0) {                // the parity entering the tile, at its first code
+                        if (lane == 0) F |= tile_entry_mask(g.a - g.pos0, carry);
+                        if (g.a > g.pos0) carry = 0;
+                    }
+                    // the parity entering each lane: the trailing run of the nearest
+                    // lower lane that is not all escapes, else the previous step's
+                    const bool all_ff = (F == 0xffffffffu);
+                    const uint32_t trail = __clz(~F);
+                    const uint64_t M = __ballot(!all_ff), T = __ballot(trail & 1u);
+                    const uint64_t mb = M & ((1ull << lane) - 1ull);
+                    const uint32_t cin = mb ? (uint32_t)((T >> (63 - __clzll(mb))) & 1ull) : carry;
+                    if (M) carry = (uint32_t)((T >> (63 - __clzll(M))) & 1ull);
+                    uint32_t esc, lit;
+                    classify_escapes(F, cin, esc, lit);
+                    lit &= valid;
+                    // literals count 1 each; they and the codes outside the tile are
+                    // read as 255, whose length is 0 (as an escape's), so every other
+                    // code adds its table length
+                    tot = (uint32_t)__builtin_popcount(lit);
+                    const uint32_t fix = ~valid | lit;
+#pragma unroll
+                    for (int c = 0; c < P; c++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            const uint32_t fb = nib_to_bytes(fix >> (c * 16 + q * 4));
+                            const uint32_t x = w[c][q] | ((fb << 8) - fb);
+                            tot += (uint32_t)s_len[x & 0xffu] + (uint32_t)s_len[(x >> 8) & 0xffu] +
+                                   (uint32_t)s_len[(x >> 16) & 0xffu] + (uint32_t)s_len[x >> 24];
+                        }
+                }
             } else {
 #pragma unroll
                 for (int c = 0; c < P; c++)

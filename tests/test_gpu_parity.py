@@ -124,6 +124,59 @@ def test_ff_run_longer_than_a_pass(mode):
         assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode, 16))
 
 
+def _edge_escape_column(seed, n_tiles=5, T=8176):
+    """Isolated escapes on the last code of lanes (32 codes), of the totals'
+    per-wave steps (2048 codes) and of tiles, so that the literal is the
+    first code of the next lane, step or tile; in some steps also a literal
+    255 (255 255), and in one a literal 255 carried into a step from the
+    escape that ends the step before.  Strings never end between an escape
+    and its literal."""
+    rng = np.random.default_rng(seed)
+    n = n_tiles * T + 37
+    codes = rng.integers(0, 3, size=n).astype(np.uint8)
+    esc = set()
+    for t in range(n_tiles):
+        base = t * T
+        for p in range(base + 31, min(base + T, n - 1), 32 * int(rng.integers(1, 5))):
+            esc.add(p)                                   # lane edges
+        for r in range(1, 5):
+            if base + 2048 * r - 1 < n - 1:
+                esc.add(base + 2048 * r - 1)             # step edges
+        if base + T - 1 < n - 1:
+            esc.add(base + T - 1)                        # tile edges
+    for p in sorted(esc):
+        codes[p] = 255
+        codes[p + 1] = int(rng.choice([0, 1, 0x41, 200]))
+    # literal 255s: an escape pair inside step 1 of tile 1, and the literal of
+    # the escape ending step 0 of tile 3 (carried into step 1)
+    for p in (T + 2048 + 100, 3 * T + 2047):
+        codes[p] = 255
+        codes[p + 1] = 255
+        esc.add(p)
+    lit = {p + 1 for p in esc}
+    cuts = [0]
+    pos = 0
+    while True:
+        pos += int(rng.integers(1, 90))
+        if pos >= n:
+            break
+        if pos not in lit:
+            cuts.append(pos)
+    cuts.append(n)
+    return codes, np.array(cuts, np.int64)
+
+
+@pytest.mark.parametrize("mis", [0, 5])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_escapes_on_lane_step_and_tile_edges(mode, mis):
+    """Escapes whose literals open the next lane, totals step or tile, with
+    and without a literal 255 in the same step (mode 1's totals take a
+    shortcut where no two 255 codes are adjacent)."""
+    codes, off = _edge_escape_column(41)
+    db, dl = pack([b"a", b"bc", b"defgh"])
+    assert_parity("fsst8", codes, off, db, dl, tuning=tu(mode), codes_misalign=mis)
+
+
 # --------------------------------------------------------------------------- #
 # slices, alignment, empty and degenerate columns
 # --------------------------------------------------------------------------- #
