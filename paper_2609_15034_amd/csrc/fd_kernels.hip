@@ -190,6 +190,12 @@ __device__ __forceinline__ uint32_t ff_mask32(const uint32_t m[8]) {
 // 4 bits -> bytes 0x01 / 0x00 (a 24-bit multiply places bit k at bit 8k)
 __device__ __forceinline__ uint32_t nib_to_bytes(uint32_t nib) { return ((nib & 0xfu) * 0x00204081u) & 0x01010101u; }
 __device__ __forceinline__ uint32_t bits_to_byte_msb(uint32_t nib) { return nib_to_bytes(nib) << 7; }
+// 4 bits -> bytes 0xFF / 0x00 with a byte permute (selector byte 12 reads as
+// 0x00, 13 as 0xFF); written as (b << 8) - b the compiler folds it into a
+// quarter-rate 32-bit multiply by 255
+__device__ __forceinline__ uint32_t nib_to_ff(uint32_t nib) {
+    return __builtin_amdgcn_perm(0u, 0u, nib_to_bytes(nib) | 0x0c0c0c0cu);
+}
 
 // --------------------------------------------------------------------------
 // configuration
@@ -535,8 +541,7 @@ __device__ __forceinline__ uint32_t fsst_chunk_lengths(S& s, const uint32_t (&w)
         const uint32_t vn = (valid >> (q * 4)) & 0xfu;
         const uint32_t ln = (lit >> (q * 4)) & vn & 0xfu;
         // literals and codes outside the tile read as 255 (length 0 in the table)
-        const uint32_t fb = nib_to_bytes((~vn & 0xfu) | ln);
-        const uint32_t x = w[q] | ((fb << 8) - fb);
+        const uint32_t x = w[q] | nib_to_ff((~vn & 0xfu) | ln);
         lws[q] = (uint32_t)s.fsst_len[x & 0xffu] | ((uint32_t)s.fsst_len[(x >> 8) & 0xffu] << 8) |
                  ((uint32_t)s.fsst_len[(x >> 16) & 0xffu] << 16) | ((uint32_t)s.fsst_len[x >> 24] << 24);
     }
@@ -611,18 +616,12 @@ __device__ __forceinline__ uint32_t lengths(S& s, const DecodeParams& p, const G
     uint32_t pre8w[P][CPC / 4];
     uint16_t cb[P];
     if constexpr (CODEC == kFsst8) {
-        uint32_t F = 0;
+        uint32_t ffb[P * 4];                      // 0x80 in each byte that is 255
 #pragma unroll
         for (int c = 0; c < P; c++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                // bytes equal to 0xFF -> bit 7 of each byte, then packed to 4 bits
-                const uint32_t x = L.w[c][q];
-                const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
-                const uint32_t nib = ((m >> 7) | (m >> 14) | (m >> 21) | (m >> 28)) & 0xfu;
-                F |= nib << (c * 16 + q * 4);
-            }
-        F &= L.valid;
+            for (int q = 0; q < 4; q++) ffb[c * 4 + q] = ff_bytes(L.w[c][q]);
+        uint32_t F = ff_mask32(ffb) & L.valid;    // bit j: code j is 255
         // the parity entering the tile, at its first code
         if (tid == 0) F |= tile_entry_mask(g.a - q0, carry);
         const bool all_ff = (F == 0xffffffffu);
@@ -843,8 +842,7 @@ __device__ __forceinline__ void assemble(S& s, Lane<CODEC>& L, int win, int c, c
         if constexpr (CODEC == kFsst8) {
             // codes outside the tile read as 255, whose table entry is zero (as
             // for an escape and a code that is not a symbol): nothing to mask later
-            const uint32_t fb = nib_to_bytes(~(L.valid >> (C::CPC * c + 4 * i)));
-            w[i] |= (fb << 8) - fb;
+            w[i] |= nib_to_ff(~(L.valid >> (C::CPC * c + 4 * i)));
         }
         asm volatile("" : "+v"(w[i]));
     }
@@ -1867,8 +1865,7 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                     for (int c = 0; c < P; c++)
 #pragma unroll
                         for (int q = 0; q < 4; q++) {
-                            const uint32_t fb = nib_to_bytes(fix >> (c * 16 + q * 4));
-                            const uint32_t x = w[c][q] | ((fb << 8) - fb);
+                            const uint32_t x = w[c][q] | nib_to_ff(fix >> (c * 16 + q * 4));
                             tot += (uint32_t)s_len[x & 0xffu] + (uint32_t)s_len[(x >> 8) & 0xffu] +
                                    (uint32_t)s_len[(x >> 16) & 0xffu] + (uint32_t)s_len[x >> 24];
                         }
@@ -2028,8 +2025,7 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
                 for (int c = 0; c < P; c++)
 #pragma unroll
                     for (int q = 0; q < 4; q++) {
-                        const uint32_t fb = nib_to_bytes(fix >> (c * 16 + q * 4));
-                        const uint32_t x = w[c][q] | ((fb << 8) - fb);
+                        const uint32_t x = w[c][q] | nib_to_ff(fix >> (c * 16 + q * 4));
                         tot += (uint32_t)s_len[x & 0xffu] + (uint32_t)s_len[(x >> 8) & 0xffu] +
                                (uint32_t)s_len[(x >> 16) & 0xffu] + (uint32_t)s_len[x >> 24];
                     }
