@@ -1716,7 +1716,9 @@ __global__ void __launch_bounds__(256) k_onpair_prepare(const uint8_t* bytes, co
 // strings exactly as in the expand phase's scan (in valid data no string ends
 // inside a run of escapes of odd length).
 // OnPair-16 token lengths as nibbles in LDS (32 KiB): 16 lengths (bytes of
-// 0..16) become 8 bytes, code 2k in the low nibble of byte k, 16 stored as 0.
+// 0..16) become 8 bytes, code 2k in the low nibble of byte k, each length l
+// stored as (l - 1) mod 16 (so 1..16 as 0..15; byte-wise, l + 15 <= 31 does
+// not carry).  Dword k then holds codes 8k..8k+7, code 8k + i at bits 4i.
 __device__ __forceinline__ void nib_table_load(uint8_t* s_nib, const uint8_t* tok_len) {
     for (unsigned i = ltid(); i < 65536 / 16; i += blockDim.x) {
         const uint4 a = ((const uint4*)tok_len)[i];
@@ -1724,7 +1726,7 @@ __device__ __forceinline__ void nib_table_load(uint8_t* s_nib, const uint8_t* to
         uint32_t h[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const uint32_t y = x[k] & 0x0f0f0f0fu;
+            const uint32_t y = (x[k] + 0x0f0f0f0fu) & 0x0f0f0f0fu;
             const uint32_t z = y | (y >> 4);
             h[k] = (z & 0xffu) | ((z >> 8) & 0xff00u);
         }
@@ -1732,11 +1734,11 @@ __device__ __forceinline__ void nib_table_load(uint8_t* s_nib, const uint8_t* to
     }
 }
 
-// A code's length from the nibble table: the nibble, 0 read as 16; codes at
-// or past the dictionary's size count 0.
+// A code's length from the nibble table: the nibble plus one; codes at or
+// past the dictionary's size count 0.
 __device__ __forceinline__ uint32_t nib_length(const uint8_t* s_nib, uint32_t cj, int32_t n_tok) {
     const uint32_t nib = ((uint32_t)s_nib[cj >> 1] >> ((cj & 1u) * 4u)) & 0xfu;
-    return (int)cj < n_tok ? ((nib + 15u) & 0xfu) + 1u : 0u;
+    return (int)cj < n_tok ? nib + 1u : 0u;
 }
 
 // --------------------------------------------------------------------------
@@ -1871,19 +1873,45 @@ __global__ void __launch_bounds__(kWG) k_tile_totals(DecodeParams p) {
                         }
                 }
             } else {
+                const int64_t s0 = g.pos0 + it * CPI * CPC;   // the step's first code
+                const bool full = uniform32(s0 >= g.a && s0 + CPI * CPC <= g.b ? 1u : 0u) != 0;
+                if (CODEC == kOnpair16 && full && p.n_sym >= 65536) {
+                    // every code of the step inside the tile and a token: each
+                    // dword of codes (two) reads two dwords of the nibble table
+                    // and extracts the nibbles at 4 (code mod 8), whose offsets
+                    // the bit-field extract takes from the low five bits of its
+                    // operand; the + 1 of every length is added once
+                    const uint32_t* s_nib32 = (const uint32_t*)s_nib;
+                    tot = (uint32_t)(P * CPC);
 #pragma unroll
-                for (int c = 0; c < P; c++)
+                    for (int c = 0; c < P; c++)
 #pragma unroll
-                    for (int j = 0; j < CPC; j++) {
-                        const int b = c * CPC + j;
-                        const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                        uint32_t l;
-                        if constexpr (kPacked12<CODEC>)
-                            l = s_len12[cj & 0xfffu];
-                        else
-                            l = nib_length(s_nib, cj, p.n_sym);
-                        tot += ((valid >> b) & 1u) ? l : 0u;
-                    }
+                        for (int q = 0; q < 4; q++) {
+                            const uint32_t x = w[c][q];
+                            tot += __builtin_amdgcn_ubfe(s_nib32[(x & 0xffffu) >> 3], x << 2, 4u) +
+                                   __builtin_amdgcn_ubfe(s_nib32[x >> 19], (x >> 14) & 0x1cu, 4u);
+                        }
+                } else if (kPacked12<CODEC> && full) {
+#pragma unroll
+                    for (int c = 0; c < P; c++)
+#pragma unroll
+                        for (int j = 0; j < CPC; j++)
+                            tot += s_len12[(w[c][j >> 1] >> (16 * (j & 1))) & 0xfffu];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < P; c++)
+#pragma unroll
+                        for (int j = 0; j < CPC; j++) {
+                            const int b = c * CPC + j;
+                            const uint32_t cj = (w[c][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                            uint32_t l;
+                            if constexpr (kPacked12<CODEC>)
+                                l = s_len12[cj & 0xfffu];
+                            else
+                                l = nib_length(s_nib, cj, p.n_sym);
+                            tot += ((valid >> b) & 1u) ? l : 0u;
+                        }
+                }
             }
             total += tot;
         }
@@ -1987,16 +2015,12 @@ __device__ void totals_tiles_wg(const SRC& src, unsigned long long* out) {
             const uint32_t valid = mhi & ~mlo;
             uint32_t tot = 0;
             if constexpr (CODEC == kFsst8) {
-                uint32_t F = 0;
+                uint32_t ffb[P * 4];              // 0x80 in each byte that is 255
 #pragma unroll
                 for (int c = 0; c < P; c++)
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const uint32_t x = w[c][q];
-                        const uint32_t m = ((x & 0x7f7f7f7fu) + 0x01010101u) & x & 0x80808080u;
-                        F |= (((m >> 7) * 0x00204081u) >> 21 & 0xfu) << (c * 16 + q * 4);
-                    }
-                F &= valid;
+                    for (int q = 0; q < 4; q++) ffb[c * 4 + q] = ff_bytes(w[c][q]);
+                uint32_t F = ff_mask32(ffb) & valid;   // bit j: code j is 255
                 if (tid == 0) F |= tile_entry_mask(g.a - q0, carry);   // the parity entering the tile
                 if (g.a > g.pos0) carry = 0;
                 const bool all_ff = (F == 0xffffffffu);
