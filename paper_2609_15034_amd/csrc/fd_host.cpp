@@ -53,7 +53,7 @@ int coarse_shift(int64_t n_codes, int64_t n_strings, int64_t tile_codes) {
 namespace {
 struct DevInfo {
     int cus = 0;
-    int occ[4][2][3] = {};  // [codec id 1..3][index64][mode]
+    int occ[5][2][3] = {};  // [codec id 1..4][index64][mode]
     int bocc[4][2][2] = {}; // batch kernels: [codec id 1..3][index64][expand]
 };
 std::mutex g_mu;
@@ -352,9 +352,15 @@ fd_status run_decode(const Args& a) {
                 return launch_scan_multi(p.tagg, pl.n_tiles + 1, (unsigned long long*)(ws + pl.off_scan), st);
             }) != hipSuccess)
             return hip_fail();
-        int g2 = grid_req ? grid_req : resident_grid(codec, a.index_bits, kModeExpand);
+        // 12-bit codes whose output capacity allows at most 3.5 bytes per code
+        // of the tiles (FSST-12's short tokens): the 16 KiB staging window holds
+        // a tile's output, and four workgroups fit a CU instead of three
+        const int ce = (codec == kOnpair12 && (double)a.out_cap <= 3.5 * (double)pl.n_tiles * (double)p.tile_codes)
+                           ? kOnpair12s
+                           : codec;
+        int g2 = grid_req ? grid_req : resident_grid(ce, a.index_bits, kModeExpand);
         if ((int64_t)g2 > pl.n_tiles) g2 = (int)pl.n_tiles;
-        if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(codec, a.index_bits, kModeExpand, p, g2, st); }) !=
+        if (timed(FD_PROF_DECODE, st, [&] { return launch_decode(ce, a.index_bits, kModeExpand, p, g2, st); }) !=
             hipSuccess)
             return hip_fail();
     }

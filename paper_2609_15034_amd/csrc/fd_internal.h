@@ -11,6 +11,10 @@ namespace fd {
 constexpr int kFsst8 = FD_FSST8;
 constexpr int kOnpair16 = FD_ONPAIR16;
 constexpr int kOnpair12 = FD_ONPAIR12;
+// (internal) the 12-bit expand pass with a 16 KiB staging window: for columns
+// whose tiles decode to at most about one such window (short tokens, as
+// FSST-12's), where the smaller window lets four workgroups share a CU
+constexpr int kOnpair12s = 4;
 
 constexpr int kWG = 256;            // threads per workgroup
 constexpr int kNWave = kWG / 64;    // waves per workgroup

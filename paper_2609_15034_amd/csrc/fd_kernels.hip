@@ -230,13 +230,16 @@ template <> struct Cfg<kOnpair12> {
     static constexpr int W = 16;
     static constexpr int WIN = kWinOnpair;
 };
-template <int CODEC> constexpr bool kPacked12 = CODEC == kOnpair12;
+template <> struct Cfg<kOnpair12s> : Cfg<kOnpair12> {
+    static constexpr int WIN = kWinFsst;
+};
+template <int CODEC> constexpr bool kPacked12 = CODEC == kOnpair12 || CODEC == kOnpair12s;
 // Code offsets each thread prefetches at a tile's start (the first block of
 // the tile's strings, read from the coarse index's sample on): enough for the
 // usual strings per tile (about 100 FSST-8 log lines, 500-800 short OnPair
 // strings) and the entries before the tile's first string.
 template <int CODEC> constexpr int kOffR = CODEC == kFsst8 ? 1 : 4;
-template <int CODEC> constexpr bool kIsOnpair = CODEC == kOnpair16 || CODEC == kOnpair12;
+template <int CODEC> constexpr bool kIsOnpair = CODEC == kOnpair16 || kPacked12<CODEC>;
 
 // bytes of a 12-bit packed stream of n codes
 __host__ __device__ __forceinline__ int64_t packed12_bytes(int64_t n) { return (n * 12 + 7) / 8; }
@@ -1202,7 +1205,7 @@ template <int CODEC, int MODE> constexpr bool kPrefetchCodes = !(CODEC == kFsst8
 // each, fits five), four with it; the OnPair kernels three (their 32 KiB
 // staging window leaves room in the LDS for three workgroups).
 template <int CODEC, int MODE>
-constexpr int kMinWaves = CODEC == kFsst8 ? (kPrefetchCodes<CODEC, MODE> ? 4 : 5) : 3;
+constexpr int kMinWaves = CODEC == kFsst8 ? (kPrefetchCodes<CODEC, MODE> ? 4 : 5) : CODEC == kOnpair12s ? 4 : 3;
 
 // Whether the look-back sums the previous block's tiles (measured: FSST-8
 // gains, OnPair-16, whose tiles publish later and wait mostly inside their
@@ -2442,7 +2445,8 @@ static int occupancy_of() {
     X(kOnpair16, int32_t, kModeTotals) X(kOnpair16, int64_t, kModeTotals) X(kFsst8, int32_t, kModeExpand)    \
     X(kFsst8, int64_t, kModeExpand) X(kOnpair16, int32_t, kModeExpand) X(kOnpair16, int64_t, kModeExpand)    \
     X(kOnpair12, int32_t, kModeLookback) X(kOnpair12, int64_t, kModeLookback) X(kOnpair12, int32_t, kModeTotals) \
-    X(kOnpair12, int64_t, kModeTotals) X(kOnpair12, int32_t, kModeExpand) X(kOnpair12, int64_t, kModeExpand)
+    X(kOnpair12, int64_t, kModeTotals) X(kOnpair12, int32_t, kModeExpand) X(kOnpair12, int64_t, kModeExpand) \
+    X(kOnpair12s, int32_t, kModeExpand) X(kOnpair12s, int64_t, kModeExpand)
 
 int decode_occupancy(int codec, int index_bits, int mode) {
 #define OCC(C, I, M) \

@@ -90,6 +90,28 @@ def test_tuning(cols, mode, tc, grid):
                     tuning={"mode": mode, "tile_codes": tc, "grid": grid, "reserved": 0})
 
 
+@pytest.mark.parametrize("tc", [0, 8, 56, 2000])
+@pytest.mark.parametrize("grid", [0, 3])
+def test_exact_capacity_three_phases(cols, tc, grid):
+    """Mode 1 with the output buffer exactly the decoded size: FSST-12's short
+    tokens (under 3.5 bytes per code) take the expand pass with the 16 KiB
+    staging window, OnPair-12's the 32 KiB one; one byte less is ECAPACITY."""
+    import oracle
+    tu = {"mode": 1, "tile_codes": tc, "grid": grid, "reserved": 0}
+    for name in ("fsst12", "onpair12"):
+        c = cols[name]
+        n = 4001
+        m = int(c.code_off[n])
+        packed = oracle.pack12(oracle.unpack12(c.codes, c.stats["n_codes"])[:m])
+        exact = len(oracle.decode("onpair12", packed, c.code_off[: n + 1], c.dict_bytes, c.dict_lens,
+                                  n_codes=m).out_bytes)
+        assert (exact <= 3.5 * m) == (name == "fsst12")
+        assert_parity12(packed, m, c.code_off[: n + 1], c.dict_bytes, c.dict_lens, tuning=tu, cap=exact)
+        exp = assert_parity12(packed, m, c.code_off[: n + 1], c.dict_bytes, c.dict_lens, tuning=tu,
+                              cap=exact - 1)
+        assert exp.status == 4
+
+
 @pytest.mark.parametrize("n_codes", [0, 1, 2, 3, 7, 8, 9, 4095, 4097])
 def test_code_counts(n_codes):
     """Every phase of the last partial group of 8 codes, against a random
