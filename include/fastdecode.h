@@ -176,7 +176,10 @@ int32_t fd_dict_size(const fd_dict *dict);
 /* Decode one column with a prepared dictionary (codec taken from the handle).
  * codes is uint8 (FSST-8), uint16 (OnPair-16) or the packed 12-bit byte
  * stream (OnPair-12, n_codes = codes in it); other arguments as
- * fsst_decode / onpair_decode. */
+ * fsst_decode / onpair_decode.  For 12-bit codes the three-phase decode takes
+ * an expand pass with a smaller staging window (faster for short tokens, as
+ * FSST-12's) when out_capacity is at most 3.5 bytes per code; a larger
+ * capacity gives the same result with the general 12-bit pass. */
 fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, const void *code_offsets, int index_bits,
                     int64_t n_strings, void *out_offsets, uint8_t *out_bytes, int64_t out_capacity, void *workspace,
                     size_t workspace_bytes, int32_t *status, unsigned flags, void *hip_stream);
