@@ -46,9 +46,14 @@ def test_onpair_urls_8mib(datagen_mod, via):
     assert np.array_equal(exp.out_bytes, c.text)
 
 
-def test_random_full_dictionary(datagen_mod):
+@pytest.mark.parametrize("tuning", [None, {"mode": 1, "tile_codes": 0, "grid": 0, "reserved": 0},
+                                    {"mode": 1, "tile_codes": 64, "grid": 5, "reserved": 0}])
+def test_random_full_dictionary(datagen_mod, tuning):
+    """All 65,536 tokens, lengths 1-16 uniform, codes uniform: in three phases
+    the totals take every length from the nibble table's dword reads."""
     c = datagen_mod.random_onpair(n_codes=1 << 20, n_strings=20_000)
-    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens)
+    assert len(c.dict_lens) == 65536 and set(np.unique(c.dict_lens)) == set(range(1, 17))
+    assert_parity("onpair16", c.codes, c.code_off, c.dict_bytes, c.dict_lens, tuning=tuning)
 
 
 # --------------------------------------------------------------------------- #
