@@ -198,8 +198,8 @@ fd_status fd_decode(const fd_dict *dict, const void *codes, int64_t n_codes, con
  *                        "sidecar regenerated at decode time" variant the
  *                        paper measures in its design overview).
  *                     With a NULL tuning: mode 1 when the column has at
- *                     least twice as many tiles as workgroups resident on
- *                     the device, else mode 0 (fewer launches).
+ *                     least four times as many tiles as workgroups resident
+ *                     on the device, else mode 0 (fewer launches).
  *   tile_codes        codes per tile.  Tiles are fixed ranges of code
  *                     positions (the paper's fixed-size batches of codes,
  *                     design overview): tile t holds the codes at positions

@@ -242,11 +242,13 @@ fd_status run_decode(const Args& a) {
     if (a.ws_bytes < (a.dict ? pl.off_dict : pl.bytes)) return FD_EINVAL;
     if (a.sidecar_op && a.sidecar_n != pl.n_tiles + 1) return FD_EINVAL;   // another tiling's sidecar
     // without a tuning: the three phases when the column's tiles fill the
-    // resident workgroups twice over (their expand pass takes tiles from the
-    // split queues), the single pass (fewer launches) below that
+    // resident workgroups four times over (their expand pass takes tiles from
+    // the split queues; measured crossover: FSST-8 between 32 and 64 MiB
+    // decoded, OnPair-16 between 64 and 128 MiB), the single pass (fewer
+    // launches, the codes read once) below that
     int mode = mode_sel;
     if (!a.tuning && !a.sidecar_op &&
-        pl.n_tiles >= 2 * (int64_t)resident_grid((int)a.codec, a.index_bits, kModeExpand))
+        pl.n_tiles >= kAutoTilesPerWorkgroup * (int64_t)resident_grid((int)a.codec, a.index_bits, kModeExpand))
         mode = 1;
 
     uint8_t* ws = (uint8_t*)a.ws;
@@ -631,12 +633,13 @@ fd_status fd_decode_take(const fd_dict* dict, const void* codes, int64_t n_codes
     if (timed(FD_PROF_COARSE, st, [&] { return launch_coarse_one(index_bits, p, st); }) != hipSuccess) return hip_fail();
     // the mode: as asked, else the three phases when the selection is expected
     // (at the column's mean codes per string) to fill the resident workgroups
-    // twice over with tiles, the single pass (fewer launches) below that
+    // four times over with tiles, the single pass (fewer launches) below that
     int mode = tuning ? tuning->mode : -1;
     if (mode < 0) {
         const double mean = n_strings ? (double)n_codes / (double)n_strings : 1.0;
         const double tiles = mean * (double)n_rows / (double)tp.dec.T;
-        mode = tiles >= 2.0 * (double)resident_grid(codec2, index_bits, kModeExpand) ? 1 : 0;
+        mode = tiles >= (double)kAutoTilesPerWorkgroup * (double)resident_grid(codec2, index_bits, kModeExpand) ? 1
+                                                                                                            : 0;
     }
     if (mode == 1) {
         if (timed(FD_PROF_TOTALS, st, [&] { return launch_tile_totals(codec2, index_bits, p, dev_cus(), st); }) !=

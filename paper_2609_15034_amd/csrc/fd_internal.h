@@ -38,6 +38,9 @@ constexpr int kBlk = 1 << kBlkShift;
 // decode modes
 constexpr int kModeLookback = 0;    // single pass, decoupled look-back for tile cursors
 constexpr int kModeTotals = 1;      // three-phase: tile totals only
+// without a tuning, the three phases from this many tiles per resident
+// expand-pass workgroup on (the single pass below)
+constexpr int kAutoTilesPerWorkgroup = 4;
 constexpr int kModeExpand = 2;      // three-phase / sidecar: expand with stored tile cursors (checked)
 // Tile queues.  Workgroups take tiles from counters in device memory.  One
 // counter takes about 12 ns per device-scope atomic on the same address, a

@@ -458,12 +458,17 @@ def test_onpair_multi_window_tiles(mode):
 
 def test_automatic_mode_both_sides(datagen_mod):
     """Without a tuning the decode picks the three phases for a column with at
-    least twice as many tiles as resident workgroups (a 32 MiB log column has
-    about 2,600 tiles of 8,176 codes) and the single pass for a small one; both
-    match the oracle."""
-    big = datagen_mod.fsst_logs(seed=41, target_bytes=32 << 20)
-    assert len(big.codes) // 8176 >= 2 * 1024
-    exp = assert_parity("fsst8", big.codes, big.code_off, big.dict_bytes, big.dict_lens)
-    assert np.array_equal(exp.out_bytes, big.text)
+    least four times as many tiles as resident workgroups (a 96 MiB log column
+    has about 7,000 tiles of 8,176 codes, against 4 x 5 x 256) and the single
+    pass for a small one (the profiler sees a totals launch only in the
+    former); both match the oracle."""
+    import paper_2609_15034_amd as fd
+    big = datagen_mod.fsst_logs(seed=41, target_bytes=96 << 20)
+    assert len(big.codes) // 8176 >= 4 * 5 * 256
     small = datagen_mod.fsst_small(seed=42)
-    assert_parity("fsst8", small.codes, small.code_off, small.dict_bytes, small.dict_lens)
+    for c, three in ((big, True), (small, False)):
+        fd.profile_begin(("totals", "decode"), 64)
+        exp = assert_parity("fsst8", c.codes, c.code_off, c.dict_bytes, c.dict_lens)
+        pr = fd.profile_end()
+        assert ("totals" in pr) == three, pr
+        assert np.array_equal(exp.out_bytes, c.text)

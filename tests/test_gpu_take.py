@@ -190,9 +190,13 @@ def test_take_errors_in_strings(datagen_mod):
 
 
 def test_take_automatic_mode_large_selection(datagen_mod):
-    """Without a tuning a selection expected to span at least twice as many
-    tiles as resident workgroups runs the three phases: every row of a 32 MiB
-    log column, in order and reversed."""
-    c = datagen_mod.fsst_logs(seed=43, target_bytes=32 << 20)
+    """Without a tuning a selection expected to span at least four times as
+    many tiles as resident workgroups runs the three phases (the profiler sees
+    its totals launch): every row of a 96 MiB log column, in order and
+    reversed."""
+    import paper_2609_15034_amd as fd
+    c = datagen_mod.fsst_logs(seed=43, target_bytes=96 << 20)
     for rows in (np.arange(c.n_strings), np.arange(c.n_strings)[::-1].copy()):
+        fd.profile_begin(("totals", "decode"), 64)
         assert assert_take(c, rows).status == 0
+        assert "totals" in fd.profile_end()
