@@ -215,11 +215,13 @@ def single_rate(workload: str, steps: int = 10, seed: int | None = None, mode: i
     return col.decoded_bytes / mean_s / 1e9
 
 
-def small_latency(runs: int = 200, mode: int = 1, seed: int | None = None) -> dict:
+def small_latency(runs: int = 200, mode: int | None = None, seed: int | None = None) -> dict:
     """The small FSST-8 column (10,000 printable strings, int32 offsets): the
     latency of one whole decode call, timed with events around each call on
     the library's stream, over `runs` calls after a warm-up; the output is
-    checked against the source strings."""
+    checked against the source strings.  mode None: the library's automatic
+    choice (the single pass at this size), as a caller without a tuning
+    gets it."""
     import numpy as np
     import torch
     import paper_2609_15034_amd as fd
@@ -229,7 +231,7 @@ def small_latency(runs: int = 200, mode: int = 1, seed: int | None = None) -> di
     d = fd.Dict(col.codec, torch.from_numpy(col.dict_bytes).to(dev), torch.from_numpy(col.dict_lens).to(dev))
     out = torch.empty(col.decoded_bytes, dtype=torch.uint8, device=dev)
     out_off = torch.empty(col.n_strings + 1, dtype=code_off.dtype, device=dev)
-    tu = {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
+    tu = None if mode is None else {"mode": mode, "tile_codes": 0, "grid": 0, "reserved": 0}
     ws = fd.alloc_workspace(col.codec, fd.codes_in(col.codec, codes), col.n_strings, tu)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     _, per = _events_time(lambda: fd.decode_into(d, codes, code_off, out_off, out, ws, status=st, async_=True,
@@ -237,7 +239,8 @@ def small_latency(runs: int = 200, mode: int = 1, seed: int | None = None) -> di
     ok = int(st.item()) == fd.OK and torch.equal(out, torch.from_numpy(col.text).to(dev)) and \
         torch.equal(out_off.to(torch.int64), torch.from_numpy(col.text_off.astype(np.int64)).to(dev))
     us = per * 1e6
-    return {"decoded_bytes": col.decoded_bytes, "n_strings": col.n_strings, "runs": runs, "mode": mode,
+    return {"decoded_bytes": col.decoded_bytes, "n_strings": col.n_strings, "runs": runs,
+            "mode": "automatic" if mode is None else mode,
             "latency_us": {"min": round(float(us.min()), 2), "p50": round(float(np.median(us)), 2),
                            "p99": round(float(np.percentile(us, 99)), 2)},
             "GBps_at_p50": round(col.decoded_bytes / float(np.median(per)) / 1e9, 3), "bit_exact": bool(ok)}
@@ -773,7 +776,8 @@ def main():
         except Exception as e:
             res["fsst_logs_GBps"] = {"error": f"{type(e).__name__}: {e}"}
         try:
-            res["fsst_small"] = small_latency(mode=args.mode)
+            res["fsst_small"] = small_latency()
+            res["fsst_small"]["three_phases_latency_us"] = small_latency(mode=1)["latency_us"]
         except Exception as e:
             res["fsst_small"] = {"error": f"{type(e).__name__}: {e}"}
         try:
